@@ -1,0 +1,202 @@
+"""FP64 CPU oracle of the mass-spring step (Python front end).
+
+TEST INFRASTRUCTURE ONLY: used by ``tests/``, the package smoke check and the
+benchmark's CPU-baseline leg; never by the GPU library or its binding.
+
+The arithmetic lives in ``titan_oracle.c`` (plain C, double precision,
+serial scatter over springs); this module compiles it with gcc on first use,
+promotes the FP32 scene arrays to FP64 and adds the observables (energies,
+momenta, centre of mass) as plain numpy sums.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "titan_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_lp = ctypes.POINTER(ctypes.c_int64)
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("dt", ctypes.c_double),
+        ("g", ctypes.c_double * 3),
+        ("ground", ctypes.c_int32),
+        ("ground_k", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("omega", ctypes.c_double),
+    ]
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle into ``oracle/liboracle.so`` (plain -O2, no FMA
+    contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        lib.orc_rest_lengths.argtypes = [ctypes.c_int64, _lp, _dp, _dp]
+        lib.orc_spring_forces.argtypes = [ctypes.c_int64, ctypes.c_int64, _lp, _dp, _dp, _dp, _dp, _dp,
+                                          ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
+        lib.orc_integrate.argtypes = [ctypes.c_int64, _dp, ctypes.POINTER(_Params), _dp, _dp, _dp]
+        lib.orc_run.argtypes = [ctypes.c_int64, _dp, ctypes.c_int64, _lp, _dp, _dp, _dp, _dp, _dp,
+                                ctypes.POINTER(_Params), ctypes.c_int64, ctypes.c_int64, _dp, _dp, _dp]
+        lib.orc_run.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _d(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a, t=_dp):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+@dataclass
+class Params:
+    dt: float = 1.0e-4
+    gravity: tuple = (0.0, 0.0, -9.81)
+    ground: bool = True
+    ground_k: float = 1.0e5
+    mu: float = 0.5
+    omega: float = 0.0
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "Params":
+        return cls(dt=d["dt"], gravity=tuple(d["gravity"]), ground=bool(d["ground"]),
+                   ground_k=d["ground_k"], mu=d["mu"], omega=d["omega"])
+
+    def _c(self) -> _Params:
+        p = _Params()
+        p.dt = self.dt
+        p.g[:] = list(self.gravity)
+        p.ground = 1 if self.ground else 0
+        p.ground_k = self.ground_k
+        p.mu = self.mu
+        p.omega = self.omega
+        return p
+
+
+class System:
+    """A scene promoted to FP64.  ``rest`` defaults to the initial lengths,
+    computed in FP64 from the (FP32) initial positions."""
+
+    def __init__(self, scene: dict, rest=None):
+        self.x0 = _d(scene["pos"]).reshape(-1, 3).copy()
+        self.v0 = _d(scene["vel"]).reshape(-1, 3).copy() if scene.get("vel") is not None \
+            else np.zeros_like(self.x0)
+        self.n = self.x0.shape[0]
+        self.mass = _d(scene["mass"])
+        self.ends = np.ascontiguousarray(scene["ends"], dtype=np.int64).reshape(-1, 2)
+        self.ns = self.ends.shape[0]
+        self.k = _d(scene["k"])
+        self.c = _d(scene.get("damping"))
+        self.amp = _d(scene.get("amp"))
+        self.phase = _d(scene.get("phase"))
+        if (self.amp is None) != (self.phase is None):
+            raise ValueError("amp and phase go together")
+        if rest is None:
+            rest = np.empty(self.ns, np.float64)
+            _load().orc_rest_lengths(self.ns, _ptr(self.ends, _lp), _ptr(self.x0), _ptr(rest))
+        self.rest = _d(rest)
+
+    def spring_forces(self, x, v, t, omega):
+        x = _d(x).reshape(-1, 3)
+        v = _d(v).reshape(-1, 3)
+        f = np.empty((self.n, 3), np.float64)
+        _load().orc_spring_forces(self.n, self.ns, _ptr(self.ends, _lp), _ptr(self.k), _ptr(self.c),
+                                  _ptr(self.rest), _ptr(self.amp), _ptr(self.phase), omega, t,
+                                  _ptr(x), _ptr(v), _ptr(f))
+        return f
+
+    def run(self, params: Params, x, v, step0: int, nsteps: int, want_forces: bool = False):
+        """Advance copies of (x, v) by ``nsteps`` steps from step index
+        ``step0``.  Returns (x, v, f) with f the spring forces of the last
+        step's starting state (or None)."""
+        x = _d(x).reshape(-1, 3).copy()
+        v = _d(v).reshape(-1, 3).copy()
+        f = np.empty((self.n, 3), np.float64) if want_forces else None
+        p = params._c()
+        rc = _load().orc_run(self.n, _ptr(self.mass), self.ns, _ptr(self.ends, _lp), _ptr(self.k),
+                             _ptr(self.c), _ptr(self.rest), _ptr(self.amp), _ptr(self.phase),
+                             ctypes.byref(p), step0, nsteps, _ptr(x), _ptr(v), _ptr(f))
+        if rc != 0:
+            raise MemoryError("oracle run failed")
+        return x, v, f
+
+    def trajectory(self, params: Params, nsteps: int, x=None, v=None, step0: int = 0):
+        """Per-step series for n = 1..nsteps: displacement X(n) - X(0),
+        velocity V(n) and spring force F of step n's starting state (F(n-1)).
+        Returns three arrays of shape (nsteps, n, 3)."""
+        x = self.x0 if x is None else _d(x).reshape(-1, 3)
+        v = self.v0 if v is None else _d(v).reshape(-1, 3)
+        xs0 = x.copy()
+        dX = np.empty((nsteps, self.n, 3))
+        V = np.empty((nsteps, self.n, 3))
+        F = np.empty((nsteps, self.n, 3))
+        for s in range(nsteps):
+            x, v, f = self.run(params, x, v, step0 + s, 1, want_forces=True)
+            dX[s] = x - xs0
+            V[s] = v
+            F[s] = f
+        return dX, V, F
+
+    # ---- observables (plain sums) -------------------------------------------------
+
+    def spring_stretch(self, x, t=0.0, omega=0.0):
+        x = _d(x).reshape(-1, 3)
+        d = x[self.ends[:, 1]] - x[self.ends[:, 0]]
+        L = self.rest.copy()
+        if self.amp is not None:
+            L = L * (1.0 + self.amp * np.sin(omega * t + self.phase))
+        return np.linalg.norm(d, axis=1) - L
+
+    def kinetic(self, v):
+        v = _d(v).reshape(-1, 3)
+        return 0.5 * float(np.sum(self.mass[:, None] * v * v))
+
+    def spring_energy(self, x, t=0.0, omega=0.0):
+        e = self.spring_stretch(x, t, omega)
+        return 0.5 * float(np.sum(self.k * e * e))
+
+    def gravity_energy(self, x, g):
+        x = _d(x).reshape(-1, 3)
+        return -float(np.sum(self.mass[:, None] * x * np.asarray(g)[None, :]))
+
+    def ground_energy(self, x, ground_k):
+        z = _d(x).reshape(-1, 3)[:, 2]
+        return 0.5 * ground_k * float(np.sum(np.where(z < 0.0, z * z, 0.0)))
+
+    def momentum(self, v):
+        return np.sum(self.mass[:, None] * _d(v).reshape(-1, 3), axis=0)
+
+    def angular_momentum(self, x, v):
+        x = _d(x).reshape(-1, 3)
+        v = _d(v).reshape(-1, 3)
+        return np.sum(np.cross(x, self.mass[:, None] * v), axis=0)
+
+    def com(self, x):
+        x = _d(x).reshape(-1, 3)
+        return np.sum(self.mass[:, None] * x, axis=0) / np.sum(self.mass)
