@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the mass-spring step on one MI355X.
+
+Workload: the large actuated lattice -- 100^3 masses (1,000,000), the
+26-neighbourhood springs (12,731,796), positions jittered by +-2% of the
+0.1 m spacing, k ~ U(5e3, 2e4) N/m, every rest length actuated as
+L0 (1 + 0.1 sin(2 pi 2 t + phi)), phi ~ U(0, 2 pi), damping 1 N s/m, ground
+contact on (k_g = 1e5 N/m, mu = 0.5), dt = 5e-5 s.  Inputs are seeded and
+synthetic and are resident in GPU memory before the timed region.
+
+One "step" is one simulation step of the whole system.  The metric is spring
+updates per second (springs x steps / wall time), the unit the paper uses for
+its lattice benchmark (Sec. IV-A).
+
+Prints ONE JSON line.  ``roofline`` reports the step kernel against the HBM
+bandwidth peak using the algorithmic byte count per step; ``cpu_baseline``
+times the FP64 CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "gather_step_lattice100.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1911_10274_amd", "csrc", "gather_step.hip")]
+
+
+def algorithmic_bytes(n_masses: int, n_springs: int) -> int:
+    """Bytes one step must move under the minimal model: per spring its two
+    int32 end indices and four FP32 constants (k, rest, actuation phasor C, S)
+    = 24 B; per mass the state read (u, v, x0: 3 x 16 B), the state written
+    (u, v: 2 x 16 B) and one int32 of incidence bookkeeping = 84 B."""
+    return 24 * n_springs + 84 * n_masses
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if there is none or the kernel source changed since it was taken."""
+    if not os.path.exists(PROFILE_SUMMARY):
+        return None
+    txt = open(PROFILE_SUMMARY).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    hsh = re.search(r"kernel_source_sha:\s*([0-9a-f]+)", txt)
+    if not m or not hsh or hsh.group(1) != kernel_source_hash():
+        return None
+    return float(m.group(1))
+
+
+def build_workload(n: int, seed: int):
+    from paper_1911_10274_amd import scenes
+
+    return scenes.jittered_actuated_lattice(n=n, seed=seed)
+
+
+PARAMS = dict(dt=5e-5, gravity=(0.0, 0.0, -9.81), ground=True, ground_k=1e5, mu=0.5, omega=2 * math.pi * 2)
+
+
+def cpu_baseline(scene, steps: int):
+    """The FP64 oracle, as it stands, on the first ``steps`` steps of the same
+    workload (single thread)."""
+    from oracle import oracle as O
+
+    op = O.Params(dt=PARAMS["dt"], gravity=PARAMS["gravity"], ground=PARAMS["ground"],
+                  ground_k=PARAMS["ground_k"], mu=PARAMS["mu"], omega=PARAMS["omega"])
+    sysm = O.System(scene)
+    t0 = time.perf_counter()
+    sysm.run(op, sysm.x0, sysm.v0, 0, steps)
+    sec = time.perf_counter() - t0
+    ns = scene["ends"].shape[0]
+    return {
+        "value": ns * steps / sec,
+        "unit": "spring updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"first {steps} steps of the same {scene['pos'].shape[0]}-mass / {ns}-spring lattice, "
+                  f"serial FP64 C oracle, {sec:.2f} s",
+    }
+
+
+def copy_calibration(mib: int = 1024, reps: int = 5):
+    """A plain device copy of known size, for scaling rocprofv3 FETCH_SIZE /
+    WRITE_SIZE counters (run under rocprofv3 --pmc)."""
+    import torch
+
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--n", type=int, default=100, help="lattice side (masses per edge)")
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the stepper has no multi-GPU path "
+              "(one lattice per GPU; see the sharding design notes)", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        copy_calibration()
+        return
+
+    import torch
+
+    from paper_1911_10274_amd import titan as T
+
+    torch.cuda.set_device(0)
+    scene = build_workload(args.n, args.seed)
+    nm, ns = scene["pos"].shape[0], scene["ends"].shape[0]
+    tp = T.Params(dt=PARAMS["dt"], gravity=PARAMS["gravity"], ground=PARAMS["ground"], ground_k=PARAMS["ground_k"],
+                  friction_mu=PARAMS["mu"], omega=PARAMS["omega"], engine=T.ENGINE_GATHER)
+    sim = T.sim_from_scene(scene, tp)
+    sim.finalize()
+    stream = torch.cuda.current_stream()
+
+    sim.step(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    sim.step(args.steps)
+    end.record(stream)
+    end.synchronize()
+    torch.cuda.synchronize()
+    sim.sync()  # raises on a non-finite state
+    ms = start.elapsed_time(end)
+    ms_per_step = ms / args.steps
+    value = ns * args.steps / (ms / 1e3)
+
+    abytes = algorithmic_bytes(nm, ns)
+    achieved = abytes / (ms_per_step / 1e3) / 1e9
+    traffic = measured_traffic()
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+    }
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene, args.cpu_steps)
+
+    out = {
+        "metric": "spring updates/s",
+        "value": value,
+        "unit": "spring updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"actuated jittered lattice {args.n}^3 (plain fused gather step)",
+            "masses": nm,
+            "springs": ns,
+            "dt": PARAMS["dt"],
+            "seed": args.seed,
+            "engine": "gather",
+            "algorithmic_bytes_per_step": abytes,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    sim.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * titan.h -- C ABI of the MI355X mass-spring stepper.
+ *
+ * The library simulates a spring-mass system the way the Titan paper
+ * (arXiv:1911.10274) describes it: every step applies Hooke's-law spring
+ * forces to the masses (Sec. III-B, Eq. 1) and then integrates every mass
+ * (Sec. III-B, Eq. 1's update dx = xdot*dt + xddot*dt^2, i.e. semi-implicit
+ * Euler) under gravity and a penalty ground plane with friction (Sec. I and
+ * Sec. III-A name plane constraints and friction).  Springs may be actuated by
+ * scaling their rest length with 1 + amp*sin(omega*t + phase) (Sec. IV-B,
+ * Eq. 4).  The host-side model of the paper's asynchronous CPU/GPU design
+ * (Sec. III-D: a simulation that runs on its own until a breakpoint, a CPU
+ * that blocks only when it asks to, edits pushed while the simulation is
+ * paused) is kept as stream-ordered work plus breakpoints.
+ *
+ * Conventions for every call:
+ *   - Arrays are plain host pointers unless a name ends in _dev (device
+ *     pointer on the simulation's device).  Vectors are packed xyz triples
+ *     ("n3" = n*3 floats, row-major).  Caller arrays are read or written
+ *     during the call only; the library keeps no pointer to them.
+ *   - Masses and springs are numbered in the order they were added, from 0.
+ *     The library may store them internally in another order; every call
+ *     that reads or writes per-mass data uses the caller's numbering.
+ *   - Every call returns a status (TITAN_OK = 0 or a negative TITAN_E*);
+ *     titan_last_error() then describes the failure of the last failing call
+ *     on the calling thread.  No C++ exception crosses this interface.
+ *   - A titan_sim is guarded by its own mutex: calls on one sim from several
+ *     threads are serialised.  Calls on different sims are independent.
+ */
+#ifndef TITAN_H
+#define TITAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TITAN_ABI_VERSION 1
+
+/* Status codes. */
+#define TITAN_OK 0
+#define TITAN_EINVAL (-1)     /* bad argument: index out of range, i == j,
+                                 zero-length spring, non-finite or negative
+                                 input, size mismatch */
+#define TITAN_ENOMEM (-2)     /* host or device allocation failed */
+#define TITAN_EDEVICE (-3)    /* HIP error or no usable GPU; sticky: the sim
+                                 refuses further stepping */
+#define TITAN_ESTATE (-4)     /* call not valid in the sim's current phase
+                                 (e.g. adding springs after the first step) */
+#define TITAN_ENONFINITE (-5) /* the simulation produced a NaN or infinity;
+                                 sticky, reported by titan_sync/titan_wait/
+                                 titan_get_state; see titan_get_info */
+
+/* Flags of titan_get_state / titan_set_state. */
+#define TITAN_STATE_DISPLACEMENT 1 /* pos is x - x0 (x0 = initial position)
+                                      instead of absolute x */
+
+/* Breakpoint kinds (titan_set_breakpoint). */
+#define TITAN_BP_SNAPSHOT 0 /* keep stepping; the state at the breakpoint
+                               step is copied aside for titan_get_snapshot */
+#define TITAN_BP_PAUSE 1    /* stop enqueuing steps at the breakpoint until
+                               titan_resume (Sec. III-D's halted simulation);
+                               also takes a snapshot */
+
+/* Kernel selection (titan_params.engine). */
+#define TITAN_ENGINE_AUTO 0    /* library chooses (autotuned) */
+#define TITAN_ENGINE_GATHER 1  /* per-mass gather, one launch per step */
+#define TITAN_ENGINE_BATCHED 2 /* one workgroup per independent body with its
+                                  state resident in LDS, many steps per
+                                  launch; needs body ids (titan_add_masses) */
+
+typedef struct titan_sim titan_sim;
+
+/* Simulation parameters (SI units).  Taken by value at each call that
+ * passes them. */
+typedef struct titan_params {
+    double dt;          /* time step, s (> 0) */
+    double gravity[3];  /* m/s^2, e.g. {0, 0, -9.81} */
+    int32_t ground;     /* nonzero: ground plane z = 0.  A mass with z < 0
+                           feels -ground_k*z upward and Coulomb friction */
+    int32_t engine;     /* TITAN_ENGINE_* */
+    double ground_k;    /* ground penalty stiffness, N/m (>= 0) */
+    double friction_mu; /* Coulomb friction coefficient (>= 0) */
+    double omega;       /* actuation angular frequency, rad/s */
+} titan_params;
+
+/* Optional device-memory provider.  alloc returns a device pointer aligned
+ * to at least 256 bytes or NULL; release frees it.  Both are called with the
+ * sim's mutex held, from the thread making the titan_* call.  With a NULL
+ * allocator the library uses hipMalloc/hipFree. */
+typedef struct titan_allocator {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*release)(void *ptr, void *ctx);
+    void *ctx;
+} titan_allocator;
+
+/* Read-only facts about a sim (titan_get_info). */
+typedef struct titan_info {
+    int64_t n_masses;
+    int64_t n_springs;
+    int64_t n_bodies;        /* distinct body ids (1 if none were given) */
+    int64_t step;            /* steps enqueued so far (the current step index) */
+    int64_t steps_requested; /* steps asked for by titan_step so far */
+    int64_t first_bad_step;  /* first step that produced a non-finite value, or -1 */
+    int32_t finalized;       /* nonzero after the first titan_step */
+    int32_t engine;          /* engine in use (TITAN_ENGINE_GATHER/BATCHED) */
+    int32_t device;          /* HIP device ordinal */
+    int32_t paused;          /* nonzero while held at a pause breakpoint */
+    int64_t device_bytes;    /* device memory held by the sim */
+} titan_info;
+
+/* ABI version this library implements (TITAN_ABI_VERSION). */
+int titan_abi_version(void);
+
+/* Message of the last failing call on the calling thread ("" if none).  The
+ * pointer stays valid until the next titan_* call on this thread. */
+const char *titan_last_error(void);
+
+/* Create an empty sim.  p: parameters (copied).  stream: a hipStream_t to
+ * run on, or NULL for the device's null stream; the caller keeps it alive
+ * until titan_destroy.  alloc: NULL or a device allocator (copied).  No device
+ * work happens before the first titan_step.  *out receives the sim. */
+int titan_create(const titan_params *p, void *stream, const titan_allocator *alloc, titan_sim **out);
+
+/* Wait for the sim's queued work, free all its memory and the sim itself.
+ * NULL is accepted. */
+int titan_destroy(titan_sim *sim);
+
+/* Append n masses (Sec. III-C: masses are the primitive objects springs act
+ * on).  pos_n3: initial positions (m).  vel_n3: initial velocities (m/s) or
+ * NULL for zero.  mass_n: kg, >= 0; 0 marks a pinned mass that never moves.
+ * body_n: NULL, or the independent body each mass belongs to (>= 0); springs
+ * may not join masses of different bodies.  *first_out (may be NULL) gets the
+ * index of the first new mass.  Only before the first titan_step. */
+int titan_add_masses(titan_sim *sim, int64_t n, const float *pos_n3, const float *vel_n3,
+                     const float *mass_n, const int32_t *body_n, int64_t *first_out);
+
+/* Append n springs (Sec. III-B).  ends_n2: mass index pairs (i, j), i != j,
+ * both already added; the spring's initial length must be > 0.  k_n:
+ * stiffness N/m (>= 0).  damping_n: axial damping N*s/m (>= 0) or NULL for 0.
+ * rest_n: rest lengths (> 0) or NULL for the initial lengths.  amp_n,
+ * phase_n: actuation (both or neither; Sec. IV-B Eq. 4): the rest length at
+ * time t is rest * (1 + amp*sin(omega*t + phase)).  Only before the first
+ * titan_step.  *first_out (may be NULL) gets the first new spring's index. */
+int titan_add_springs(titan_sim *sim, int64_t n, const int64_t *ends_n2, const float *k_n,
+                      const float *damping_n, const float *rest_n, const float *amp_n,
+                      const float *phase_n, int64_t *first_out);
+
+/* Replace the parameters.  Takes effect for steps enqueued after this call
+ * (while paused at a breakpoint: from the breakpoint on).  The engine field
+ * may change only before the first step. */
+int titan_set_params(titan_sim *sim, const titan_params *p);
+
+/* Build the device representation now (otherwise done by the first
+ * titan_step): validation, internal ordering, incidence lists, upload and
+ * engine selection. */
+int titan_finalize(titan_sim *sim);
+
+/* Ask for n more steps (n >= 0).  Asynchronous: work is enqueued on the
+ * sim's stream and the call returns; step n of the run uses t = n*dt.  Steps
+ * beyond a pause breakpoint are held until titan_resume. */
+int titan_step(titan_sim *sim, int64_t n);
+
+/* Breakpoint at absolute step index `step` (the state after `step` steps),
+ * which must not be behind the steps already enqueued.  kind: TITAN_BP_*.
+ * *bp_out receives a handle for titan_wait / titan_get_snapshot. */
+int titan_set_breakpoint(titan_sim *sim, int64_t step, int32_t kind, uint64_t *bp_out);
+
+/* Block until breakpoint bp has been reached on the GPU (Sec. III-D's
+ * waitForEvent).  Returns TITAN_ESTATE if bp will never be reached with the
+ * steps requested so far. */
+int titan_wait(titan_sim *sim, uint64_t bp);
+
+/* Release a pause breakpoint and enqueue the held steps. */
+int titan_resume(titan_sim *sim);
+
+/* Block until all enqueued work is done; reports non-finite state. */
+int titan_sync(titan_sim *sim);
+
+/* Copy the state of masses [first, first+count) after all enqueued steps
+ * (blocks until they are done).  pos_n3 / vel_n3 may be NULL.  flags:
+ * TITAN_STATE_DISPLACEMENT.  *step_out (may be NULL) gets the step index. */
+int titan_get_state(titan_sim *sim, int64_t first, int64_t count, float *pos_n3, float *vel_n3,
+                    int32_t flags, int64_t *step_out);
+
+/* Copy the state saved at breakpoint bp (blocks until it is reached), while
+ * later steps may still be running. */
+int titan_get_snapshot(titan_sim *sim, uint64_t bp, int64_t first, int64_t count, float *pos_n3,
+                       float *vel_n3, int32_t flags, int64_t *step_out);
+
+/* Overwrite the state of masses [first, first+count), in stream order: it
+ * applies after the steps enqueued so far (at the breakpoint if paused).
+ * pos_n3 / vel_n3 may be NULL to keep that part.  With
+ * TITAN_STATE_DISPLACEMENT pos is x - x0. */
+int titan_set_state(titan_sim *sim, int64_t first, int64_t count, const float *pos_n3,
+                    const float *vel_n3, int32_t flags);
+
+/* Set the step index of the next step to `step` (>= 0); the time of step n
+ * is n*dt.  Together with titan_set_state this restores a checkpoint taken
+ * with titan_get_state (Sec. III-D: state pushed while the simulation is
+ * stopped).  Only when no steps are held at a pause breakpoint. */
+int titan_set_step(titan_sim *sim, int64_t step);
+
+/* Summed spring force on masses [first, first+count) at the current state
+ * and the current step's time (blocks).  f_n3 receives N. */
+int titan_get_forces(titan_sim *sim, int64_t first, int64_t count, float *f_n3);
+
+/* Fill *info. */
+int titan_get_info(titan_sim *sim, titan_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TITAN_H */

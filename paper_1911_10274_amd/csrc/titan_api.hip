@@ -1,0 +1,729 @@
+// Host runtime behind the C ABI (include/titan.h): staging and validation of
+// masses and springs, construction of the device representation, the
+// stream-ordered step queue with breakpoints (the paper's asynchronous
+// CPU/GPU model, Sec. III-D), state I/O and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "titan.h"
+#include "titan_internal.h"
+#include "titan_sim.h"
+
+using namespace titan;
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_last_error;
+
+int titan::fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int titan::hip_fail(titan_sim *sim, hipError_t e, const char *what)
+{
+    if (sim)
+        sim->dev_error = true;
+    return fail(TITAN_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(sim, expr)                                  \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess)                               \
+            return titan::hip_fail((sim), e_, #expr);       \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------------
+
+int titan::dev_alloc(titan_sim *s, size_t bytes, void **out)
+{
+    *out = nullptr;
+    if (bytes == 0)
+        bytes = 256;
+    void *p = nullptr;
+    if (s->alloc.alloc) {
+        p = s->alloc.alloc(bytes, s->alloc.ctx);
+        if (!p)
+            return fail(TITAN_ENOMEM, "device allocator returned NULL for %zu bytes", bytes);
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(e == hipErrorOutOfMemory ? TITAN_ENOMEM : TITAN_EDEVICE,
+                        "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        }
+    }
+    s->allocations.push_back(p);
+    s->device_bytes += (int64_t)bytes;
+    *out = p;
+    return TITAN_OK;
+}
+
+static void dev_free_all(titan_sim *s)
+{
+    for (void *p : s->allocations) {
+        if (s->alloc.release)
+            s->alloc.release(p, s->alloc.ctx);
+        else
+            (void)hipFree(p);
+    }
+    s->allocations.clear();
+    s->device_bytes = 0;
+}
+
+template <class T>
+static int upload(titan_sim *s, const std::vector<T> &h, T **d)
+{
+    int rc = dev_alloc(s, h.size() * sizeof(T), (void **)d);
+    if (rc)
+        return rc;
+    if (!h.empty())
+        HIP_TRY(s, hipMemcpyAsync(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s->stream));
+    return TITAN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// validation helpers
+// ---------------------------------------------------------------------------
+
+static bool finite3(const float *p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
+
+static int check_params(const titan_params *p)
+{
+    if (!p)
+        return fail(TITAN_EINVAL, "params is NULL");
+    if (!(std::isfinite(p->dt) && p->dt > 0))
+        return fail(TITAN_EINVAL, "dt must be finite and > 0 (got %g)", p->dt);
+    for (int q = 0; q < 3; ++q)
+        if (!std::isfinite(p->gravity[q]))
+            return fail(TITAN_EINVAL, "gravity must be finite");
+    if (!(std::isfinite(p->ground_k) && p->ground_k >= 0))
+        return fail(TITAN_EINVAL, "ground_k must be finite and >= 0");
+    if (!(std::isfinite(p->friction_mu) && p->friction_mu >= 0))
+        return fail(TITAN_EINVAL, "friction_mu must be finite and >= 0");
+    if (!std::isfinite(p->omega))
+        return fail(TITAN_EINVAL, "omega must be finite");
+    if (p->engine < TITAN_ENGINE_AUTO || p->engine > TITAN_ENGINE_BATCHED)
+        return fail(TITAN_EINVAL, "unknown engine %d", p->engine);
+    return TITAN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ABI: lifetime
+// ---------------------------------------------------------------------------
+
+extern "C" int titan_abi_version(void) { return TITAN_ABI_VERSION; }
+
+extern "C" const char *titan_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int titan_create(const titan_params *p, void *stream, const titan_allocator *alloc, titan_sim **out)
+{
+    if (!out)
+        return fail(TITAN_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (int rc = check_params(p))
+        return rc;
+    if (alloc && (!alloc->alloc || !alloc->release))
+        return fail(TITAN_EINVAL, "allocator needs both alloc and release");
+    titan_sim *s = new (std::nothrow) titan_sim();
+    if (!s)
+        return fail(TITAN_ENOMEM, "out of host memory");
+    s->params = *p;
+    s->stream = (hipStream_t)stream;
+    if (alloc)
+        s->alloc = *alloc;
+    *out = s;
+    return TITAN_OK;
+}
+
+extern "C" int titan_destroy(titan_sim *s)
+{
+    if (!s)
+        return TITAN_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->finalized) {
+            (void)hipSetDevice(s->device);
+            (void)hipStreamSynchronize(s->stream);
+            if (s->side_stream)
+                (void)hipStreamSynchronize(s->side_stream);
+            for (auto &kv : s->bps)
+                if (kv.second.ev)
+                    (void)hipEventDestroy(kv.second.ev);
+            if (s->side_stream)
+                (void)hipStreamDestroy(s->side_stream);
+            if (s->host_stage)
+                (void)hipHostFree(s->host_stage);
+            destroy_engines(s);
+            dev_free_all(s);
+        }
+    }
+    delete s;
+    return TITAN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ABI: building the system
+// ---------------------------------------------------------------------------
+
+extern "C" int titan_add_masses(titan_sim *s, int64_t n, const float *pos, const float *vel, const float *mass,
+                                const int32_t *body, int64_t *first_out)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->finalized)
+        return fail(TITAN_ESTATE, "masses can only be added before the first step");
+    if (n < 0)
+        return fail(TITAN_EINVAL, "negative count");
+    if (n > 0 && (!pos || !mass))
+        return fail(TITAN_EINVAL, "pos and mass are required");
+    if ((int64_t)s->h_mass.size() + n > (int64_t)std::numeric_limits<int32_t>::max())
+        return fail(TITAN_EINVAL, "too many masses (limit 2^31-1)");
+    for (int64_t i = 0; i < n; ++i) {
+        if (!finite3(pos + 3 * i))
+            return fail(TITAN_EINVAL, "mass %lld: non-finite position", (long long)i);
+        if (vel && !finite3(vel + 3 * i))
+            return fail(TITAN_EINVAL, "mass %lld: non-finite velocity", (long long)i);
+        if (!(std::isfinite(mass[i]) && mass[i] >= 0.f))
+            return fail(TITAN_EINVAL, "mass %lld: mass must be finite and >= 0", (long long)i);
+        if (body && body[i] < 0)
+            return fail(TITAN_EINVAL, "mass %lld: negative body id", (long long)i);
+    }
+    if (first_out)
+        *first_out = (int64_t)s->h_mass.size();
+    s->h_pos.insert(s->h_pos.end(), pos, pos + 3 * n);
+    if (vel)
+        s->h_vel.insert(s->h_vel.end(), vel, vel + 3 * n);
+    else
+        s->h_vel.insert(s->h_vel.end(), (size_t)(3 * n), 0.f);
+    s->h_mass.insert(s->h_mass.end(), mass, mass + n);
+    if (body)
+        s->h_body.insert(s->h_body.end(), body, body + n);
+    else
+        s->h_body.insert(s->h_body.end(), (size_t)n, 0);
+    return TITAN_OK;
+}
+
+extern "C" int titan_add_springs(titan_sim *s, int64_t n, const int64_t *ends, const float *k, const float *damping,
+                                 const float *rest, const float *amp, const float *phase, int64_t *first_out)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->finalized)
+        return fail(TITAN_ESTATE, "springs can only be added before the first step");
+    if (n < 0)
+        return fail(TITAN_EINVAL, "negative count");
+    if (n > 0 && (!ends || !k))
+        return fail(TITAN_EINVAL, "ends and k are required");
+    if ((amp == nullptr) != (phase == nullptr))
+        return fail(TITAN_EINVAL, "amp and phase must be given together");
+    const int64_t nm = (int64_t)s->h_mass.size();
+    if ((int64_t)s->h_k.size() + n > (int64_t)std::numeric_limits<int32_t>::max() / 2)
+        return fail(TITAN_EINVAL, "too many springs (limit 2^30-1)");
+    for (int64_t q = 0; q < n; ++q) {
+        const int64_t i = ends[2 * q], j = ends[2 * q + 1];
+        if (i < 0 || j < 0 || i >= nm || j >= nm)
+            return fail(TITAN_EINVAL, "spring %lld: end out of range [0, %lld)", (long long)q, (long long)nm);
+        if (i == j)
+            return fail(TITAN_EINVAL, "spring %lld: both ends are mass %lld", (long long)q, (long long)i);
+        if (s->h_body[i] != s->h_body[j])
+            return fail(TITAN_EINVAL, "spring %lld joins bodies %d and %d", (long long)q, s->h_body[i], s->h_body[j]);
+        const float *a = &s->h_pos[3 * i], *b = &s->h_pos[3 * j];
+        const double dx = (double)b[0] - a[0], dy = (double)b[1] - a[1], dz = (double)b[2] - a[2];
+        if (!(dx * dx + dy * dy + dz * dz > 0))
+            return fail(TITAN_EINVAL, "spring %lld: zero initial length", (long long)q);
+        if (!(std::isfinite(k[q]) && k[q] >= 0.f))
+            return fail(TITAN_EINVAL, "spring %lld: k must be finite and >= 0", (long long)q);
+        if (damping && !(std::isfinite(damping[q]) && damping[q] >= 0.f))
+            return fail(TITAN_EINVAL, "spring %lld: damping must be finite and >= 0", (long long)q);
+        if (rest && !(std::isfinite(rest[q]) && rest[q] > 0.f))
+            return fail(TITAN_EINVAL, "spring %lld: rest length must be finite and > 0", (long long)q);
+        if (amp && !(std::isfinite(amp[q]) && std::isfinite(phase[q])))
+            return fail(TITAN_EINVAL, "spring %lld: non-finite actuation", (long long)q);
+    }
+    if (first_out)
+        *first_out = (int64_t)s->h_k.size();
+    s->h_ends.insert(s->h_ends.end(), ends, ends + 2 * n);
+    s->h_k.insert(s->h_k.end(), k, k + n);
+    if (damping)
+        s->h_damp.insert(s->h_damp.end(), damping, damping + n);
+    else
+        s->h_damp.insert(s->h_damp.end(), (size_t)n, 0.f);
+    if (rest)
+        s->h_rest.insert(s->h_rest.end(), rest, rest + n);
+    else
+        s->h_rest.insert(s->h_rest.end(), (size_t)n, -1.f);  // -1: initial length
+    if (amp) {
+        s->h_amp.insert(s->h_amp.end(), amp, amp + n);
+        s->h_phase.insert(s->h_phase.end(), phase, phase + n);
+    } else {
+        s->h_amp.insert(s->h_amp.end(), (size_t)n, 0.f);
+        s->h_phase.insert(s->h_phase.end(), (size_t)n, 0.f);
+    }
+    return TITAN_OK;
+}
+
+extern "C" int titan_set_params(titan_sim *s, const titan_params *p)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (int rc = check_params(p))
+        return rc;
+    if (s->finalized && p->engine != s->params.engine)
+        return fail(TITAN_ESTATE, "the engine can only be chosen before the first step");
+    s->params = *p;
+    return TITAN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// finalize: device representation
+// ---------------------------------------------------------------------------
+
+static int ensure_device(titan_sim *s)
+{
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) {
+        (void)hipGetLastError();
+        s->dev_error = true;
+        return fail(TITAN_EDEVICE, "no usable HIP device (%s)", e == hipSuccess ? "count 0" : hipGetErrorString(e));
+    }
+    HIP_TRY(s, hipGetDevice(&s->device));
+    return TITAN_OK;
+}
+
+static int finalize_locked(titan_sim *s)
+{
+    if (s->finalized)
+        return TITAN_OK;
+    if (s->dev_error)
+        return fail(TITAN_EDEVICE, "sim is in a failed device state");
+    if (int rc = ensure_device(s))
+        return rc;
+    const int64_t n = (int64_t)s->h_mass.size();
+    s->n = n;
+    s->ns = (int64_t)s->h_k.size();
+
+    // Reference positions and initial state in internal order.  The internal
+    // order is the caller's order for now (perm = identity).
+    s->perm.resize(n);
+    for (int64_t i = 0; i < n; ++i)
+        s->perm[i] = i;
+    std::vector<float4> hX0(n), hU(n), hV(n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t u = s->perm[i];
+        hX0[i] = make_float4(s->h_pos[3 * u], s->h_pos[3 * u + 1], s->h_pos[3 * u + 2], 0.f);
+        const float m = s->h_mass[u];
+        hU[i] = make_float4(0.f, 0.f, 0.f, m > 0.f ? (float)(1.0 / (double)m) : 0.f);
+        hV[i] = make_float4(s->h_vel[3 * u], s->h_vel[3 * u + 1], s->h_vel[3 * u + 2], 0.f);
+    }
+    s->hX0 = hX0;
+
+    for (int b = 0; b < 2; ++b) {
+        if (int rc = dev_alloc(s, sizeof(float4) * n, (void **)&s->U[b]))
+            return rc;
+        if (int rc = dev_alloc(s, sizeof(float4) * n, (void **)&s->V[b]))
+            return rc;
+    }
+    if (int rc = upload(s, hX0, &s->X0))
+        return rc;
+    if (n)
+        HIP_TRY(s, hipMemcpyAsync(s->U[0], hU.data(), sizeof(float4) * n, hipMemcpyHostToDevice, s->stream));
+    if (n)
+        HIP_TRY(s, hipMemcpyAsync(s->V[0], hV.data(), sizeof(float4) * n, hipMemcpyHostToDevice, s->stream));
+    s->cur = 0;
+
+    if (int rc = dev_alloc(s, sizeof(unsigned long long), (void **)&s->first_bad))
+        return rc;
+    const unsigned long long none = ~0ull;
+    HIP_TRY(s, hipMemcpyAsync(s->first_bad, &none, sizeof none, hipMemcpyHostToDevice, s->stream));
+
+    // Engine selection.
+    int engine = s->params.engine;
+    if (engine == TITAN_ENGINE_AUTO || engine == TITAN_ENGINE_BATCHED)
+        engine = TITAN_ENGINE_GATHER;  // the batched engine is selected by build_engines when eligible
+    s->engine = engine;
+    if (int rc = build_engines(s))
+        return rc;
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    HIP_TRY(s, hipStreamCreateWithFlags(&s->side_stream, hipStreamNonBlocking));
+    HIP_TRY(s, hipHostMalloc(&s->host_stage, sizeof(float4) * (n > 0 ? 2 * n : 2), hipHostMallocDefault));
+    s->finalized = true;
+    return TITAN_OK;
+}
+
+extern "C" int titan_finalize(titan_sim *s)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    return finalize_locked(s);
+}
+
+// ---------------------------------------------------------------------------
+// stepping and breakpoints
+// ---------------------------------------------------------------------------
+
+static int fire_breakpoints(titan_sim *s)
+{
+    for (auto &kv : s->bps) {
+        BP &bp = kv.second;
+        if (bp.fired || bp.step != s->step_enq)
+            continue;
+        if (s->n) {
+            HIP_TRY(s, hipMemcpyAsync(bp.snapU, s->U[s->cur], sizeof(float4) * s->n, hipMemcpyDeviceToDevice, s->stream));
+            HIP_TRY(s, hipMemcpyAsync(bp.snapV, s->V[s->cur], sizeof(float4) * s->n, hipMemcpyDeviceToDevice, s->stream));
+        }
+        HIP_TRY(s, hipEventRecord(bp.ev, s->stream));
+        bp.fired = true;
+        if (bp.kind == TITAN_BP_PAUSE)
+            s->paused = true;
+    }
+    return TITAN_OK;
+}
+
+static int pump(titan_sim *s)
+{
+    if (int rc = fire_breakpoints(s))
+        return rc;
+    while (!s->paused && s->step_enq < s->steps_req) {
+        int64_t end = s->steps_req;
+        for (auto &kv : s->bps)
+            if (!kv.second.fired && kv.second.step > s->step_enq && kv.second.step < end)
+                end = kv.second.step;
+        if (int rc = enqueue_steps(s, s->step_enq, end - s->step_enq))
+            return rc;
+        s->step_enq = end;
+        if (int rc = fire_breakpoints(s))
+            return rc;
+    }
+    return TITAN_OK;
+}
+
+static int ready(titan_sim *s)
+{
+    if (s->dev_error)
+        return fail(TITAN_EDEVICE, "sim is in a failed device state");
+    if (!s->finalized)
+        if (int rc = finalize_locked(s))
+            return rc;
+    HIP_TRY(s, hipSetDevice(s->device));
+    return TITAN_OK;
+}
+
+extern "C" int titan_step(titan_sim *s, int64_t n)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (n < 0)
+        return fail(TITAN_EINVAL, "negative step count");
+    if (int rc = ready(s))
+        return rc;
+    s->steps_req += n;
+    return pump(s);
+}
+
+extern "C" int titan_set_breakpoint(titan_sim *s, int64_t step, int32_t kind, uint64_t *bp_out)
+{
+    if (!s || !bp_out)
+        return fail(TITAN_EINVAL, "sim or bp_out is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (kind != TITAN_BP_SNAPSHOT && kind != TITAN_BP_PAUSE)
+        return fail(TITAN_EINVAL, "unknown breakpoint kind %d", kind);
+    if (int rc = ready(s))
+        return rc;
+    if (step < s->step_enq)
+        return fail(TITAN_EINVAL, "breakpoint step %lld is behind the %lld steps already enqueued",
+                    (long long)step, (long long)s->step_enq);
+    BP bp;
+    bp.id = ++s->next_bp;
+    bp.step = step;
+    bp.kind = kind;
+    HIP_TRY(s, hipEventCreateWithFlags(&bp.ev, hipEventDisableTiming));
+    if (int rc = dev_alloc(s, sizeof(float4) * s->n, (void **)&bp.snapU))
+        return rc;
+    if (int rc = dev_alloc(s, sizeof(float4) * s->n, (void **)&bp.snapV))
+        return rc;
+    s->bps[bp.id] = bp;
+    *bp_out = bp.id;
+    return pump(s);
+}
+
+static int check_bad(titan_sim *s)
+{
+    unsigned long long fb = ~0ull;
+    HIP_TRY(s, hipMemcpy(&fb, s->first_bad, sizeof fb, hipMemcpyDeviceToHost));
+    if (fb != ~0ull) {
+        s->first_bad_step = (int64_t)fb;
+        return fail(TITAN_ENONFINITE, "non-finite state first produced by step %lld", (long long)fb);
+    }
+    return TITAN_OK;
+}
+
+extern "C" int titan_wait(titan_sim *s, uint64_t id)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->bps.find(id);
+    if (it == s->bps.end())
+        return fail(TITAN_EINVAL, "unknown breakpoint %llu", (unsigned long long)id);
+    if (int rc = ready(s))
+        return rc;
+    if (!it->second.fired)
+        return fail(TITAN_ESTATE, "breakpoint at step %lld is not reached by the %lld steps requested%s",
+                    (long long)it->second.step, (long long)s->steps_req, s->paused ? " (paused)" : "");
+    HIP_TRY(s, hipEventSynchronize(it->second.ev));
+    return check_bad(s);
+}
+
+extern "C" int titan_resume(titan_sim *s)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (int rc = ready(s))
+        return rc;
+    s->paused = false;
+    return pump(s);
+}
+
+extern "C" int titan_sync(titan_sim *s)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (int rc = ready(s))
+        return rc;
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return check_bad(s);
+}
+
+// ---------------------------------------------------------------------------
+// state I/O
+// ---------------------------------------------------------------------------
+
+static int check_range(titan_sim *s, int64_t first, int64_t count)
+{
+    if (first < 0 || count < 0 || first + count > s->n)
+        return fail(TITAN_EINVAL, "range [%lld, %lld) outside [0, %lld)", (long long)first,
+                    (long long)(first + count), (long long)s->n);
+    return TITAN_OK;
+}
+
+// Device state (internal order, U/V float4) -> caller arrays for [first, first+count).
+static void export_state(titan_sim *s, const float4 *hU, const float4 *hV, int64_t first, int64_t count,
+                         float *pos, float *vel, int32_t flags)
+{
+    for (int64_t q = 0; q < count; ++q) {
+        const int64_t i = s->inv_perm_of(first + q);
+        if (pos) {
+            if (flags & TITAN_STATE_DISPLACEMENT) {
+                pos[3 * q] = hU[i].x;
+                pos[3 * q + 1] = hU[i].y;
+                pos[3 * q + 2] = hU[i].z;
+            } else {
+                pos[3 * q] = (float)((double)s->hX0[i].x + hU[i].x);
+                pos[3 * q + 1] = (float)((double)s->hX0[i].y + hU[i].y);
+                pos[3 * q + 2] = (float)((double)s->hX0[i].z + hU[i].z);
+            }
+        }
+        if (vel) {
+            vel[3 * q] = hV[i].x;
+            vel[3 * q + 1] = hV[i].y;
+            vel[3 * q + 2] = hV[i].z;
+        }
+    }
+}
+
+extern "C" int titan_get_state(titan_sim *s, int64_t first, int64_t count, float *pos, float *vel, int32_t flags,
+                               int64_t *step_out)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (int rc = ready(s))
+        return rc;
+    if (int rc = check_range(s, first, count))
+        return rc;
+    float4 *hU = s->host_stage, *hV = s->host_stage + s->n;
+    if (s->n) {
+        HIP_TRY(s, hipMemcpyAsync(hU, s->U[s->cur], sizeof(float4) * s->n, hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(s, hipMemcpyAsync(hV, s->V[s->cur], sizeof(float4) * s->n, hipMemcpyDeviceToHost, s->stream));
+    }
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    if (step_out)
+        *step_out = s->step_enq;
+    export_state(s, hU, hV, first, count, pos, vel, flags);
+    return check_bad(s);
+}
+
+extern "C" int titan_get_snapshot(titan_sim *s, uint64_t id, int64_t first, int64_t count, float *pos, float *vel,
+                                  int32_t flags, int64_t *step_out)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->bps.find(id);
+    if (it == s->bps.end())
+        return fail(TITAN_EINVAL, "unknown breakpoint %llu", (unsigned long long)id);
+    if (int rc = ready(s))
+        return rc;
+    if (int rc = check_range(s, first, count))
+        return rc;
+    BP &bp = it->second;
+    if (!bp.fired)
+        return fail(TITAN_ESTATE, "breakpoint at step %lld not reached", (long long)bp.step);
+    // Copy out on the side stream after the snapshot event: the compute stream
+    // keeps running the steps behind the breakpoint.
+    float4 *hU = s->host_stage, *hV = s->host_stage + s->n;
+    HIP_TRY(s, hipStreamWaitEvent(s->side_stream, bp.ev, 0));
+    if (s->n) {
+        HIP_TRY(s, hipMemcpyAsync(hU, bp.snapU, sizeof(float4) * s->n, hipMemcpyDeviceToHost, s->side_stream));
+        HIP_TRY(s, hipMemcpyAsync(hV, bp.snapV, sizeof(float4) * s->n, hipMemcpyDeviceToHost, s->side_stream));
+    }
+    HIP_TRY(s, hipStreamSynchronize(s->side_stream));
+    if (step_out)
+        *step_out = bp.step;
+    export_state(s, hU, hV, first, count, pos, vel, flags);
+    return TITAN_OK;
+}
+
+extern "C" int titan_set_state(titan_sim *s, int64_t first, int64_t count, const float *pos, const float *vel,
+                               int32_t flags)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (int rc = ready(s))
+        return rc;
+    if (int rc = check_range(s, first, count))
+        return rc;
+    for (int64_t q = 0; q < count; ++q) {
+        if ((pos && !finite3(pos + 3 * q)) || (vel && !finite3(vel + 3 * q)))
+            return fail(TITAN_EINVAL, "mass %lld: non-finite state", (long long)(first + q));
+    }
+    if (!s->n || (!pos && !vel))
+        return TITAN_OK;
+    float4 *hU = s->host_stage, *hV = s->host_stage + s->n;
+    HIP_TRY(s, hipMemcpyAsync(hU, s->U[s->cur], sizeof(float4) * s->n, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(hV, s->V[s->cur], sizeof(float4) * s->n, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    for (int64_t q = 0; q < count; ++q) {
+        const int64_t i = s->inv_perm_of(first + q);
+        if (pos) {
+            float u[3];
+            for (int c = 0; c < 3; ++c) {
+                const float x0 = c == 0 ? s->hX0[i].x : c == 1 ? s->hX0[i].y : s->hX0[i].z;
+                u[c] = (flags & TITAN_STATE_DISPLACEMENT) ? pos[3 * q + c] : (float)((double)pos[3 * q + c] - x0);
+            }
+            hU[i].x = u[0];
+            hU[i].y = u[1];
+            hU[i].z = u[2];
+        }
+        if (vel) {
+            hV[i].x = vel[3 * q];
+            hV[i].y = vel[3 * q + 1];
+            hV[i].z = vel[3 * q + 2];
+        }
+    }
+    HIP_TRY(s, hipMemcpyAsync(s->U[s->cur], hU, sizeof(float4) * s->n, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(s->V[s->cur], hV, sizeof(float4) * s->n, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    // A new state clears a previous non-finite report.
+    const unsigned long long none = ~0ull;
+    HIP_TRY(s, hipMemcpy(s->first_bad, &none, sizeof none, hipMemcpyHostToDevice));
+    s->first_bad_step = -1;
+    return TITAN_OK;
+}
+
+extern "C" int titan_set_step(titan_sim *s, int64_t step)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (step < 0)
+        return fail(TITAN_EINVAL, "negative step index");
+    if (int rc = ready(s))
+        return rc;
+    if (s->steps_req != s->step_enq)
+        return fail(TITAN_ESTATE, "%lld steps are held at a pause breakpoint",
+                    (long long)(s->steps_req - s->step_enq));
+    s->step_enq = step;
+    s->steps_req = step;
+    return TITAN_OK;
+}
+
+extern "C" int titan_get_forces(titan_sim *s, int64_t first, int64_t count, float *f)
+{
+    if (!s || (!f && count))
+        return fail(TITAN_EINVAL, "sim or f is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (int rc = ready(s))
+        return rc;
+    if (int rc = check_range(s, first, count))
+        return rc;
+    if (!s->n)
+        return TITAN_OK;
+    if (int rc = compute_forces(s))
+        return rc;
+    float4 *hF = s->host_stage;
+    HIP_TRY(s, hipMemcpyAsync(hF, s->F, sizeof(float4) * s->n, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    for (int64_t q = 0; q < count; ++q) {
+        const int64_t i = s->inv_perm_of(first + q);
+        f[3 * q] = hF[i].x;
+        f[3 * q + 1] = hF[i].y;
+        f[3 * q + 2] = hF[i].z;
+    }
+    return TITAN_OK;
+}
+
+extern "C" int titan_get_info(titan_sim *s, titan_info *info)
+{
+    if (!s || !info)
+        return fail(TITAN_EINVAL, "sim or info is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    memset(info, 0, sizeof *info);
+    info->n_masses = (int64_t)s->h_mass.size();
+    info->n_springs = (int64_t)s->h_k.size();
+    int32_t maxb = -1;
+    for (int32_t b : s->h_body)
+        maxb = std::max(maxb, b);
+    info->n_bodies = maxb < 0 ? 1 : (int64_t)maxb + 1;
+    info->step = s->step_enq;
+    info->steps_requested = s->steps_req;
+    info->first_bad_step = s->first_bad_step;
+    info->finalized = s->finalized;
+    info->engine = s->finalized ? s->engine : s->params.engine;
+    info->device = s->device;
+    info->paused = s->paused;
+    info->device_bytes = s->device_bytes;
+    return TITAN_OK;
+}

@@ -1,0 +1,57 @@
+// Internal declarations shared by the host runtime and the kernel translation
+// units of libtitan.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace titan {
+
+// Width of a sliced-ELL slice: one wavefront of masses.
+constexpr int kSlice = 64;
+
+// Per-step scalars of the gather engine.
+struct StepConsts {
+    float dt;
+    float gx, gy, gz;
+    float ground_k;
+    float mu;
+    float sin_wt, cos_wt;  // sin/cos(omega * t_n), t_n = n * dt, rounded from FP64
+    int32_t ground;
+    int64_t step;          // step index n (for the non-finite report)
+};
+
+// Device representation used by the gather engine.  Masses are in internal
+// order; per-incidence arrays are sliced-ELL: the w-th incidence of the mass
+// in lane l of slice s sits at slice_off[s] + w*64 + l.
+struct GatherGraph {
+    int64_t n;                 // masses
+    int64_t n_slices;
+    const int64_t *slice_off;  // [n_slices + 1]
+    const int32_t *deg;        // [n] incidences of each mass
+    const int32_t *nbr;        // [slots] internal index of the other end
+    const float *k;            // [slots] stiffness
+    const float *c;            // [slots] damping, or null: c_uniform
+    const float *act_c;        // [slots] amp*cos(phase), or null: no actuation
+    const float *act_s;        // [slots] amp*sin(phase)
+    const float *d0;           // [slots] |R| - rest (FP64-rounded), or null: rest = |R|
+    const float *rest;         // [slots] rest length (with d0)
+    const float4 *X0;          // [n] reference positions (w unused)
+    float c_uniform;
+};
+
+// State buffers: U = (x - x0, inverse mass), V = (v, 0).
+struct StateIO {
+    const float4 *U_in;
+    const float4 *V_in;
+    float4 *U_out;
+    float4 *V_out;
+    float4 *F_out;                   // forces-only mode: summed spring force
+    unsigned long long *first_bad;   // min step index that produced a non-finite value
+};
+
+// Launch one gather step (or, with forces_only, only the spring-force sum).
+hipError_t launch_gather_step(const GatherGraph &g, const StateIO &io, const StepConsts &sc,
+                              bool forces_only, hipStream_t stream);
+
+}  // namespace titan

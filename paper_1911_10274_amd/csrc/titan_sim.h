@@ -1,0 +1,92 @@
+// The titan_sim object and the engine interface of the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "titan.h"
+#include "titan_internal.h"
+
+namespace titan {
+
+struct BP {
+    uint64_t id = 0;
+    int64_t step = 0;
+    int32_t kind = TITAN_BP_SNAPSHOT;
+    bool fired = false;
+    hipEvent_t ev = nullptr;
+    float4 *snapU = nullptr;
+    float4 *snapV = nullptr;
+};
+
+struct BatchEngine;  // defined by the batched engine
+
+}  // namespace titan
+
+struct titan_sim {
+    std::mutex mu;
+    titan_params params{};
+    hipStream_t stream = nullptr;
+    hipStream_t side_stream = nullptr;
+    titan_allocator alloc{};
+
+    // host staging, caller order
+    std::vector<float> h_pos, h_vel, h_mass;
+    std::vector<int32_t> h_body;
+    std::vector<int64_t> h_ends;
+    std::vector<float> h_k, h_damp, h_rest, h_amp, h_phase;
+
+    // device state
+    bool finalized = false;
+    bool dev_error = false;
+    int device = 0;
+    int engine = TITAN_ENGINE_GATHER;
+    std::vector<void *> allocations;
+    int64_t device_bytes = 0;
+    int64_t n = 0, ns = 0;
+    std::vector<int64_t> perm;      // perm[internal] = caller index
+    std::vector<int64_t> inv_perm;  // inv_perm[caller] = internal index (empty: identity)
+    std::vector<float4> hX0;        // reference positions, internal order
+    float4 *U[2] = {nullptr, nullptr};
+    float4 *V[2] = {nullptr, nullptr};
+    float4 *X0 = nullptr;
+    float4 *F = nullptr;
+    int cur = 0;
+    unsigned long long *first_bad = nullptr;
+    float4 *host_stage = nullptr;  // pinned, 2*n float4
+
+    // gather engine
+    titan::GatherGraph gg{};
+
+    // batched engine (null unless selected)
+    titan::BatchEngine *batch = nullptr;
+
+    // step queue and breakpoints
+    int64_t step_enq = 0;
+    int64_t steps_req = 0;
+    bool paused = false;
+    uint64_t next_bp = 0;
+    std::map<uint64_t, titan::BP> bps;
+    int64_t first_bad_step = -1;
+
+    int64_t inv_perm_of(int64_t caller) const { return inv_perm.empty() ? caller : inv_perm[caller]; }
+};
+
+namespace titan {
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(titan_sim *sim, hipError_t e, const char *what);
+int dev_alloc(titan_sim *s, size_t bytes, void **out);
+
+// Engines (engine_gather.hip): build the device representation of the
+// selected engine after the state buffers exist, enqueue steps, compute the
+// spring-force sum, and release engine-private resources.
+int build_engines(titan_sim *s);
+int enqueue_steps(titan_sim *s, int64_t first_step, int64_t count);
+int compute_forces(titan_sim *s);
+void destroy_engines(titan_sim *s);
+
+}  // namespace titan

@@ -1,0 +1,59 @@
+"""Helpers shared by the GPU parity tests: run the native path and the FP64
+oracle on the same seeded scene and compare per step."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import oracle as O
+
+TOL = 1e-5  # relative error per step over the first 10 steps
+
+
+def both_params(dt=1e-4, gravity=(0.0, 0.0, -9.81), ground=True, ground_k=1e5, mu=0.5, omega=0.0, engine=None):
+    from paper_1911_10274_amd import titan as T
+
+    tp = T.Params(dt=dt, gravity=gravity, ground=ground, ground_k=ground_k, friction_mu=mu, omega=omega,
+                  engine=T.ENGINE_GATHER if engine is None else engine)
+    op = O.Params(dt=dt, gravity=gravity, ground=ground, ground_k=ground_k, mu=mu, omega=omega)
+    return tp, op
+
+
+def rel(a, b, floor=0.0):
+    num = float(np.linalg.norm(np.asarray(a, np.float64) - b))
+    den = max(float(np.linalg.norm(b)), floor)
+    return num / den if den > 0 else num
+
+
+def gpu_series(sim, nsteps, with_start_states=False):
+    """Per step n = 1..nsteps of the native path: displacement, velocity and
+    the spring force of step n's starting state.  With ``with_start_states``
+    also the (displacement, velocity) each step started from."""
+    dX, V, F, S = [], [], [], []
+    p, v, _ = sim.get_state(displacement=True)
+    for _ in range(nsteps):
+        S.append((p.astype(np.float64), v.astype(np.float64)))
+        F.append(sim.get_forces().astype(np.float64))
+        sim.step(1)
+        p, v, _ = sim.get_state(displacement=True)
+        dX.append(p.astype(np.float64))
+        V.append(v.astype(np.float64))
+    out = np.array(dX), np.array(V), np.array(F)
+    return (out, S) if with_start_states else out
+
+
+def compare_series(gpu, ref, mass, g=9.81, label=""):
+    """Worst per-step relative errors (displacement, velocity, force).
+
+    The spring-force error is taken relative to the larger of the reference
+    force norm and the weight norm ||m g|| over all masses: where springs are
+    at rest (free fall, rigid sliding) the exact spring force is zero and only
+    its size against the forces that drive the motion is meaningful."""
+    gdX, gV, gF = gpu
+    rdX, rV, rF = ref
+    ffloor = float(np.linalg.norm(np.asarray(mass, np.float64) * g))
+    out = {"dX": 0.0, "V": 0.0, "F": 0.0}
+    for s in range(gdX.shape[0]):
+        out["dX"] = max(out["dX"], rel(gdX[s], rdX[s]))
+        out["V"] = max(out["V"], rel(gV[s], rV[s]))
+        out["F"] = max(out["F"], rel(gF[s], rF[s], ffloor))
+    return out

@@ -1,0 +1,117 @@
+"""C ABI: the library loads, exports every function the header declares, and
+its host-side validation works without a GPU (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "titan.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(titan_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    from paper_1911_10274_amd import titan as T
+
+    names = _declared()
+    assert "titan_step" in names and "titan_create" in names
+    for name in names:
+        assert hasattr(T.lib, name), name
+
+
+def test_abi_version():
+    from paper_1911_10274_amd import titan as T
+
+    src = open(HEADER).read()
+    want = int(re.search(r"#define TITAN_ABI_VERSION (\d+)", src).group(1))
+    assert T.lib.titan_abi_version() == want
+
+
+def _host_sim():
+    from paper_1911_10274_amd import titan as T
+
+    return T.Sim(T.Params(), memory="hip")
+
+
+def test_validation_errors_without_gpu():
+    from paper_1911_10274_amd import titan as T
+
+    sim = _host_sim()
+    pos = np.array([[0, 0, 0], [1, 0, 0], [1, 0, 0]], np.float32)
+    assert sim.add_masses(pos, [1, 1, 0]) == 0
+    cases = [
+        dict(ends=[[0, 3]], k=[1.0]),                 # out of range
+        dict(ends=[[1, 1]], k=[1.0]),                 # self spring
+        dict(ends=[[1, 2]], k=[1.0]),                 # zero initial length
+        dict(ends=[[0, 1]], k=[-1.0]),                # negative k
+        dict(ends=[[0, 1]], k=[np.nan]),              # non-finite
+        dict(ends=[[0, 1]], k=[1.0], rest=[0.0]),     # zero rest
+        dict(ends=[[0, 1]], k=[1.0], damping=[-1.0]),
+    ]
+    for c in cases:
+        with pytest.raises(T.TitanError) as ei:
+            sim.add_springs(**c)
+        assert ei.value.code == T.EINVAL
+        assert T.last_error()
+    with pytest.raises(T.TitanError):
+        sim.add_springs([[0, 1]], [1.0], amp=[0.1])  # amp without phase
+    assert sim.add_springs([[0, 1]], [1.0]) == 0
+    assert sim.add_springs([[0, 2], [1, 0]], [1.0, 2.0]) == 1
+    with pytest.raises(T.TitanError):
+        sim.add_masses([[0, 0, np.inf]], [1.0])
+    with pytest.raises(T.TitanError):
+        sim.add_masses([[0, 0, 0]], [-1.0])
+    info = sim.info()
+    assert info["n_masses"] == 3 and info["n_springs"] == 3 and info["finalized"] == 0
+    sim.close()
+
+
+def test_bodies_cannot_be_joined():
+    from paper_1911_10274_amd import titan as T
+
+    sim = _host_sim()
+    sim.add_masses([[0, 0, 0], [1, 0, 0]], [1, 1], body=[0, 1])
+    with pytest.raises(T.TitanError) as ei:
+        sim.add_springs([[0, 1]], [1.0])
+    assert ei.value.code == T.EINVAL
+    assert sim.info()["n_bodies"] == 2
+    sim.close()
+
+
+def test_bad_params_rejected():
+    from paper_1911_10274_amd import titan as T
+
+    for p in [T.Params(dt=0.0), T.Params(dt=-1.0), T.Params(ground_k=-1.0), T.Params(friction_mu=float("nan")),
+              T.Params(engine=7)]:
+        with pytest.raises(T.TitanError) as ei:
+            T.Sim(p, memory="hip")
+        assert ei.value.code == T.EINVAL
+
+
+def test_null_sim_is_rejected():
+    from paper_1911_10274_amd import titan as T
+
+    assert T.lib.titan_step(None, 1) == T.EINVAL
+    assert T.lib.titan_destroy(None) == T.OK
+
+
+def test_step_without_device_reports_edevice():
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_1911_10274_amd import titan as T
+
+    sim = _host_sim()
+    sim.add_masses([[0, 0, 1]], [1.0])
+    with pytest.raises(T.TitanError) as ei:
+        sim.step(1)
+    assert ei.value.code == T.EDEVICE
+    sim.close()

@@ -1,0 +1,145 @@
+"""The asynchronous CPU/GPU model (Sec. III-D): breakpoints, pausing, edits
+applied at a breakpoint, snapshots read while stepping continues, recovery
+from a checkpoint.  Stepping is deterministic, so every comparison here is
+bitwise."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1911_10274_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(seed=4, n=12):
+    from paper_1911_10274_amd import titan as T
+
+    sc = scenes.jittered_actuated_lattice(n=n, seed=seed)
+    tp = T.Params(dt=5e-5, omega=2 * math.pi * 2, engine=T.ENGINE_GATHER)
+    return T, T.sim_from_scene(sc, tp), sc
+
+
+def _state(sim):
+    p, v, step = sim.get_state(displacement=True)
+    return p, v, step
+
+
+def test_snapshot_breakpoint_equals_synchronous_state():
+    T, a, _ = _sim()
+    bp = a.set_breakpoint(5, T.BP_SNAPSHOT)
+    a.step(40)
+    a.wait(bp)
+    ps, vs, step = a.get_snapshot(bp, displacement=True)
+    assert step == 5
+    _, b, _ = _sim()
+    b.step(5)
+    pb, vb, _ = _state(b)
+    assert np.array_equal(ps, pb) and np.array_equal(vs, vb)
+    pa, va, stepa = _state(a)
+    assert stepa == 40
+    b.step(35)
+    pb, vb, _ = _state(b)
+    assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+    a.close()
+    b.close()
+
+
+def test_pause_edit_resume():
+    T, a, sc = _sim()
+    bp = a.set_breakpoint(7, T.BP_PAUSE)
+    a.step(20)
+    info = a.info()
+    assert info["paused"] == 1 and info["step"] == 7 and info["steps_requested"] == 20
+    a.wait(bp)
+    p7, v7, step = _state(a)
+    assert step == 7
+    kick = v7.copy()
+    kick[:50] += np.float32(0.25)
+    a.set_state(vel=kick)  # applied at the breakpoint
+    a.set_params(T.Params(dt=5e-5, omega=2 * math.pi * 2, gravity=(0.0, 0.0, -5.0)))
+    a.resume()
+    pa, va, stepa = _state(a)
+    assert stepa == 20
+    # same sequence, synchronously
+    _, b, _ = _sim()
+    b.step(7)
+    b.set_state(vel=kick)
+    b.set_params(T.Params(dt=5e-5, omega=2 * math.pi * 2, gravity=(0.0, 0.0, -5.0)))
+    b.step(13)
+    pb, vb, _ = _state(b)
+    assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+    a.close()
+    b.close()
+
+
+def test_breakpoint_errors():
+    T, a, _ = _sim()
+    a.step(10)
+    with pytest.raises(T.TitanError) as ei:
+        a.set_breakpoint(3)  # behind the enqueued steps
+    assert ei.value.code == T.EINVAL
+    bp = a.set_breakpoint(50)
+    with pytest.raises(T.TitanError) as ei:
+        a.wait(bp)  # not enough steps requested
+    assert ei.value.code == T.ESTATE
+    a.step(40)
+    a.wait(bp)
+    with pytest.raises(T.TitanError):
+        a.wait(12345)
+    a.close()
+
+
+def test_recovery_from_checkpoint_is_bitwise():
+    T, a, _ = _sim()
+    a.step(30)
+    pc, vc, _ = _state(a)                        # checkpoint
+    a.set_state(vel=np.zeros_like(vc) + 3.0)     # corrupt
+    a.step(5)
+    a.set_state(pos=pc, vel=vc, displacement=True)  # restore the state ...
+    a.set_step(30)                                   # ... and the time
+    a.step(20)
+    pa, va, _ = _state(a)
+    _, b, _ = _sim()
+    b.step(50)
+    pb, vb, _ = _state(b)
+    assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+    a.close()
+    b.close()
+
+
+def test_runs_on_a_caller_stream_and_torch_memory():
+    import torch
+
+    from paper_1911_10274_amd import titan as T
+
+    sc = scenes.jittered_actuated_lattice(n=10, seed=9)
+    tp = T.Params(dt=5e-5, omega=2 * math.pi * 2, engine=T.ENGINE_GATHER)
+    before = torch.cuda.memory_allocated()
+    s = torch.cuda.Stream()
+    a = T.sim_from_scene(sc, tp, stream=s)
+    a.step(25)
+    assert torch.cuda.memory_allocated() > before  # buffers come from torch's allocator
+    assert a.info()["device_bytes"] > 0
+    pa, va, _ = a.get_state(displacement=True)
+    b = T.sim_from_scene(sc, tp, memory="hip")
+    b.step(25)
+    pb, vb, _ = b.get_state(displacement=True)
+    assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+    a.close()
+    b.close()
+    torch.cuda.synchronize()
+
+
+def test_absolute_state_roundtrip():
+    T, a, sc = _sim()
+    a.step(3)
+    p, v, _ = a.get_state()
+    a.set_state(pos=p, vel=v)
+    p2, v2, _ = a.get_state()
+    assert np.allclose(p, p2, atol=1e-6) and np.array_equal(v, v2)
+    with pytest.raises(T.TitanError):
+        a.set_state(pos=np.full((3, 3), np.nan, np.float32))
+    with pytest.raises(T.TitanError):
+        a.get_state(first=a.n_masses, count=1)
+    a.close()

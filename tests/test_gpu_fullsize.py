@@ -1,0 +1,45 @@
+"""Parity at the benchmark's full size and in its launch configuration: the
+1,000,000-mass / 12,731,796-spring actuated lattice, every mass, steps 1..10,
+and a 64-robot sub-batch of the uneven voxel-robot workload."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1911_10274_amd import scenes
+from tests.parity import TOL, both_params, compare_series, gpu_series
+
+pytestmark = pytest.mark.gpu
+
+
+def test_large_lattice_full_size_10_steps():
+    from paper_1911_10274_amd import titan as T
+
+    sc = scenes.jittered_actuated_lattice(n=100, seed=2)
+    assert sc["ends"].shape[0] == 12731796
+    tp, op = both_params(dt=5e-5, omega=2 * math.pi * 2)
+    sim = T.sim_from_scene(sc, tp)
+    gpu = gpu_series(sim, 10)
+    sim.close()
+    sysm = O.System(sc)
+    ref = sysm.trajectory(op, 10)
+    err = compare_series(gpu, ref, sysm.mass)
+    print("full size lattice", err)
+    assert max(err.values()) <= TOL
+
+
+def test_voxel_robot_subbatch_10_steps():
+    from paper_1911_10274_amd import titan as T
+
+    robots = scenes.robot_batch(64, seed=3, side_lo=3, side_hi=12)
+    sc = scenes.concat(robots)
+    tp, op = both_params(dt=1e-4, omega=2 * math.pi * 2)
+    sim = T.sim_from_scene(sc, tp)
+    gpu = gpu_series(sim, 10)
+    sim.close()
+    sysm = O.System(sc)
+    ref = sysm.trajectory(op, 10)
+    err = compare_series(gpu, ref, sysm.mass)
+    print("voxel sub-batch", err)
+    assert max(err.values()) <= TOL
