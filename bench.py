@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "gather_step_lattice100.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1911_10274_amd", "csrc", "gather_step.hip")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1911_10274_amd", "csrc", f) for f in ("gather_step.hip", "step_device.h")]
 
 
 def algorithmic_bytes(n_masses: int, n_springs: int) -> int:
@@ -119,6 +119,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--engine", choices=("tiled", "gather"), default="tiled")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -137,9 +138,11 @@ def main():
     scene = build_workload(args.n, args.seed)
     nm, ns = scene["pos"].shape[0], scene["ends"].shape[0]
     tp = T.Params(dt=PARAMS["dt"], gravity=PARAMS["gravity"], ground=PARAMS["ground"], ground_k=PARAMS["ground_k"],
-                  friction_mu=PARAMS["mu"], omega=PARAMS["omega"], engine=T.ENGINE_GATHER)
+                  friction_mu=PARAMS["mu"], omega=PARAMS["omega"],
+                  engine=T.ENGINE_TILED if args.engine == "tiled" else T.ENGINE_GATHER)
     sim = T.sim_from_scene(scene, tp)
     sim.finalize()
+    engine = {T.ENGINE_TILED: "tiled", T.ENGINE_GATHER: "gather"}[sim.info()["engine"]]
     stream = torch.cuda.current_stream()
 
     sim.step(args.warmup)
@@ -186,12 +189,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"actuated jittered lattice {args.n}^3 (plain fused gather step)",
+            "workload": f"actuated jittered lattice {args.n}^3 (plain fused step, {engine} kernel)",
             "masses": nm,
             "springs": ns,
             "dt": PARAMS["dt"],
             "seed": args.seed,
-            "engine": "gather",
+            "engine": engine,
             "algorithmic_bytes_per_step": abytes,
         },
         "roofline": roofline,

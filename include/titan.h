@@ -70,6 +70,10 @@ extern "C" {
 #define TITAN_ENGINE_BATCHED 2 /* one workgroup per independent body with its
                                   state resident in LDS, many steps per
                                   launch; needs body ids (titan_add_masses) */
+#define TITAN_ENGINE_TILED 3   /* per-mass gather over LDS-staged tiles of
+                                  spatially ordered masses, one launch per
+                                  step (falls back to GATHER when a tile's
+                                  neighbourhood does not fit in LDS) */
 
 typedef struct titan_sim titan_sim;
 
@@ -105,7 +109,7 @@ typedef struct titan_info {
     int64_t steps_requested; /* steps asked for by titan_step so far */
     int64_t first_bad_step;  /* first step that produced a non-finite value, or -1 */
     int32_t finalized;       /* nonzero after the first titan_step */
-    int32_t engine;          /* engine in use (TITAN_ENGINE_GATHER/BATCHED) */
+    int32_t engine;          /* engine in use (TITAN_ENGINE_GATHER/TILED/BATCHED) */
     int32_t device;          /* HIP device ordinal */
     int32_t paused;          /* nonzero while held at a pause breakpoint */
     int64_t device_bytes;    /* device memory held by the sim */
@@ -150,7 +154,8 @@ int titan_add_springs(titan_sim *sim, int64_t n, const int64_t *ends_n2, const f
 
 /* Replace the parameters.  Takes effect for steps enqueued after this call
  * (while paused at a breakpoint: from the breakpoint on).  The engine field
- * may change only before the first step. */
+ * may change only before the first step; afterwards it must be
+ * TITAN_ENGINE_AUTO or the engine first asked for. */
 int titan_set_params(titan_sim *sim, const titan_params *p);
 
 /* Build the device representation now (otherwise done by the first

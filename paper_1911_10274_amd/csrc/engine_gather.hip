@@ -38,14 +38,69 @@ static int put(titan_sim *s, const std::vector<T> &h, const T **d)
     return TITAN_OK;
 }
 
-static int build_gather(titan_sim *s)
+// Interleave the low 21 bits of x with two zero bits between each.
+static uint64_t spread3(uint64_t x)
+{
+    x &= 0x1fffffull;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+
+// Internal mass order: Morton (Z-order) of the reference positions quantised
+// to cells of about one short spring length, so that consecutive masses --
+// and therefore each tile -- form compact regions.  Ties keep caller order.
+void plan_order(titan_sim *s)
 {
     const int64_t n = s->n, ns = s->ns;
-    std::vector<int64_t> inv(n);
+    s->perm.resize(n);
+    if (n == 0)
+        return;
+    double lo[3] = {1e300, 1e300, 1e300};
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c)
+            lo[c] = std::min(lo[c], (double)s->h_pos[3 * i + c]);
+    double h = 1.0;
+    if (ns > 0) {
+        std::vector<double> len;
+        const int64_t stride = std::max<int64_t>(1, ns / 65536);
+        for (int64_t q = 0; q < ns; q += stride) {
+            const float *a = &s->h_pos[3 * s->h_ends[2 * q]], *b = &s->h_pos[3 * s->h_ends[2 * q + 1]];
+            const double dx = (double)b[0] - a[0], dy = (double)b[1] - a[1], dz = (double)b[2] - a[2];
+            len.push_back(std::sqrt(dx * dx + dy * dy + dz * dz));
+        }
+        std::nth_element(len.begin(), len.begin() + len.size() / 10, len.end());
+        h = len[len.size() / 10];
+    }
+    std::vector<std::pair<uint64_t, int64_t>> key(n);
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t m = 0;
+        for (int c = 0; c < 3; ++c) {
+            double q = std::floor(((double)s->h_pos[3 * i + c] - lo[c]) / h + 0.5);
+            q = std::min(std::max(q, 0.0), 2097151.0);
+            m |= spread3((uint64_t)q) << c;
+        }
+        key[i] = {m, i};
+    }
+    std::sort(key.begin(), key.end());
+    for (int64_t i = 0; i < n; ++i)
+        s->perm[i] = key[i].second;
+}
+
+static int build_gather(titan_sim *s, bool allow_tiled)
+{
+    const int64_t n = s->n, ns = s->ns;
+    std::vector<int64_t> &inv = s->inv_perm;
+    inv.assign(n, 0);
     for (int64_t i = 0; i < n; ++i)
         inv[s->perm[i]] = i;
 
-    // Incidence rows (internal order), each sorted by (neighbour, spring).
+    // Incidence rows (internal order), each sorted by the neighbour's caller
+    // index (then spring index): the summation order, hence the result, does
+    // not depend on the internal order or on the tiling.
     std::vector<int32_t> deg(n, 0);
     for (int64_t q = 0; q < ns; ++q) {
         ++deg[inv[s->h_ends[2 * q]]];
@@ -55,22 +110,45 @@ static int build_gather(titan_sim *s)
     for (int64_t i = 0; i < n; ++i)
         rp[i + 1] = rp[i] + deg[i];
     struct Inc {
-        int32_t nbr;
+        int32_t nbr_caller;
         int32_t spring;
     };
     std::vector<Inc> inc(rp[n]);
     {
         std::vector<int64_t> fill(rp.begin(), rp.end() - 1);
         for (int64_t q = 0; q < ns; ++q) {
-            const int64_t a = inv[s->h_ends[2 * q]], b = inv[s->h_ends[2 * q + 1]];
-            inc[fill[a]++] = {(int32_t)b, (int32_t)q};
-            inc[fill[b]++] = {(int32_t)a, (int32_t)q};
+            const int64_t a = s->h_ends[2 * q], b = s->h_ends[2 * q + 1];
+            inc[fill[inv[a]]++] = {(int32_t)b, (int32_t)q};
+            inc[fill[inv[b]]++] = {(int32_t)a, (int32_t)q};
         }
     }
     for (int64_t i = 0; i < n; ++i)
         std::sort(inc.begin() + rp[i], inc.begin() + rp[i + 1], [](const Inc &x, const Inc &y) {
-            return x.nbr != y.nbr ? x.nbr < y.nbr : x.spring < y.spring;
+            return x.nbr_caller != y.nbr_caller ? x.nbr_caller < y.nbr_caller : x.spring < y.spring;
         });
+
+    // Tiles and halos.
+    const int64_t nt = (n + kTile - 1) / kTile;
+    std::vector<int64_t> halo_off(nt + 1, 0);
+    std::vector<int32_t> halo_idx;
+    int32_t max_local = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t a = t * kTile, b = std::min(n, a + kTile);
+        std::vector<int32_t> h;
+        for (int64_t i = a; i < b; ++i)
+            for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+                const int64_t j = inv[inc[e].nbr_caller];
+                if (j < a || j >= b)
+                    h.push_back((int32_t)j);
+            }
+        std::sort(h.begin(), h.end());
+        h.erase(std::unique(h.begin(), h.end()), h.end());
+        halo_idx.insert(halo_idx.end(), h.begin(), h.end());
+        halo_off[t + 1] = (int64_t)halo_idx.size();
+        max_local = std::max<int32_t>(max_local, kTile + (int32_t)h.size());
+    }
+    // LDS per tile: 3 float4 per local entry must fit the default 64 KB.
+    const bool tiled = allow_tiled && max_local * 3 * (int64_t)sizeof(float4) <= 65536;
 
     // Per-spring constants (FP64 -> FP32).
     bool act = false, rest = false, damp_uniform = true;
@@ -101,7 +179,7 @@ static int build_gather(titan_sim *s)
         }
     }
 
-    // Sliced ELL.
+    // Sliced ELL (slices of 64 masses; a tile is 4 slices).
     const int64_t nsl = (n + kSlice - 1) / kSlice;
     std::vector<int64_t> off(nsl + 1, 0);
     for (int64_t sl = 0; sl < nsl; ++sl) {
@@ -111,7 +189,12 @@ static int build_gather(titan_sim *s)
         off[sl + 1] = off[sl] + (int64_t)w * kSlice;
     }
     const int64_t slots = off[nsl];
-    std::vector<int32_t> nbr(slots, 0);
+    std::vector<int32_t> nbr;
+    std::vector<uint16_t> nbr_local;
+    if (tiled)
+        nbr_local.assign(slots, 0);
+    else
+        nbr.assign(slots, 0);
     std::vector<float> kk(slots, 0.f), cc, ac, as, d0, L0;
     if (!damp_uniform)
         cc.assign(slots, 0.f);
@@ -125,10 +208,29 @@ static int build_gather(titan_sim *s)
     }
     for (int64_t i = 0; i < n; ++i) {
         const int64_t base = off[i / kSlice] + (i % kSlice);
+        const int64_t t = i / kTile, a = t * kTile;
+        const int32_t *hb = halo_idx.data() + halo_off[t], *he = halo_idx.data() + halo_off[t + 1];
+        // Padding slots (past this mass's degree, up to the slice width) point
+        // the mass at itself with zero constants: zero force.
+        const int64_t width = (off[i / kSlice + 1] - off[i / kSlice]) / kSlice;
+        for (int64_t w = deg[i]; w < width; ++w) {
+            if (tiled)
+                nbr_local[base + w * kSlice] = (uint16_t)(i - a);
+            else
+                nbr[base + w * kSlice] = (int32_t)i;
+        }
         for (int64_t w = 0; w < deg[i]; ++w) {
             const Inc &x = inc[rp[i] + w];
             const int64_t e = base + w * kSlice;
-            nbr[e] = x.nbr;
+            const int64_t j = inv[x.nbr_caller];
+            if (tiled) {
+                if (j >= a && j < a + kTile)
+                    nbr_local[e] = (uint16_t)(j - a);
+                else
+                    nbr_local[e] = (uint16_t)(kTile + (std::lower_bound(hb, he, (int32_t)j) - hb));
+            } else {
+                nbr[e] = (int32_t)j;
+            }
             kk[e] = s->h_k[x.spring];
             if (!damp_uniform)
                 cc[e] = s->h_damp[x.spring];
@@ -147,13 +249,24 @@ static int build_gather(titan_sim *s)
     g = GatherGraph{};
     g.n = n;
     g.n_slices = nsl;
+    g.n_tiles = nt;
+    g.max_local = max_local;
     g.c_uniform = (ns > 0 && damp_uniform) ? s->h_damp[0] : 0.f;
     if (int rc = put(s, off, &g.slice_off))
         return rc;
     if (int rc = put(s, deg, &g.deg))
         return rc;
-    if (int rc = put(s, nbr, &g.nbr))
-        return rc;
+    if (tiled) {
+        if (int rc = put(s, nbr_local, &g.nbr_local))
+            return rc;
+        if (int rc = put(s, halo_off, &g.halo_off))
+            return rc;
+        if (int rc = put(s, halo_idx, &g.halo_idx))
+            return rc;
+    } else {
+        if (int rc = put(s, nbr, &g.nbr))
+            return rc;
+    }
     if (int rc = put(s, kk, &g.k))
         return rc;
     if (!damp_uniform)
@@ -172,6 +285,7 @@ static int build_gather(titan_sim *s)
             return rc;
     }
     g.X0 = s->X0;
+    s->tiled = tiled;
     // keep the staging alive until the copies have run
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     return TITAN_OK;
@@ -179,17 +293,20 @@ static int build_gather(titan_sim *s)
 
 int build_engines(titan_sim *s)
 {
-    if (s->params.engine == TITAN_ENGINE_BATCHED || s->params.engine == TITAN_ENGINE_AUTO) {
+    const int want = s->params.engine;
+    // The gather representation is always built: it serves the plain engines
+    // and the force query of every engine.
+    if (int rc = build_gather(s, want != TITAN_ENGINE_GATHER))
+        return rc;
+    s->engine = s->tiled ? TITAN_ENGINE_TILED : TITAN_ENGINE_GATHER;
+    if (want == TITAN_ENGINE_BATCHED || want == TITAN_ENGINE_AUTO) {
         const int rc = build_batch_engine(s);
-        if (rc == TITAN_OK && s->batch) {
+        if (rc == TITAN_OK && s->batch)
             s->engine = TITAN_ENGINE_BATCHED;
-        } else if (rc != TITAN_OK && s->params.engine == TITAN_ENGINE_BATCHED) {
-            return rc;
-        }
+        else if (want == TITAN_ENGINE_BATCHED)
+            return rc != TITAN_OK ? rc : fail(TITAN_EINVAL, "the batched engine cannot run this system");
     }
-    // The gather representation is always built: it serves the plain engine
-    // and the force query of either engine.
-    return build_gather(s);
+    return TITAN_OK;
 }
 
 static StepConsts consts_for(const titan_sim *s, int64_t step)
@@ -222,7 +339,7 @@ int enqueue_steps(titan_sim *s, int64_t first_step, int64_t count)
         io.V_out = s->V[1 - s->cur];
         io.first_bad = s->first_bad;
         const StepConsts sc = consts_for(s, first_step + q);
-        HIP_TRY(s, launch_gather_step(s->gg, io, sc, false, s->stream));
+        HIP_TRY(s, launch_gather_step(s->gg, io, sc, false, s->tiled, s->stream));
         s->cur = 1 - s->cur;
     }
     return TITAN_OK;
@@ -239,7 +356,7 @@ int compute_forces(titan_sim *s)
     io.F_out = s->F;
     io.first_bad = s->first_bad;
     const StepConsts sc = consts_for(s, s->step_enq);
-    HIP_TRY(s, launch_gather_step(s->gg, io, sc, true, s->stream));
+    HIP_TRY(s, launch_gather_step(s->gg, io, sc, true, s->tiled, s->stream));
     return TITAN_OK;
 }
 

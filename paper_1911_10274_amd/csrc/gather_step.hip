@@ -1,27 +1,86 @@
-// Gather engine: one thread per mass, fused spring force + mass update.
+// Step kernels of the gather engine: one thread per mass, fused spring force
+// + mass update.
 //
 // The paper (Sec. III-B) alternates a spring pass that adds Hooke forces to
 // both ends (atomics by default) with a mass pass that integrates.  Here each
-// mass instead walks its own incidence list in a fixed order and evaluates
-// every incident spring itself, so a spring is evaluated once from each end,
-// no atomics are needed and the per-mass sum order -- hence the result -- is
-// the same on every run.  The two evaluations of one spring are exact
-// negatives of each other (every operand is negated, so every rounding is the
-// same), which keeps Newton's third law pairwise exact.
+// mass walks its own incidence list in a fixed order and evaluates every
+// incident spring itself, so a spring is evaluated once from each end, no
+// atomics are needed and the per-mass sum order -- hence the result -- is the
+// same on every run and in both kernels below.
 //
-// Positions are stored as displacement u = x - x0 next to the read-only
-// reference x0.  The stretch is formed without cancellation,
-//     l - |R| = (2 R.du + du.du) / (l + |R|),   R = x0_j - x0_i, du = u_j - u_i,
-// so that FP32 keeps relative accuracy even when a step moves a mass by less
-// than one ulp of its absolute coordinate.
-#include "titan_internal.h"
+// untiled: neighbours' state is read from global memory (L2).
+// tiled:   a workgroup owns a tile of 256 consecutive masses; it first
+//          stages the tile's state and its halo (the outside masses its
+//          springs reach) in LDS, then every neighbour read is an LDS read
+//          through a 16-bit tile-local index.  Tiles are assigned to
+//          workgroups so that each XCD walks a contiguous range.
+#include "step_device.h"
 
 namespace titan {
 
 namespace {
 
-template <bool ACT, bool DAMPV, bool REST, bool FORCES>
-__global__ __launch_bounds__(256) void gather_step_kernel(GatherGraph g, StateIO io, StepConsts sc)
+template <bool ACT, bool DAMPV, bool REST>
+__device__ __forceinline__ SpringConst load_const(const GatherGraph &g, int64_t e)
+{
+    SpringConst p;
+    p.k = g.k[e];
+    p.c = DAMPV ? g.c[e] : g.c_uniform;
+    p.act_c = ACT ? g.act_c[e] : 0.f;
+    p.act_s = ACT ? g.act_s[e] : 0.f;
+    p.d0 = REST ? g.d0[e] : 0.f;
+    p.L0 = REST ? g.rest[e] : 0.f;
+    return p;
+}
+
+// Sum the spring forces on one mass over its incidence slots
+// [base + w*64 for w < width).  Slots past the mass's own degree are padding
+// that points the mass at itself and contributes nothing.  Loads of kUnroll
+// slots (neighbour index and spring constants) are issued together before
+// any of them is used, so each wave keeps several requests in flight.
+// Nbr(e) loads the neighbour reference of slot e; State(ref, xj, uj, vj)
+// fetches that neighbour's state.
+constexpr int kUnroll = 4;
+
+template <bool ACT, bool DAMP, bool DAMPV, bool REST, class Nbr, class State>
+__device__ __forceinline__ void sum_forces(const GatherGraph &g, int64_t base, int width, const float4 &xi,
+                                           const float4 &ui, const float4 &vi, const StepConsts &sc, Nbr nbr,
+                                           State state, float &fx, float &fy, float &fz)
+{
+    int w = 0;
+    for (; w + kUnroll <= width; w += kUnroll) {
+        int ref[kUnroll];
+        SpringConst p[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t e = base + (int64_t)(w + u) * kSlice;
+            ref[u] = nbr(e);
+            p[u] = load_const<ACT, DAMPV, REST>(g, e);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            float4 xj, uj, vj;
+            state(ref[u], xj, uj, vj);
+            spring_force<ACT, DAMP, REST>(xi, ui, vi, xj, uj, vj, p[u], sc.sin_wt, sc.cos_wt, fx, fy, fz);
+        }
+    }
+    for (; w < width; ++w) {
+        const int64_t e = base + (int64_t)w * kSlice;
+        const int ref = nbr(e);
+        const SpringConst p = load_const<ACT, DAMPV, REST>(g, e);
+        float4 xj, uj, vj;
+        state(ref, xj, uj, vj);
+        spring_force<ACT, DAMP, REST>(xi, ui, vi, xj, uj, vj, p, sc.sin_wt, sc.cos_wt, fx, fy, fz);
+    }
+}
+
+__device__ __forceinline__ int slice_width(const GatherGraph &g, int64_t i)
+{
+    return (int)((g.slice_off[(i >> 6) + 1] - g.slice_off[i >> 6]) >> 6);
+}
+
+template <bool ACT, bool DAMP, bool DAMPV, bool REST, bool FORCES>
+__global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateIO io, StepConsts sc)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n)
@@ -30,117 +89,132 @@ __global__ __launch_bounds__(256) void gather_step_kernel(GatherGraph g, StateIO
     const float4 vi = io.V_in[i];
     const float4 xi = g.X0[i];
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
-    const int deg = g.deg[i];
-
     float fx = 0.f, fy = 0.f, fz = 0.f;
-    for (int w = 0; w < deg; ++w) {
-        const int64_t e = base + (int64_t)w * kSlice;
-        const int j = g.nbr[e];
-        const float4 uj = io.U_in[j];
-        const float4 xj = g.X0[j];
-        const float Rx = xj.x - xi.x, Ry = xj.y - xi.y, Rz = xj.z - xi.z;
-        const float ax = uj.x - ui.x, ay = uj.y - ui.y, az = uj.z - ui.z;
-        const float dx = Rx + ax, dy = Ry + ay, dz = Rz + az;
-        const float l2 = dx * dx + dy * dy + dz * dz;
-        if (l2 == 0.f)
-            continue;  // coincident ends: no direction, no force
-        const float l = sqrtf(l2);
-        const float il = 1.f / l;
-        const float r = sqrtf(Rx * Rx + Ry * Ry + Rz * Rz);
-        const float num = 2.f * (Rx * ax + Ry * ay + Rz * az) + (ax * ax + ay * ay + az * az);
-        float stretch = num / (l + r);
-        if (REST) {
-            const float L0 = g.rest[e];
-            stretch += g.d0[e];
-            if (ACT)
-                stretch -= L0 * (g.act_c[e] * sc.sin_wt + g.act_s[e] * sc.cos_wt);
-        } else if (ACT) {
-            stretch -= r * (g.act_c[e] * sc.sin_wt + g.act_s[e] * sc.cos_wt);
-        }
-        const float ux = dx * il, uy = dy * il, uz = dz * il;
-        float mag = g.k[e] * stretch;
-        const float c = DAMPV ? g.c[e] : g.c_uniform;
-        if (DAMPV || g.c_uniform != 0.f) {
-            const float4 vj = io.V_in[j];
-            const float vr = (vj.x - vi.x) * ux + (vj.y - vi.y) * uy + (vj.z - vi.z) * uz;
-            mag += c * vr;
-        }
-        fx += mag * ux;
-        fy += mag * uy;
-        fz += mag * uz;
-    }
-
+    sum_forces<ACT, DAMP, DAMPV, REST>(
+        g, base, slice_width(g, i), xi, ui, vi, sc, [&](int64_t e) { return g.nbr[e]; },
+        [&](int j, float4 &xj, float4 &uj, float4 &vj) {
+            uj = io.U_in[j];
+            xj = g.X0[j];
+            vj = DAMP ? io.V_in[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        },
+        fx, fy, fz);
     if (FORCES) {
         io.F_out[i] = make_float4(fx, fy, fz, 0.f);
         return;
     }
-
-    const float im = ui.w;  // inverse mass; 0 = pinned
-    if (im == 0.f) {
-        io.U_out[i] = ui;
-        io.V_out[i] = vi;
-        return;
-    }
-    float ax = fx * im + sc.gx;
-    float ay = fy * im + sc.gy;
-    float az = fz * im + sc.gz;
-    const float z = xi.z + ui.z;
-    const bool contact = sc.ground && z < 0.f;
-    float fn = 0.f;
-    if (contact) {
-        fn = -sc.ground_k * z;
-        az += fn * im;
-    }
-    float wx = vi.x + sc.dt * ax;
-    float wy = vi.y + sc.dt * ay;
-    const float wz = vi.z + sc.dt * az;
-    if (contact) {
-        const float vt = sqrtf(wx * wx + wy * wy);
-        if (vt > 0.f) {
-            const float s = fmaxf(0.f, 1.f - sc.mu * fn * sc.dt * im / vt);
-            wx *= s;
-            wy *= s;
-        }
-    }
-    const float4 uo = make_float4(ui.x + sc.dt * wx, ui.y + sc.dt * wy, ui.z + sc.dt * wz, im);
+    float4 uo, vo;
+    const bool ok = integrate_mass(xi, ui, vi, fx, fy, fz, sc, uo, vo);
     io.U_out[i] = uo;
-    io.V_out[i] = make_float4(wx, wy, wz, 0.f);
-    if (!(isfinite(uo.x) && isfinite(uo.y) && isfinite(uo.z) && isfinite(wx) && isfinite(wy) &&
-          isfinite(wz)))
+    io.V_out[i] = vo;
+    if (!ok)
         atomicMin(io.first_bad, (unsigned long long)sc.step);
 }
 
-template <bool ACT, bool DAMPV, bool REST>
-hipError_t launch3(const GatherGraph &g, const StateIO &io, const StepConsts &sc, bool forces,
+template <bool ACT, bool DAMP, bool DAMPV, bool REST, bool FORCES>
+__global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateIO io, StepConsts sc)
+{
+    extern __shared__ float4 smem[];
+    const int L = g.max_local;
+    float4 *sU = smem;
+    float4 *sX = smem + L;
+    float4 *sV = smem + 2 * L;  // only with damping
+
+    const unsigned t = xcd_tile(blockIdx.x, gridDim.x);
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)t * kTile + tid;
+    const bool valid = i < g.n;
+    float4 ui = make_float4(0.f, 0.f, 0.f, 0.f), vi = ui, xi = ui;
+    if (valid) {
+        ui = io.U_in[i];
+        vi = io.V_in[i];
+        xi = g.X0[i];
+        sU[tid] = ui;
+        sX[tid] = xi;
+        if (DAMP)
+            sV[tid] = vi;
+    }
+    const int64_t hb = g.halo_off[t], he = g.halo_off[t + 1];
+    for (int64_t h = hb + tid; h < he; h += kTile) {
+        const int j = g.halo_idx[h];
+        const int q = kTile + (int)(h - hb);
+        sU[q] = io.U_in[j];
+        sX[q] = g.X0[j];
+        if (DAMP)
+            sV[q] = io.V_in[j];
+    }
+    __syncthreads();
+    if (!valid)
+        return;
+
+    const int64_t base = g.slice_off[i >> 6] + (i & 63);
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    sum_forces<ACT, DAMP, DAMPV, REST>(
+        g, base, slice_width(g, i), xi, ui, vi, sc, [&](int64_t e) { return (int)g.nbr_local[e]; },
+        [&](int q, float4 &xj, float4 &uj, float4 &vj) {
+            uj = sU[q];
+            xj = sX[q];
+            vj = DAMP ? sV[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        },
+        fx, fy, fz);
+    if (FORCES) {
+        io.F_out[i] = make_float4(fx, fy, fz, 0.f);
+        return;
+    }
+    float4 uo, vo;
+    const bool ok = integrate_mass(xi, ui, vi, fx, fy, fz, sc, uo, vo);
+    io.U_out[i] = uo;
+    io.V_out[i] = vo;
+    if (!ok)
+        atomicMin(io.first_bad, (unsigned long long)sc.step);
+}
+
+template <bool ACT, bool DAMP, bool DAMPV, bool REST>
+hipError_t launch4(const GatherGraph &g, const StateIO &io, const StepConsts &sc, bool forces, bool tiled,
                    hipStream_t st)
 {
-    const dim3 block(256);
-    const dim3 grid((unsigned)((g.n + 255) / 256));
-    if (forces)
-        hipLaunchKernelGGL((gather_step_kernel<ACT, DAMPV, REST, true>), grid, block, 0, st, g, io, sc);
-    else
-        hipLaunchKernelGGL((gather_step_kernel<ACT, DAMPV, REST, false>), grid, block, 0, st, g, io, sc);
+    if (tiled) {
+        const dim3 grid((unsigned)g.n_tiles), block(kTile);
+        const size_t lds = (size_t)g.max_local * sizeof(float4) * (DAMP ? 3 : 2);
+        if (forces)
+            hipLaunchKernelGGL((tiled_step_kernel<ACT, DAMP, DAMPV, REST, true>), grid, block, lds, st, g, io, sc);
+        else
+            hipLaunchKernelGGL((tiled_step_kernel<ACT, DAMP, DAMPV, REST, false>), grid, block, lds, st, g, io, sc);
+    } else {
+        const dim3 grid((unsigned)((g.n + 255) / 256)), block(256);
+        if (forces)
+            hipLaunchKernelGGL((untiled_step_kernel<ACT, DAMP, DAMPV, REST, true>), grid, block, 0, st, g, io, sc);
+        else
+            hipLaunchKernelGGL((untiled_step_kernel<ACT, DAMP, DAMPV, REST, false>), grid, block, 0, st, g, io, sc);
+    }
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_gather_step(const GatherGraph &g, const StateIO &io, const StepConsts &sc,
-                              bool forces_only, hipStream_t stream)
+hipError_t launch_gather_step(const GatherGraph &g, const StateIO &io, const StepConsts &sc, bool forces_only,
+                              bool tiled, hipStream_t stream)
 {
     if (g.n == 0)
         return hipSuccess;
     const bool act = g.act_c != nullptr, dampv = g.c != nullptr, rest = g.d0 != nullptr;
-    const int key = (act ? 4 : 0) | (dampv ? 2 : 0) | (rest ? 1 : 0);
+    const bool damp = dampv || g.c_uniform != 0.f;
+    tiled = tiled && g.nbr_local != nullptr;
+    // (ACT, DAMP, DAMPV, REST); DAMPV implies DAMP.
+    const int key = (act ? 8 : 0) | (damp ? 4 : 0) | (dampv ? 2 : 0) | (rest ? 1 : 0);
     switch (key) {
-    case 0: return launch3<false, false, false>(g, io, sc, forces_only, stream);
-    case 1: return launch3<false, false, true>(g, io, sc, forces_only, stream);
-    case 2: return launch3<false, true, false>(g, io, sc, forces_only, stream);
-    case 3: return launch3<false, true, true>(g, io, sc, forces_only, stream);
-    case 4: return launch3<true, false, false>(g, io, sc, forces_only, stream);
-    case 5: return launch3<true, false, true>(g, io, sc, forces_only, stream);
-    case 6: return launch3<true, true, false>(g, io, sc, forces_only, stream);
-    default: return launch3<true, true, true>(g, io, sc, forces_only, stream);
+    case 0: return launch4<false, false, false, false>(g, io, sc, forces_only, tiled, stream);
+    case 1: return launch4<false, false, false, true>(g, io, sc, forces_only, tiled, stream);
+    case 4: return launch4<false, true, false, false>(g, io, sc, forces_only, tiled, stream);
+    case 5: return launch4<false, true, false, true>(g, io, sc, forces_only, tiled, stream);
+    case 6: return launch4<false, true, true, false>(g, io, sc, forces_only, tiled, stream);
+    case 7: return launch4<false, true, true, true>(g, io, sc, forces_only, tiled, stream);
+    case 8: return launch4<true, false, false, false>(g, io, sc, forces_only, tiled, stream);
+    case 9: return launch4<true, false, false, true>(g, io, sc, forces_only, tiled, stream);
+    case 12: return launch4<true, true, false, false>(g, io, sc, forces_only, tiled, stream);
+    case 13: return launch4<true, true, false, true>(g, io, sc, forces_only, tiled, stream);
+    case 14: return launch4<true, true, true, false>(g, io, sc, forces_only, tiled, stream);
+    case 15: return launch4<true, true, true, true>(g, io, sc, forces_only, tiled, stream);
+    default: return hipErrorInvalidValue;
     }
 }
 

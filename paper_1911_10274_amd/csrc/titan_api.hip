@@ -125,7 +125,7 @@ static int check_params(const titan_params *p)
         return fail(TITAN_EINVAL, "friction_mu must be finite and >= 0");
     if (!std::isfinite(p->omega))
         return fail(TITAN_EINVAL, "omega must be finite");
-    if (p->engine < TITAN_ENGINE_AUTO || p->engine > TITAN_ENGINE_BATCHED)
+    if (p->engine < TITAN_ENGINE_AUTO || p->engine > TITAN_ENGINE_TILED)
         return fail(TITAN_EINVAL, "unknown engine %d", p->engine);
     return TITAN_OK;
 }
@@ -294,9 +294,11 @@ extern "C" int titan_set_params(titan_sim *s, const titan_params *p)
     std::lock_guard<std::mutex> lk(s->mu);
     if (int rc = check_params(p))
         return rc;
-    if (s->finalized && p->engine != s->params.engine)
+    if (s->finalized && p->engine != s->params.engine && p->engine != TITAN_ENGINE_AUTO)
         return fail(TITAN_ESTATE, "the engine can only be chosen before the first step");
+    const int32_t engine = s->finalized ? s->params.engine : p->engine;
     s->params = *p;
+    s->params.engine = engine;
     return TITAN_OK;
 }
 
@@ -329,11 +331,8 @@ static int finalize_locked(titan_sim *s)
     s->n = n;
     s->ns = (int64_t)s->h_k.size();
 
-    // Reference positions and initial state in internal order.  The internal
-    // order is the caller's order for now (perm = identity).
-    s->perm.resize(n);
-    for (int64_t i = 0; i < n; ++i)
-        s->perm[i] = i;
+    // Reference positions and initial state in internal (spatial) order.
+    plan_order(s);
     std::vector<float4> hX0(n), hU(n), hV(n);
     for (int64_t i = 0; i < n; ++i) {
         const int64_t u = s->perm[i];
@@ -363,11 +362,6 @@ static int finalize_locked(titan_sim *s)
     const unsigned long long none = ~0ull;
     HIP_TRY(s, hipMemcpyAsync(s->first_bad, &none, sizeof none, hipMemcpyHostToDevice, s->stream));
 
-    // Engine selection.
-    int engine = s->params.engine;
-    if (engine == TITAN_ENGINE_AUTO || engine == TITAN_ENGINE_BATCHED)
-        engine = TITAN_ENGINE_GATHER;  // the batched engine is selected by build_engines when eligible
-    s->engine = engine;
     if (int rc = build_engines(s))
         return rc;
     HIP_TRY(s, hipStreamSynchronize(s->stream));

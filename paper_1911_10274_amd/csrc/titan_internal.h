@@ -21,6 +21,9 @@ struct StepConsts {
     int64_t step;          // step index n (for the non-finite report)
 };
 
+// Masses per tile of the tiled kernel (one workgroup, one thread per mass).
+constexpr int kTile = 256;
+
 // Device representation used by the gather engine.  Masses are in internal
 // order; per-incidence arrays are sliced-ELL: the w-th incidence of the mass
 // in lane l of slice s sits at slice_off[s] + w*64 + l.
@@ -30,6 +33,14 @@ struct GatherGraph {
     const int64_t *slice_off;  // [n_slices + 1]
     const int32_t *deg;        // [n] incidences of each mass
     const int32_t *nbr;        // [slots] internal index of the other end
+    // Tiled layout: tile t holds masses [t*kTile, (t+1)*kTile); its halo is
+    // halo_idx[halo_off[t] .. halo_off[t+1]) (internal indices).  Within a
+    // tile, index q < kTile is mass t*kTile + q and kTile + h is halo entry h.
+    const uint16_t *nbr_local;  // [slots] tile-local index of the other end, or null
+    const int64_t *halo_off;    // [n_tiles + 1]
+    const int32_t *halo_idx;
+    int64_t n_tiles;
+    int32_t max_local;          // max over tiles of kTile + halo size
     const float *k;            // [slots] stiffness
     const float *c;            // [slots] damping, or null: c_uniform
     const float *act_c;        // [slots] amp*cos(phase), or null: no actuation
@@ -50,8 +61,10 @@ struct StateIO {
     unsigned long long *first_bad;   // min step index that produced a non-finite value
 };
 
-// Launch one gather step (or, with forces_only, only the spring-force sum).
+// Launch one step (or, with forces_only, only the spring-force sum).  tiled:
+// stage each tile's masses and halo in LDS (needs nbr_local); otherwise every
+// neighbour is read from global memory.
 hipError_t launch_gather_step(const GatherGraph &g, const StateIO &io, const StepConsts &sc,
-                              bool forces_only, hipStream_t stream);
+                              bool forces_only, bool tiled, hipStream_t stream);
 
 }  // namespace titan

@@ -60,6 +60,7 @@ struct titan_sim {
 
     // gather engine
     titan::GatherGraph gg{};
+    bool tiled = false;  // gather engine runs the LDS-tiled kernel
 
     // batched engine (null unless selected)
     titan::BatchEngine *batch = nullptr;
@@ -84,6 +85,7 @@ int dev_alloc(titan_sim *s, size_t bytes, void **out);
 // Engines (engine_gather.hip): build the device representation of the
 // selected engine after the state buffers exist, enqueue steps, compute the
 // spring-force sum, and release engine-private resources.
+void plan_order(titan_sim *s);  // fills perm (internal -> caller)
 int build_engines(titan_sim *s);
 int enqueue_steps(titan_sim *s, int64_t first_step, int64_t count);
 int compute_forces(titan_sim *s);

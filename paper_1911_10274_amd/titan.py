@@ -29,6 +29,7 @@ BP_PAUSE = 1
 ENGINE_AUTO = 0
 ENGINE_GATHER = 1
 ENGINE_BATCHED = 2
+ENGINE_TILED = 3
 
 _ERR_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE", ENONFINITE: "ENONFINITE"}
 
@@ -149,7 +150,7 @@ class Params:
     ground_k: float = 1.0e5
     friction_mu: float = 0.5
     omega: float = 0.0
-    engine: int = ENGINE_GATHER
+    engine: int = ENGINE_AUTO
 
     def _c(self) -> _Params:
         p = _Params()

@@ -13,7 +13,7 @@ def both_params(dt=1e-4, gravity=(0.0, 0.0, -9.81), ground=True, ground_k=1e5, m
     from paper_1911_10274_amd import titan as T
 
     tp = T.Params(dt=dt, gravity=gravity, ground=ground, ground_k=ground_k, friction_mu=mu, omega=omega,
-                  engine=T.ENGINE_GATHER if engine is None else engine)
+                  engine=T.ENGINE_TILED if engine is None else engine)
     op = O.Params(dt=dt, gravity=gravity, ground=ground, ground_k=ground_k, mu=mu, omega=omega)
     return tp, op
 

@@ -16,7 +16,7 @@ def _sim(seed=4, n=12):
     from paper_1911_10274_amd import titan as T
 
     sc = scenes.jittered_actuated_lattice(n=n, seed=seed)
-    tp = T.Params(dt=5e-5, omega=2 * math.pi * 2, engine=T.ENGINE_GATHER)
+    tp = T.Params(dt=5e-5, omega=2 * math.pi * 2, engine=T.ENGINE_TILED)
     return T, T.sim_from_scene(sc, tp), sc
 
 
@@ -114,7 +114,7 @@ def test_runs_on_a_caller_stream_and_torch_memory():
     from paper_1911_10274_amd import titan as T
 
     sc = scenes.jittered_actuated_lattice(n=10, seed=9)
-    tp = T.Params(dt=5e-5, omega=2 * math.pi * 2, engine=T.ENGINE_GATHER)
+    tp = T.Params(dt=5e-5, omega=2 * math.pi * 2, engine=T.ENGINE_TILED)
     before = torch.cuda.memory_allocated()
     s = torch.cuda.Stream()
     a = T.sim_from_scene(sc, tp, stream=s)

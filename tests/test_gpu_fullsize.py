@@ -20,6 +20,8 @@ def test_large_lattice_full_size_10_steps():
     assert sc["ends"].shape[0] == 12731796
     tp, op = both_params(dt=5e-5, omega=2 * math.pi * 2)
     sim = T.sim_from_scene(sc, tp)
+    sim.finalize()
+    assert sim.info()["engine"] == T.ENGINE_TILED  # the benchmark's kernel
     gpu = gpu_series(sim, 10)
     sim.close()
     sysm = O.System(sc)

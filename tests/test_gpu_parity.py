@@ -17,6 +17,13 @@ from tests.parity import TOL, both_params, compare_series, gpu_series, rel
 
 pytestmark = pytest.mark.gpu
 
+ENGINES = {"gather": 1, "tiled": 3}
+
+
+@pytest.fixture(params=sorted(ENGINES))
+def engine(request):
+    return ENGINES[request.param]
+
 
 def _T():
     from paper_1911_10274_amd import titan as T
@@ -44,9 +51,9 @@ def _run_both(scene, tp, op, nsteps=10, rest=None, pre=0, starts=None):
     return gpu, (ref_dX, ref_V, ref_F), sysm
 
 
-def test_cube_drop_10_steps():
+def test_cube_drop_10_steps(engine):
     sc = scenes.cube_drop(10)
-    tp, op = both_params(dt=1e-4)
+    tp, op = both_params(dt=1e-4, engine=engine)
     gpu, ref, sysm = _run_both(sc, tp, op)
     err = compare_series(gpu, ref, sysm.mass)
     print("cube drop", err)
@@ -54,20 +61,20 @@ def test_cube_drop_10_steps():
 
 
 @pytest.mark.parametrize("n", [17, 24])
-def test_actuated_jittered_lattice_10_steps(n):
+def test_actuated_jittered_lattice_10_steps(n, engine):
     # several 64-mass slices and (n = 17) a ragged last slice
     sc = scenes.jittered_actuated_lattice(n=n, seed=2)
-    tp, op = both_params(dt=5e-5, omega=2 * math.pi * 2)
+    tp, op = both_params(dt=5e-5, omega=2 * math.pi * 2, engine=engine)
     gpu, ref, sysm = _run_both(sc, tp, op)
     err = compare_series(gpu, ref, sysm.mass)
     print("actuated lattice", n, err)
     assert max(err.values()) <= TOL
 
 
-def test_actuated_lattice_later_steps():
+def test_actuated_lattice_later_steps(engine):
     # the actuation phase matters: start the window at step 3000 (t = 0.15 s)
     sc = scenes.jittered_actuated_lattice(n=12, seed=7)
-    tp, op = both_params(dt=5e-5, omega=2 * math.pi * 2)
+    tp, op = both_params(dt=5e-5, omega=2 * math.pi * 2, engine=engine)
     gpu, ref, sysm = _run_both(sc, tp, op, nsteps=10, pre=3000)
     err = compare_series(gpu, ref, sysm.mass)
     print("actuated lattice after 3000 steps", err)
@@ -80,10 +87,10 @@ def test_actuated_lattice_later_steps():
     assert err["V"] < 1e-3 and inc_err < 1e-3
 
 
-def test_contact_and_friction_window():
+def test_contact_and_friction_window(engine):
     # cube sliding just above the ground: contact starts near step 143
     sc = scenes.contact_slide()
-    tp, op = both_params(dt=1e-4)
+    tp, op = both_params(dt=1e-4, engine=engine)
     starts = []
     gpu, ref, sysm = _run_both(sc, tp, op, nsteps=20, pre=140, starts=starts)
     err = compare_series(gpu, ref, sysm.mass)
@@ -132,9 +139,9 @@ def _random_graph(seed=5, n=700):
     ), (length * rng.uniform(0.9, 1.1, s)).astype(np.float32)
 
 
-def test_random_graph_explicit_rest_damping_pins_hub():
+def test_random_graph_explicit_rest_damping_pins_hub(engine):
     sc, rest = _random_graph()
-    tp, op = both_params(dt=2e-4, omega=7.0, ground=True, ground_k=1e4, mu=0.3)
+    tp, op = both_params(dt=2e-4, omega=7.0, ground=True, ground_k=1e4, mu=0.3, engine=engine)
     gpu, ref, sysm = _run_both(sc, tp, op, rest=rest)
     err = compare_series(gpu, ref, sysm.mass)
     print("random graph", err)
@@ -163,10 +170,10 @@ def test_single_mass_free_fall_and_empty():
     empty.close()
 
 
-def test_newton_third_law_on_gpu():
+def test_newton_third_law_on_gpu(engine):
     sc = scenes.jittered_actuated_lattice(n=10, seed=3)
     T = _T()
-    tp, _ = both_params(dt=5e-5, omega=2 * math.pi * 2)
+    tp, _ = both_params(dt=5e-5, omega=2 * math.pi * 2, engine=engine)
     sim = T.sim_from_scene(sc, tp)
     sim.step(50)
     f = sim.get_forces().astype(np.float64)
@@ -175,10 +182,10 @@ def test_newton_third_law_on_gpu():
     sim.close()
 
 
-def test_bitwise_deterministic():
+def test_bitwise_deterministic(engine):
     sc = scenes.jittered_actuated_lattice(n=20, seed=4)
     T = _T()
-    tp, _ = both_params(dt=5e-5, omega=2 * math.pi * 2)
+    tp, _ = both_params(dt=5e-5, omega=2 * math.pi * 2, engine=engine)
     outs = []
     for _ in range(2):
         sim = T.sim_from_scene(sc, tp)
@@ -201,3 +208,20 @@ def test_unstable_dt_reports_nonfinite():
     assert ei.value.code == T.ENONFINITE
     assert 0 <= sim.info()["first_bad_step"] < 2000
     sim.close()
+
+
+def test_engines_agree_bitwise():
+    # the per-mass summation order does not depend on the kernel or on the
+    # internal (spatial) order, so both gather kernels give identical bits
+    T = _T()
+    sc = scenes.jittered_actuated_lattice(n=21, seed=8)
+    outs = []
+    for eng in (ENGINES["gather"], ENGINES["tiled"]):
+        tp, _ = both_params(dt=5e-5, omega=2 * math.pi * 2, engine=eng)
+        sim = T.sim_from_scene(sc, tp)
+        sim.step(300)
+        assert sim.info()["engine"] == eng
+        outs.append(sim.get_state(displacement=True) + (sim.get_forces(),))
+        sim.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
