@@ -32,8 +32,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "gather_step_lattice100.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1911_10274_amd", "csrc", f) for f in ("gather_step.hip", "step_device.h")]
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "tiled_step_lattice100.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1911_10274_amd", "csrc", f)
+                  for f in ("gather_step.hip", "step_device.h", "titan_internal.h")]
 
 
 def algorithmic_bytes(n_masses: int, n_springs: int) -> int:

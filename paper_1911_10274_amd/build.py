@@ -36,14 +36,22 @@ def sources() -> list[str]:
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(verbose: bool = False, defines: dict | None = None, out: str | None = None) -> str:
+    """Compile and link.  ``defines`` adds -D macros (e.g. the tiled kernel's
+    TITAN_TILE / TITAN_UNROLL / TITAN_NT_LOADS tuning knobs) and ``out`` puts
+    the library elsewhere; the defaults build the shipped library."""
+    defines = defines or {}
+    tag = "_".join(f"{k}{v}" for k, v in sorted(defines.items()))
+    bdir = os.path.join(BUILD_DIR, tag) if tag else BUILD_DIR
+    os.makedirs(bdir, exist_ok=True)
+    out = out or LIB
     cc = hipcc()
     srcs = sources()
+    dflags = [f"-D{k}={v}" for k, v in sorted(defines.items())]
 
     def compile_one(src):
-        obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-        cmd = [cc, *COMMON, *DEVICE_FLAGS, "-c", src, "-o", obj]
+        obj = os.path.join(bdir, os.path.basename(src) + ".o")
+        cmd = [cc, *COMMON, *DEVICE_FLAGS, *dflags, "-c", src, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -53,13 +61,13 @@ def build(verbose: bool = False) -> str:
 
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(compile_one, srcs))
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

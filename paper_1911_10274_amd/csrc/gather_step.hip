@@ -9,7 +9,7 @@
 // same on every run and in both kernels below.
 //
 // untiled: neighbours' state is read from global memory (L2).
-// tiled:   a workgroup owns a tile of 256 consecutive masses; it first
+// tiled:   a workgroup owns a tile of kTile consecutive masses; it first
 //          stages the tile's state and its halo (the outside masses its
 //          springs reach) in LDS, then every neighbour read is an LDS read
 //          through a 16-bit tile-local index.  Tiles are assigned to
@@ -20,16 +20,28 @@ namespace titan {
 
 namespace {
 
+// Spring constants are read once per step: optionally as non-temporal loads
+// so they do not displace the state arrays from the caches.
+template <class T>
+__device__ __forceinline__ T stream_load(const T *p)
+{
+#if TITAN_NT_LOADS
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
 template <bool ACT, bool DAMPV, bool REST>
 __device__ __forceinline__ SpringConst load_const(const GatherGraph &g, int64_t e)
 {
     SpringConst p;
-    p.k = g.k[e];
-    p.c = DAMPV ? g.c[e] : g.c_uniform;
-    p.act_c = ACT ? g.act_c[e] : 0.f;
-    p.act_s = ACT ? g.act_s[e] : 0.f;
-    p.d0 = REST ? g.d0[e] : 0.f;
-    p.L0 = REST ? g.rest[e] : 0.f;
+    p.k = stream_load(g.k + e);
+    p.c = DAMPV ? stream_load(g.c + e) : g.c_uniform;
+    p.act_c = ACT ? stream_load(g.act_c + e) : 0.f;
+    p.act_s = ACT ? stream_load(g.act_s + e) : 0.f;
+    p.d0 = REST ? stream_load(g.d0 + e) : 0.f;
+    p.L0 = REST ? stream_load(g.rest + e) : 0.f;
     return p;
 }
 
@@ -40,7 +52,7 @@ __device__ __forceinline__ SpringConst load_const(const GatherGraph &g, int64_t 
 // any of them is used, so each wave keeps several requests in flight.
 // Nbr(e) loads the neighbour reference of slot e; State(ref, xj, uj, vj)
 // fetches that neighbour's state.
-constexpr int kUnroll = 4;
+constexpr int kUnroll = TITAN_UNROLL;
 
 template <bool ACT, bool DAMP, bool DAMPV, bool REST, class Nbr, class State>
 __device__ __forceinline__ void sum_forces(const GatherGraph &g, int64_t base, int width, const float4 &xi,
@@ -91,7 +103,7 @@ __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateI
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
     float fx = 0.f, fy = 0.f, fz = 0.f;
     sum_forces<ACT, DAMP, DAMPV, REST>(
-        g, base, slice_width(g, i), xi, ui, vi, sc, [&](int64_t e) { return g.nbr[e]; },
+        g, base, slice_width(g, i), xi, ui, vi, sc, [&](int64_t e) { return stream_load(g.nbr + e); },
         [&](int j, float4 &xj, float4 &uj, float4 &vj) {
             uj = io.U_in[j];
             xj = g.X0[j];
@@ -149,7 +161,7 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
     float fx = 0.f, fy = 0.f, fz = 0.f;
     sum_forces<ACT, DAMP, DAMPV, REST>(
-        g, base, slice_width(g, i), xi, ui, vi, sc, [&](int64_t e) { return (int)g.nbr_local[e]; },
+        g, base, slice_width(g, i), xi, ui, vi, sc, [&](int64_t e) { return (int)stream_load(g.nbr_local + e); },
         [&](int q, float4 &xj, float4 &uj, float4 &vj) {
             uj = sU[q];
             xj = sX[q];

@@ -22,7 +22,19 @@ struct StepConsts {
 };
 
 // Masses per tile of the tiled kernel (one workgroup, one thread per mass).
-constexpr int kTile = 256;
+// Compile-time tuning of the tiled kernel (overridable with -D for tuning
+// builds): tile size, incidence loads issued per batch, and non-temporal
+// loads for the once-per-step streams of spring constants.
+#ifndef TITAN_TILE
+#define TITAN_TILE 512
+#endif
+#ifndef TITAN_UNROLL
+#define TITAN_UNROLL 4
+#endif
+#ifndef TITAN_NT_LOADS
+#define TITAN_NT_LOADS 1
+#endif
+constexpr int kTile = TITAN_TILE;
 
 // Device representation used by the gather engine.  Masses are in internal
 // order; per-incidence arrays are sliced-ELL: the w-th incidence of the mass

@@ -15,7 +15,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtitan.so")
+LIB_PATH = os.environ.get("TITAN_LIBRARY") or os.path.join(_HERE, "libtitan.so")
 
 OK = 0
 EINVAL = -1
