@@ -110,6 +110,86 @@ def copy_calibration(mib: int = 1024, reps: int = 5):
     print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4, "reps": reps}))
 
 
+def _timed_steps(sim, steps, stream):
+    """Milliseconds of ``steps`` steps, HIP events on the sim's stream."""
+    import torch
+
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    sim.step(steps)
+    end.record(stream)
+    end.synchronize()
+    sim.sync()
+    return start.elapsed_time(end)
+
+
+def bench_batched(T, robots_n: int, steps: int, loop_sample: int):
+    """Uneven voxel robots: the batched engine (one launch runs every robot
+    for all steps, each robot group resident in LDS) against the plain tiled
+    engine on the same system and against the plain per-robot loop (each
+    robot its own simulation, one launch per step), the latter timed on a
+    sample of robots at evenly spaced size ranks and scaled to all robots."""
+    import numpy as np
+    import torch
+
+    from paper_1911_10274_amd import scenes
+
+    robots = scenes.robot_batch(robots_n, seed=3, side_lo=3, side_hi=12)
+    sc = scenes.concat(robots)
+    nm, ns = sc["pos"].shape[0], sc["ends"].shape[0]
+    stream = torch.cuda.current_stream()
+    res = {"workload": f"{robots_n} voxel robots, side U{{3..12}}, Bernoulli(0.6) voxels, largest "
+                       f"6-connected component, {steps} steps", "robots": robots_n, "masses": nm,
+           "springs": ns, "steps": steps, "unit": "spring updates/s"}
+
+    def mk(engine):
+        tp = T.Params(dt=1e-4, gravity=(0.0, 0.0, -9.81), ground=True, ground_k=1e5, friction_mu=0.5,
+                      omega=2 * math.pi * 2, engine=engine)
+        sim = T.sim_from_scene(sc, tp)
+        sim.finalize()
+        return sim
+
+    sim = mk(T.ENGINE_BATCHED)
+    info = sim.info()
+    sim.step(20)
+    sim.sync()
+    ms = _timed_steps(sim, steps, stream)
+    sim.close()
+    res.update(value=ns * steps / (ms / 1e3), ms_per_step=ms / steps, engine="batched",
+               workgroup_threads=info["batch_threads"])
+    sim = mk(T.ENGINE_TILED)
+    sim.step(20)
+    sim.sync()
+    ms_plain = _timed_steps(sim, steps, stream)
+    sim.close()
+    res["plain_same_system"] = {"value": ns * steps / (ms_plain / 1e3), "ms_per_step": ms_plain / steps,
+                                "engine": "tiled"}
+
+    order = np.argsort([r["ends"].shape[0] for r in robots], kind="stable")
+    pick = order[np.linspace(0, len(robots) - 1, loop_sample).round().astype(int)]
+    tot_ms, tot_springs = 0.0, 0
+    for b in pick:
+        r = robots[b]
+        tp = T.Params(dt=1e-4, gravity=(0.0, 0.0, -9.81), ground=True, ground_k=1e5, friction_mu=0.5,
+                      omega=2 * math.pi * 2, engine=T.ENGINE_TILED)
+        one = T.sim_from_scene(r, tp)
+        one.finalize()
+        one.step(5)
+        one.sync()
+        tot_ms += _timed_steps(one, steps, stream)
+        tot_springs += r["ends"].shape[0]
+        one.close()
+    loop_ms = tot_ms / len(pick) * len(robots)
+    res["per_robot_loop"] = {"value": ns * steps / (loop_ms / 1e3), "ms_total": loop_ms,
+                             "sample": f"{len(pick)} robots at evenly spaced spring-count ranks, each "
+                                       f"{steps} steps on its own; mean time x {len(robots)} robots",
+                             "extrapolated": True}
+    res["speedup_vs_per_robot_loop"] = loop_ms / ms
+    res["speedup_vs_plain_same_system"] = ms_plain / ms
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +201,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--engine", choices=("tiled", "gather"), default="tiled")
+    ap.add_argument("--robots", type=int, default=4096, help="voxel robots in the batched workload (0: skip)")
+    ap.add_argument("--robot-steps", type=int, default=2000)
+    ap.add_argument("--loop-sample", type=int, default=32)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -202,6 +285,8 @@ def main():
         "cpu_baseline": cpu,
     }
     sim.close()
+    if args.robots > 0:
+        out["batched"] = bench_batched(T, args.robots, args.robot_steps, args.loop_sample)
     print(json.dumps(out))
 
 

@@ -113,6 +113,11 @@ typedef struct titan_info {
     int32_t device;          /* HIP device ordinal */
     int32_t paused;          /* nonzero while held at a pause breakpoint */
     int64_t device_bytes;    /* device memory held by the sim */
+    int32_t batch_threads;   /* workgroup size the tuner chose for the batched
+                                engine (0 if it is not in use) */
+    float tune_batch_ms;     /* tuner's time per step of the batched engine */
+    float tune_gather_ms;    /* tuner's time per step of the gather engine
+                                (measured only under TITAN_ENGINE_AUTO) */
 } titan_info;
 
 /* ABI version this library implements (TITAN_ABI_VERSION). */

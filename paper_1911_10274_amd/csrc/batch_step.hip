@@ -1,0 +1,147 @@
+// Batched engine kernel: one workgroup per group of whole, independent bodies
+// (robots).  The group's state is loaded into LDS once, stepped `nsteps`
+// times with two workgroup barriers per step, and written back once, so the
+// only per-step memory traffic is the spring constants, which stay cached
+// (L2 / Infinity Cache) across the steps of a launch.  The per-mass force sum
+// uses the same incidence order and arithmetic as the gather engines, so the
+// result is bitwise identical to stepping the same system with them.
+#include "step_device.h"
+
+namespace titan {
+
+namespace {
+
+template <bool ACT, bool DAMP, bool DAMPV, bool REST, int T, int MAXM>
+__global__ __launch_bounds__(T) void batch_step_kernel(GatherGraph g, BatchLayout b, StateIO io, StepConsts sc,
+                                                       int nsteps)
+{
+    extern __shared__ float4 smem[];
+    const int cap = b.max_group;
+    float4 *sX = smem;
+    float4 *sU = smem + cap;
+    float4 *sV = smem + 2 * cap;
+    const int64_t m0 = b.mass_off[blockIdx.x];
+    const int nm = (int)(b.mass_off[blockIdx.x + 1] - m0);
+    const int tid = threadIdx.x;
+    for (int q = tid; q < nm; q += T) {
+        sX[q] = g.X0[m0 + q];
+        sU[q] = io.U_in[m0 + q];
+        sV[q] = io.V_in[m0 + q];
+    }
+    __syncthreads();
+
+    for (int s = 0; s < nsteps; ++s) {
+        const float2 tr = ACT ? sc.trig[s] : make_float2(0.f, 1.f);
+        float4 nu[MAXM], nv[MAXM];
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) {
+            const int q = tid + k * T;
+            if (q < nm) {
+                const int64_t i = m0 + q;
+                const float4 xi = sX[q], ui = sU[q], vi = sV[q];
+                const int64_t base = g.slice_off[i >> 6] + (i & 63);
+                float fx = 0.f, fy = 0.f, fz = 0.f;
+                sum_forces<ACT, DAMP, DAMPV, REST, false>(
+                    g, base, slice_width(g, i), xi, ui, vi, tr, [&](int64_t e) { return (int)b.nbr_group[e]; },
+                    [&](int r, float4 &xj, float4 &uj, float4 &vj) {
+                        uj = sU[r];
+                        xj = sX[r];
+                        vj = DAMP ? sV[r] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    },
+                    fx, fy, fz);
+                ok &= integrate_mass(xi, ui, vi, fx, fy, fz, sc, nu[k], nv[k]);
+            }
+        }
+        if (!ok)
+            atomicMin(io.first_bad, (unsigned long long)(sc.step + s));
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) {
+            const int q = tid + k * T;
+            if (q < nm) {
+                sU[q] = nu[k];
+                sV[q] = nv[k];
+            }
+        }
+        __syncthreads();
+    }
+
+    for (int q = tid; q < nm; q += T) {
+        io.U_out[m0 + q] = sU[q];
+        io.V_out[m0 + q] = sV[q];
+    }
+}
+
+template <bool ACT, bool DAMP, bool DAMPV, bool REST, int T, int MAXM>
+hipError_t launch_tm(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc,
+                     int nsteps, hipStream_t st)
+{
+    auto kern = batch_step_kernel<ACT, DAMP, DAMPV, REST, T, MAXM>;
+    const size_t lds = (size_t)b.max_group * 3 * sizeof(float4);
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)b.n_groups), dim3(T), lds, st, g, b, io, sc, nsteps);
+    return hipGetLastError();
+}
+
+template <bool ACT, bool DAMP, bool DAMPV, bool REST, int T>
+hipError_t launch_t(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc, int nsteps,
+                    hipStream_t st)
+{
+    const int per = (b.max_group + T - 1) / T;
+    if (per <= 1)
+        return launch_tm<ACT, DAMP, DAMPV, REST, T, 1>(g, b, io, sc, nsteps, st);
+    if (per <= 2)
+        return launch_tm<ACT, DAMP, DAMPV, REST, T, 2>(g, b, io, sc, nsteps, st);
+    if (per <= 4)
+        return launch_tm<ACT, DAMP, DAMPV, REST, T, 4>(g, b, io, sc, nsteps, st);
+    if (per <= 8)
+        return launch_tm<ACT, DAMP, DAMPV, REST, T, 8>(g, b, io, sc, nsteps, st);
+    return hipErrorInvalidValue;
+}
+
+template <bool ACT, bool DAMP, bool DAMPV, bool REST>
+hipError_t launch4(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc, int nsteps,
+                   int threads, hipStream_t st)
+{
+    switch (threads) {
+    case 256: return launch_t<ACT, DAMP, DAMPV, REST, 256>(g, b, io, sc, nsteps, st);
+    case 512: return launch_t<ACT, DAMP, DAMPV, REST, 512>(g, b, io, sc, nsteps, st);
+    case 1024: return launch_t<ACT, DAMP, DAMPV, REST, 1024>(g, b, io, sc, nsteps, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_batch(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc,
+                        int nsteps, int threads, hipStream_t stream)
+{
+    if (b.n_groups == 0 || nsteps <= 0)
+        return hipSuccess;
+    const bool act = g.act_c != nullptr, dampv = g.c != nullptr, rest = g.d0 != nullptr;
+    const bool damp = dampv || g.c_uniform != 0.f;
+    const int key = (act ? 8 : 0) | (damp ? 4 : 0) | (dampv ? 2 : 0) | (rest ? 1 : 0);
+    switch (key) {
+    case 0: return launch4<false, false, false, false>(g, b, io, sc, nsteps, threads, stream);
+    case 1: return launch4<false, false, false, true>(g, b, io, sc, nsteps, threads, stream);
+    case 4: return launch4<false, true, false, false>(g, b, io, sc, nsteps, threads, stream);
+    case 5: return launch4<false, true, false, true>(g, b, io, sc, nsteps, threads, stream);
+    case 6: return launch4<false, true, true, false>(g, b, io, sc, nsteps, threads, stream);
+    case 7: return launch4<false, true, true, true>(g, b, io, sc, nsteps, threads, stream);
+    case 8: return launch4<true, false, false, false>(g, b, io, sc, nsteps, threads, stream);
+    case 9: return launch4<true, false, false, true>(g, b, io, sc, nsteps, threads, stream);
+    case 12: return launch4<true, true, false, false>(g, b, io, sc, nsteps, threads, stream);
+    case 13: return launch4<true, true, false, true>(g, b, io, sc, nsteps, threads, stream);
+    case 14: return launch4<true, true, true, false>(g, b, io, sc, nsteps, threads, stream);
+    case 15: return launch4<true, true, true, true>(g, b, io, sc, nsteps, threads, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace titan

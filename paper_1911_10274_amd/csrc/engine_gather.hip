@@ -50,7 +50,8 @@ static uint64_t spread3(uint64_t x)
     return x;
 }
 
-// Internal mass order: Morton (Z-order) of the reference positions quantised
+// Internal mass order: bodies contiguous, largest body first (ties by body
+// id); within a body, Morton (Z-order) of the reference positions quantised
 // to cells of about one short spring length, so that consecutive masses --
 // and therefore each tile -- form compact regions.  Ties keep caller order.
 void plan_order(titan_sim *s)
@@ -75,7 +76,34 @@ void plan_order(titan_sim *s)
         std::nth_element(len.begin(), len.begin() + len.size() / 10, len.end());
         h = len[len.size() / 10];
     }
-    std::vector<std::pair<uint64_t, int64_t>> key(n);
+    // body rank: by size, descending
+    int32_t nb = 0;
+    for (int32_t b : s->h_body)
+        nb = std::max(nb, b + 1);
+    std::vector<int64_t> bsize(nb, 0);
+    for (int32_t b : s->h_body)
+        ++bsize[b];
+    std::vector<int32_t> border(nb);
+    for (int32_t b = 0; b < nb; ++b)
+        border[b] = b;
+    std::stable_sort(border.begin(), border.end(), [&](int32_t a, int32_t b) { return bsize[a] > bsize[b]; });
+    std::vector<int32_t> brank(nb);
+    for (int32_t r = 0; r < nb; ++r)
+        brank[border[r]] = r;
+    struct Key {
+        int32_t rank;
+        uint64_t morton;
+        int64_t caller;
+        bool operator<(const Key &o) const
+        {
+            if (rank != o.rank)
+                return rank < o.rank;
+            if (morton != o.morton)
+                return morton < o.morton;
+            return caller < o.caller;
+        }
+    };
+    std::vector<Key> key(n);
     for (int64_t i = 0; i < n; ++i) {
         uint64_t m = 0;
         for (int c = 0; c < 3; ++c) {
@@ -83,11 +111,11 @@ void plan_order(titan_sim *s)
             q = std::min(std::max(q, 0.0), 2097151.0);
             m |= spread3((uint64_t)q) << c;
         }
-        key[i] = {m, i};
+        key[i] = {brank[s->h_body[i]], m, i};
     }
     std::sort(key.begin(), key.end());
     for (int64_t i = 0; i < n; ++i)
-        s->perm[i] = key[i].second;
+        s->perm[i] = key[i].caller;
 }
 
 static int build_gather(titan_sim *s, bool allow_tiled)
@@ -151,11 +179,12 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     const bool tiled = allow_tiled && max_local * 3 * (int64_t)sizeof(float4) <= 65536;
 
     // Per-spring constants (FP64 -> FP32).
-    bool act = false, rest = false, damp_uniform = true;
+    bool act = false, rest = false, damp_uniform = true, k_uniform = true;
     for (int64_t q = 0; q < ns; ++q) {
         act |= s->h_amp[q] != 0.f;
         rest |= s->h_rest[q] > 0.f;
         damp_uniform &= s->h_damp[q] == s->h_damp[0];
+        k_uniform &= s->h_k[q] == s->h_k[0];
     }
     std::vector<float> sC, sS, sD0, sL0;
     if (act) {
@@ -189,13 +218,13 @@ static int build_gather(titan_sim *s, bool allow_tiled)
         off[sl + 1] = off[sl] + (int64_t)w * kSlice;
     }
     const int64_t slots = off[nsl];
-    std::vector<int32_t> nbr;
+    std::vector<int32_t> nbr(slots, 0);  // internal index of the other end, per slot
     std::vector<uint16_t> nbr_local;
     if (tiled)
         nbr_local.assign(slots, 0);
-    else
-        nbr.assign(slots, 0);
-    std::vector<float> kk(slots, 0.f), cc, ac, as, d0, L0;
+    std::vector<float> kk, cc, ac, as, d0, L0;
+    if (!k_uniform)
+        kk.assign(slots, 0.f);
     if (!damp_uniform)
         cc.assign(slots, 0.f);
     if (act) {
@@ -216,8 +245,7 @@ static int build_gather(titan_sim *s, bool allow_tiled)
         for (int64_t w = deg[i]; w < width; ++w) {
             if (tiled)
                 nbr_local[base + w * kSlice] = (uint16_t)(i - a);
-            else
-                nbr[base + w * kSlice] = (int32_t)i;
+            nbr[base + w * kSlice] = (int32_t)i;
         }
         for (int64_t w = 0; w < deg[i]; ++w) {
             const Inc &x = inc[rp[i] + w];
@@ -228,10 +256,10 @@ static int build_gather(titan_sim *s, bool allow_tiled)
                     nbr_local[e] = (uint16_t)(j - a);
                 else
                     nbr_local[e] = (uint16_t)(kTile + (std::lower_bound(hb, he, (int32_t)j) - hb));
-            } else {
-                nbr[e] = (int32_t)j;
             }
-            kk[e] = s->h_k[x.spring];
+            nbr[e] = (int32_t)j;
+            if (!k_uniform)
+                kk[e] = s->h_k[x.spring];
             if (!damp_uniform)
                 cc[e] = s->h_damp[x.spring];
             if (act) {
@@ -252,6 +280,7 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     g.n_tiles = nt;
     g.max_local = max_local;
     g.c_uniform = (ns > 0 && damp_uniform) ? s->h_damp[0] : 0.f;
+    g.k_uniform = (ns > 0 && k_uniform) ? s->h_k[0] : 0.f;
     if (int rc = put(s, off, &g.slice_off))
         return rc;
     if (int rc = put(s, deg, &g.deg))
@@ -267,8 +296,9 @@ static int build_gather(titan_sim *s, bool allow_tiled)
         if (int rc = put(s, nbr, &g.nbr))
             return rc;
     }
-    if (int rc = put(s, kk, &g.k))
-        return rc;
+    if (!k_uniform)
+        if (int rc = put(s, kk, &g.k))
+            return rc;
     if (!damp_uniform)
         if (int rc = put(s, cc, &g.c))
             return rc;
@@ -288,12 +318,15 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     s->tiled = tiled;
     // keep the staging alive until the copies have run
     HIP_TRY(s, hipStreamSynchronize(s->stream));
+    s->h_slot_nbr.swap(nbr);  // for the batched engine's layout
     return TITAN_OK;
 }
 
 int build_engines(titan_sim *s)
 {
     const int want = s->params.engine;
+    if (int rc = dev_alloc(s, sizeof(float2) * (kTrigChunk + 1), (void **)&s->trig))
+        return rc;
     // The gather representation is always built: it serves the plain engines
     // and the force query of every engine.
     if (int rc = build_gather(s, want != TITAN_ENGINE_GATHER))
@@ -305,11 +338,14 @@ int build_engines(titan_sim *s)
             s->engine = TITAN_ENGINE_BATCHED;
         else if (want == TITAN_ENGINE_BATCHED)
             return rc != TITAN_OK ? rc : fail(TITAN_EINVAL, "the batched engine cannot run this system");
+        else if (rc != TITAN_OK)
+            return rc;
     }
+    std::vector<int32_t>().swap(s->h_slot_nbr);
     return TITAN_OK;
 }
 
-static StepConsts consts_for(const titan_sim *s, int64_t step)
+StepConsts consts_for(const titan_sim *s, int64_t step, const float2 *trig)
 {
     StepConsts sc{};
     const titan_params &p = s->params;
@@ -320,9 +356,7 @@ static StepConsts consts_for(const titan_sim *s, int64_t step)
     sc.ground = p.ground ? 1 : 0;
     sc.ground_k = (float)p.ground_k;
     sc.mu = (float)p.friction_mu;
-    const double ph = p.omega * ((double)step * p.dt);
-    sc.sin_wt = (float)std::sin(ph);
-    sc.cos_wt = (float)std::cos(ph);
+    sc.trig = trig;
     sc.step = step;
     return sc;
 }
@@ -331,16 +365,20 @@ int enqueue_steps(titan_sim *s, int64_t first_step, int64_t count)
 {
     if (s->engine == TITAN_ENGINE_BATCHED && s->batch)
         return enqueue_batch_steps(s, first_step, count);
-    for (int64_t q = 0; q < count; ++q) {
-        StateIO io{};
-        io.U_in = s->U[s->cur];
-        io.V_in = s->V[s->cur];
-        io.U_out = s->U[1 - s->cur];
-        io.V_out = s->V[1 - s->cur];
-        io.first_bad = s->first_bad;
-        const StepConsts sc = consts_for(s, first_step + q);
-        HIP_TRY(s, launch_gather_step(s->gg, io, sc, false, s->tiled, s->stream));
-        s->cur = 1 - s->cur;
+    for (int64_t c0 = 0; c0 < count; c0 += kTrigChunk) {
+        const int nc = (int)std::min<int64_t>(kTrigChunk, count - c0);
+        HIP_TRY(s, launch_trig_table(s->trig, first_step + c0, nc, s->params.omega, s->params.dt, s->stream));
+        for (int q = 0; q < nc; ++q) {
+            StateIO io{};
+            io.U_in = s->U[s->cur];
+            io.V_in = s->V[s->cur];
+            io.U_out = s->U[1 - s->cur];
+            io.V_out = s->V[1 - s->cur];
+            io.first_bad = s->first_bad;
+            const StepConsts sc = consts_for(s, first_step + c0 + q, s->trig + q);
+            HIP_TRY(s, launch_gather_step(s->gg, io, sc, false, s->tiled, s->stream));
+            s->cur = 1 - s->cur;
+        }
     }
     return TITAN_OK;
 }
@@ -355,7 +393,9 @@ int compute_forces(titan_sim *s)
     io.V_in = s->V[s->cur];
     io.F_out = s->F;
     io.first_bad = s->first_bad;
-    const StepConsts sc = consts_for(s, s->step_enq);
+    // the clock entry of the current step sits after the chunk table
+    HIP_TRY(s, launch_trig_table(s->trig + kTrigChunk, s->step_enq, 1, s->params.omega, s->params.dt, s->stream));
+    const StepConsts sc = consts_for(s, s->step_enq, s->trig + kTrigChunk);
     HIP_TRY(s, launch_gather_step(s->gg, io, sc, true, s->tiled, s->stream));
     return TITAN_OK;
 }

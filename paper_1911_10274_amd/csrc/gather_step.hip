@@ -20,77 +20,6 @@ namespace titan {
 
 namespace {
 
-// Spring constants are read once per step: optionally as non-temporal loads
-// so they do not displace the state arrays from the caches.
-template <class T>
-__device__ __forceinline__ T stream_load(const T *p)
-{
-#if TITAN_NT_LOADS
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
-}
-
-template <bool ACT, bool DAMPV, bool REST>
-__device__ __forceinline__ SpringConst load_const(const GatherGraph &g, int64_t e)
-{
-    SpringConst p;
-    p.k = stream_load(g.k + e);
-    p.c = DAMPV ? stream_load(g.c + e) : g.c_uniform;
-    p.act_c = ACT ? stream_load(g.act_c + e) : 0.f;
-    p.act_s = ACT ? stream_load(g.act_s + e) : 0.f;
-    p.d0 = REST ? stream_load(g.d0 + e) : 0.f;
-    p.L0 = REST ? stream_load(g.rest + e) : 0.f;
-    return p;
-}
-
-// Sum the spring forces on one mass over its incidence slots
-// [base + w*64 for w < width).  Slots past the mass's own degree are padding
-// that points the mass at itself and contributes nothing.  Loads of kUnroll
-// slots (neighbour index and spring constants) are issued together before
-// any of them is used, so each wave keeps several requests in flight.
-// Nbr(e) loads the neighbour reference of slot e; State(ref, xj, uj, vj)
-// fetches that neighbour's state.
-constexpr int kUnroll = TITAN_UNROLL;
-
-template <bool ACT, bool DAMP, bool DAMPV, bool REST, class Nbr, class State>
-__device__ __forceinline__ void sum_forces(const GatherGraph &g, int64_t base, int width, const float4 &xi,
-                                           const float4 &ui, const float4 &vi, const StepConsts &sc, Nbr nbr,
-                                           State state, float &fx, float &fy, float &fz)
-{
-    int w = 0;
-    for (; w + kUnroll <= width; w += kUnroll) {
-        int ref[kUnroll];
-        SpringConst p[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int64_t e = base + (int64_t)(w + u) * kSlice;
-            ref[u] = nbr(e);
-            p[u] = load_const<ACT, DAMPV, REST>(g, e);
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            float4 xj, uj, vj;
-            state(ref[u], xj, uj, vj);
-            spring_force<ACT, DAMP, REST>(xi, ui, vi, xj, uj, vj, p[u], sc.sin_wt, sc.cos_wt, fx, fy, fz);
-        }
-    }
-    for (; w < width; ++w) {
-        const int64_t e = base + (int64_t)w * kSlice;
-        const int ref = nbr(e);
-        const SpringConst p = load_const<ACT, DAMPV, REST>(g, e);
-        float4 xj, uj, vj;
-        state(ref, xj, uj, vj);
-        spring_force<ACT, DAMP, REST>(xi, ui, vi, xj, uj, vj, p, sc.sin_wt, sc.cos_wt, fx, fy, fz);
-    }
-}
-
-__device__ __forceinline__ int slice_width(const GatherGraph &g, int64_t i)
-{
-    return (int)((g.slice_off[(i >> 6) + 1] - g.slice_off[i >> 6]) >> 6);
-}
-
 template <bool ACT, bool DAMP, bool DAMPV, bool REST, bool FORCES>
 __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateIO io, StepConsts sc)
 {
@@ -102,8 +31,9 @@ __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateI
     const float4 xi = g.X0[i];
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
     float fx = 0.f, fy = 0.f, fz = 0.f;
-    sum_forces<ACT, DAMP, DAMPV, REST>(
-        g, base, slice_width(g, i), xi, ui, vi, sc, [&](int64_t e) { return stream_load(g.nbr + e); },
+    const float2 tr = ACT ? *sc.trig : make_float2(0.f, 1.f);
+    sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0>(
+        g, base, slice_width(g, i), xi, ui, vi, tr, [&](int64_t e) { return stream_load(g.nbr + e); },
         [&](int j, float4 &xj, float4 &uj, float4 &vj) {
             uj = io.U_in[j];
             xj = g.X0[j];
@@ -160,8 +90,9 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
 
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
     float fx = 0.f, fy = 0.f, fz = 0.f;
-    sum_forces<ACT, DAMP, DAMPV, REST>(
-        g, base, slice_width(g, i), xi, ui, vi, sc, [&](int64_t e) { return (int)stream_load(g.nbr_local + e); },
+    const float2 tr = ACT ? *sc.trig : make_float2(0.f, 1.f);
+    sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0>(
+        g, base, slice_width(g, i), xi, ui, vi, tr, [&](int64_t e) { return (int)stream_load(g.nbr_local + e); },
         [&](int q, float4 &xj, float4 &uj, float4 &vj) {
             uj = sU[q];
             xj = sX[q];
@@ -201,7 +132,25 @@ hipError_t launch4(const GatherGraph &g, const StateIO &io, const StepConsts &sc
     return hipGetLastError();
 }
 
+__global__ void trig_table_kernel(float2 *trig, int64_t first, int count, double omega, double dt)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= count)
+        return;
+    const double ph = omega * ((double)(first + s) * dt);
+    trig[s] = make_float2((float)sin(ph), (float)cos(ph));
+}
+
 }  // namespace
+
+hipError_t launch_trig_table(float2 *trig, int64_t first, int count, double omega, double dt, hipStream_t stream)
+{
+    if (count <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(trig_table_kernel, dim3((count + 255) / 256), dim3(256), 0, stream, trig, first, count, omega,
+                       dt);
+    return hipGetLastError();
+}
 
 hipError_t launch_gather_step(const GatherGraph &g, const StateIO &io, const StepConsts &sc, bool forces_only,
                               bool tiled, hipStream_t stream)

@@ -33,6 +33,12 @@ struct SpringConst {
     float L0;     // rest length (only with explicit rest lengths)
 };
 
+// Every floating-point operation below is spelled out: contraction of
+// multiplies and adds into FMAs is switched off and the FMAs that are wanted
+// are written as fmaf.  The rounding of each operation is therefore fixed by
+// this source, not by how the compiler schedules a particular kernel, and all
+// engines that step the system give identical bits.
+
 // Force on mass i from one incident spring (xi, ui, vi: mass i; xj, uj, vj:
 // the other end).  Evaluating the same spring from its other end gives the
 // exact negative: every operand is negated, so every rounding is the same.
@@ -42,72 +48,157 @@ __device__ __forceinline__ void spring_force(const float4 &xi, const float4 &ui,
                                              const SpringConst &p, float sin_wt, float cos_wt,
                                              float &fx, float &fy, float &fz)
 {
+#pragma clang fp contract(off)
     const float Rx = xj.x - xi.x, Ry = xj.y - xi.y, Rz = xj.z - xi.z;
     const float ax = uj.x - ui.x, ay = uj.y - ui.y, az = uj.z - ui.z;
     const float dx = Rx + ax, dy = Ry + ay, dz = Rz + az;
-    const float l2 = dx * dx + dy * dy + dz * dz;
+    const float l2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     // Coincident ends (also the padding slots, which point a mass at itself)
     // have no direction and exert no force: select zeros, no branch, so the
     // loads of the next incidences need not wait for this test.
     const bool ok = l2 > 0.f;
     const float il = ok ? __builtin_amdgcn_rsqf(l2) : 0.f;  // 1/l (1 ulp)
     const float l = l2 * il;
-    const float R2 = Rx * Rx + Ry * Ry + Rz * Rz;
+    const float R2 = fmaf(Rx, Rx, fmaf(Ry, Ry, Rz * Rz));
     const float r = R2 > 0.f ? R2 * __builtin_amdgcn_rsqf(R2) : 0.f;  // |R|
-    const float num = 2.f * (Rx * ax + Ry * ay + Rz * az) + (ax * ax + ay * ay + az * az);
+    const float Rda = fmaf(Rx, ax, fmaf(Ry, ay, Rz * az));
+    const float ada = fmaf(ax, ax, fmaf(ay, ay, az * az));
+    const float num = fmaf(2.f, Rda, ada);  // 2 R.du + du.du = l^2 - |R|^2
     float stretch = ok ? num * __builtin_amdgcn_rcpf(l + r) : 0.f;
     if (REST) {
         stretch += p.d0;
         if (ACT)
-            stretch -= p.L0 * (p.act_c * sin_wt + p.act_s * cos_wt);
+            stretch = fmaf(-p.L0, fmaf(p.act_c, sin_wt, p.act_s * cos_wt), stretch);
     } else if (ACT) {
-        stretch -= r * (p.act_c * sin_wt + p.act_s * cos_wt);
+        stretch = fmaf(-r, fmaf(p.act_c, sin_wt, p.act_s * cos_wt), stretch);
     }
     const float ux = dx * il, uy = dy * il, uz = dz * il;
     float mag = p.k * stretch;
     if (DAMP) {
-        const float vr = (vj.x - vi.x) * ux + (vj.y - vi.y) * uy + (vj.z - vi.z) * uz;
-        mag += p.c * vr;
+        const float vr = fmaf(vj.x - vi.x, ux, fmaf(vj.y - vi.y, uy, (vj.z - vi.z) * uz));
+        mag = fmaf(p.c, vr, mag);
     }
-    fx += mag * ux;
-    fy += mag * uy;
-    fz += mag * uz;
+    fx = fmaf(mag, ux, fx);
+    fy = fmaf(mag, uy, fy);
+    fz = fmaf(mag, uz, fz);
 }
 
 // Mass update.  Returns false if the new state is not finite.
 __device__ __forceinline__ bool integrate_mass(const float4 &xi, const float4 &ui, const float4 &vi, float fx,
                                                float fy, float fz, const StepConsts &sc, float4 &uo, float4 &vo)
 {
+#pragma clang fp contract(off)
     const float im = ui.w;  // inverse mass; 0 = pinned
     if (im == 0.f) {
         uo = ui;
         vo = vi;
         return true;
     }
-    float ax = fx * im + sc.gx;
-    float ay = fy * im + sc.gy;
-    float az = fz * im + sc.gz;
+    float ax = fmaf(fx, im, sc.gx);
+    float ay = fmaf(fy, im, sc.gy);
+    float az = fmaf(fz, im, sc.gz);
     const float z = xi.z + ui.z;
     const bool contact = sc.ground && z < 0.f;
     float fn = 0.f;
     if (contact) {
         fn = -sc.ground_k * z;
-        az += fn * im;
+        az = fmaf(fn, im, az);
     }
-    float wx = vi.x + sc.dt * ax;
-    float wy = vi.y + sc.dt * ay;
-    const float wz = vi.z + sc.dt * az;
+    float wx = fmaf(sc.dt, ax, vi.x);
+    float wy = fmaf(sc.dt, ay, vi.y);
+    const float wz = fmaf(sc.dt, az, vi.z);
     if (contact) {
-        const float vt = sqrtf(wx * wx + wy * wy);
+        const float vt = sqrtf(fmaf(wx, wx, wy * wy));
         if (vt > 0.f) {
             const float s = fmaxf(0.f, 1.f - sc.mu * fn * sc.dt * im / vt);
             wx *= s;
             wy *= s;
         }
     }
-    uo = make_float4(ui.x + sc.dt * wx, ui.y + sc.dt * wy, ui.z + sc.dt * wz, im);
+    uo = make_float4(fmaf(sc.dt, wx, ui.x), fmaf(sc.dt, wy, ui.y), fmaf(sc.dt, wz, ui.z), im);
     vo = make_float4(wx, wy, wz, 0.f);
     return isfinite(uo.x) && isfinite(uo.y) && isfinite(uo.z) && isfinite(wx) && isfinite(wy) && isfinite(wz);
+}
+
+// Spring constants are read once per step: optionally as non-temporal loads
+// so they do not displace the state arrays from the caches.
+template <class T>
+__device__ __forceinline__ T stream_load(const T *p)
+{
+#if TITAN_NT_LOADS
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+template <bool NT, class T>
+__device__ __forceinline__ T const_load(const T *p)
+{
+    if (NT)
+        return stream_load(p);
+    return *p;
+}
+
+// NT: the constants are streamed once per launch (gather engines); the
+// batched engine reads them every step of a launch and keeps them cached.
+template <bool ACT, bool DAMPV, bool REST, bool NT>
+__device__ __forceinline__ SpringConst load_const(const GatherGraph &g, int64_t e)
+{
+    SpringConst p;
+    p.k = g.k ? const_load<NT>(g.k + e) : g.k_uniform;
+    p.c = DAMPV ? const_load<NT>(g.c + e) : g.c_uniform;
+    p.act_c = ACT ? const_load<NT>(g.act_c + e) : 0.f;
+    p.act_s = ACT ? const_load<NT>(g.act_s + e) : 0.f;
+    p.d0 = REST ? const_load<NT>(g.d0 + e) : 0.f;
+    p.L0 = REST ? const_load<NT>(g.rest + e) : 0.f;
+    return p;
+}
+
+// Sum the spring forces on one mass over its incidence slots
+// [base + w*64 for w < width).  Slots past the mass's own degree are padding
+// that points the mass at itself and contributes nothing.  Loads of kUnroll
+// slots (neighbour index and spring constants) are issued together before
+// any of them is used, so each wave keeps several requests in flight.
+// Nbr(e) loads the neighbour reference of slot e; State(ref, xj, uj, vj)
+// fetches that neighbour's state.
+constexpr int kUnroll = TITAN_UNROLL;
+
+template <bool ACT, bool DAMP, bool DAMPV, bool REST, bool NT, class Nbr, class State>
+__device__ __forceinline__ void sum_forces(const GatherGraph &g, int64_t base, int width, const float4 &xi,
+                                           const float4 &ui, const float4 &vi, float2 tr, Nbr nbr,
+                                           State state, float &fx, float &fy, float &fz)
+{
+    int w = 0;
+    for (; w + kUnroll <= width; w += kUnroll) {
+        int ref[kUnroll];
+        SpringConst p[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t e = base + (int64_t)(w + u) * kSlice;
+            ref[u] = nbr(e);
+            p[u] = load_const<ACT, DAMPV, REST, NT>(g, e);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            float4 xj, uj, vj;
+            state(ref[u], xj, uj, vj);
+            spring_force<ACT, DAMP, REST>(xi, ui, vi, xj, uj, vj, p[u], tr.x, tr.y, fx, fy, fz);
+        }
+    }
+    for (; w < width; ++w) {
+        const int64_t e = base + (int64_t)w * kSlice;
+        const int ref = nbr(e);
+        const SpringConst p = load_const<ACT, DAMPV, REST, NT>(g, e);
+        float4 xj, uj, vj;
+        state(ref, xj, uj, vj);
+        spring_force<ACT, DAMP, REST>(xi, ui, vi, xj, uj, vj, p, tr.x, tr.y, fx, fy, fz);
+    }
+}
+
+__device__ __forceinline__ int slice_width(const GatherGraph &g, int64_t i)
+{
+    return (int)((g.slice_off[(i >> 6) + 1] - g.slice_off[i >> 6]) >> 6);
 }
 
 // Workgroup -> tile mapping that gives each XCD a contiguous range of tiles:

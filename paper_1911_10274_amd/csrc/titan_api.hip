@@ -75,20 +75,36 @@ int titan::dev_alloc(titan_sim *s, size_t bytes, void **out)
                         "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
         }
     }
-    s->allocations.push_back(p);
+    s->allocations.push_back({p, bytes});
     s->device_bytes += (int64_t)bytes;
     *out = p;
     return TITAN_OK;
 }
 
+static void release(titan_sim *s, void *p)
+{
+    if (s->alloc.release)
+        s->alloc.release(p, s->alloc.ctx);
+    else
+        (void)hipFree(p);
+}
+
+void titan::dev_free(titan_sim *s, void *p)
+{
+    for (size_t q = 0; q < s->allocations.size(); ++q)
+        if (s->allocations[q].first == p) {
+            (void)hipStreamSynchronize(s->stream);
+            release(s, p);
+            s->device_bytes -= (int64_t)s->allocations[q].second;
+            s->allocations.erase(s->allocations.begin() + q);
+            return;
+        }
+}
+
 static void dev_free_all(titan_sim *s)
 {
-    for (void *p : s->allocations) {
-        if (s->alloc.release)
-            s->alloc.release(p, s->alloc.ctx);
-        else
-            (void)hipFree(p);
-    }
+    for (auto &a : s->allocations)
+        release(s, a.first);
     s->allocations.clear();
     s->device_bytes = 0;
 }
@@ -719,5 +735,8 @@ extern "C" int titan_get_info(titan_sim *s, titan_info *info)
     info->device = s->device;
     info->paused = s->paused;
     info->device_bytes = s->device_bytes;
+    info->batch_threads = batch_threads(s);
+    info->tune_batch_ms = s->tune_batch_ms;
+    info->tune_gather_ms = s->tune_gather_ms;
     return TITAN_OK;
 }

@@ -10,16 +10,25 @@ namespace titan {
 // Width of a sliced-ELL slice: one wavefront of masses.
 constexpr int kSlice = 64;
 
-// Per-step scalars of the gather engine.
+// Per-step scalars.  The actuation clock (sin, cos)(omega * t_n),
+// t_n = n * dt, is read from a device table filled in FP64 by
+// launch_trig_table, so every engine uses the same FP32 values.
 struct StepConsts {
     float dt;
     float gx, gy, gz;
     float ground_k;
     float mu;
-    float sin_wt, cos_wt;  // sin/cos(omega * t_n), t_n = n * dt, rounded from FP64
     int32_t ground;
-    int64_t step;          // step index n (for the non-finite report)
+    const float2 *trig;  // entry of this step (gather engines) or of the chunk's first step (batched)
+    int64_t step;        // step index n (for the non-finite report)
 };
+
+// Largest number of steps whose clock entries one table holds.
+constexpr int kTrigChunk = 4096;
+
+// trig[s] = (sin, cos)(omega * (first + s) * dt) for s < count (FP64, rounded).
+hipError_t launch_trig_table(float2 *trig, int64_t first, int count, double omega, double dt,
+                             hipStream_t stream);
 
 // Masses per tile of the tiled kernel (one workgroup, one thread per mass).
 // Compile-time tuning of the tiled kernel (overridable with -D for tuning
@@ -53,7 +62,7 @@ struct GatherGraph {
     const int32_t *halo_idx;
     int64_t n_tiles;
     int32_t max_local;          // max over tiles of kTile + halo size
-    const float *k;            // [slots] stiffness
+    const float *k;            // [slots] stiffness, or null: k_uniform
     const float *c;            // [slots] damping, or null: c_uniform
     const float *act_c;        // [slots] amp*cos(phase), or null: no actuation
     const float *act_s;        // [slots] amp*sin(phase)
@@ -61,6 +70,7 @@ struct GatherGraph {
     const float *rest;         // [slots] rest length (with d0)
     const float4 *X0;          // [n] reference positions (w unused)
     float c_uniform;
+    float k_uniform;
 };
 
 // State buffers: U = (x - x0, inverse mass), V = (v, 0).
@@ -72,6 +82,26 @@ struct StateIO {
     float4 *F_out;                   // forces-only mode: summed spring force
     unsigned long long *first_bad;   // min step index that produced a non-finite value
 };
+
+// Batched engine: independent groups of whole bodies, each stepped by one
+// workgroup with its state resident in LDS.  Group q owns internal masses
+// [mass_off[q], mass_off[q+1]); nbr_group holds, per incidence slot of the
+// gather layout, the neighbour's index relative to its group's first mass.
+struct BatchLayout {
+    int64_t n_groups;
+    const int64_t *mass_off;     // [n_groups + 1]
+    const uint16_t *nbr_group;   // [slots]
+    int32_t max_group;           // masses of the largest group
+};
+
+// Threads per workgroup of the batched kernel (variants the tuner picks from).
+constexpr int kBatchThreadChoices[] = {256, 512, 1024};
+
+// Run `nsteps` steps (step indices step0 ..) of every group in one launch:
+// state is read from io.U_in/V_in, kept in LDS, written to io.U_out/V_out.
+// sc.trig points at the clock entry of step0.
+hipError_t launch_batch(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc,
+                        int nsteps, int threads, hipStream_t stream);
 
 // Launch one step (or, with forces_only, only the spring-force sum).  tiled:
 // stage each tile's masses and halo in LDS (needs nbr_local); otherwise every

@@ -44,7 +44,7 @@ struct titan_sim {
     bool dev_error = false;
     int device = 0;
     int engine = TITAN_ENGINE_GATHER;
-    std::vector<void *> allocations;
+    std::vector<std::pair<void *, size_t>> allocations;
     int64_t device_bytes = 0;
     int64_t n = 0, ns = 0;
     std::vector<int64_t> perm;      // perm[internal] = caller index
@@ -61,9 +61,13 @@ struct titan_sim {
     // gather engine
     titan::GatherGraph gg{};
     bool tiled = false;  // gather engine runs the LDS-tiled kernel
+    std::vector<int32_t> h_slot_nbr;  // per-slot neighbour (internal), kept only during finalize
+    float2 *trig = nullptr;           // clock table: kTrigChunk entries + 1 for force queries
 
-    // batched engine (null unless selected)
+    // batched engine (null unless selected) and the tuner's measurements
     titan::BatchEngine *batch = nullptr;
+    float tune_batch_ms = 0.f;   // per step, best batched workgroup size
+    float tune_gather_ms = 0.f;  // per step, gather engine (AUTO only)
 
     // step queue and breakpoints
     int64_t step_enq = 0;
@@ -81,6 +85,8 @@ namespace titan {
 int fail(int code, const char *fmt, ...);
 int hip_fail(titan_sim *sim, hipError_t e, const char *what);
 int dev_alloc(titan_sim *s, size_t bytes, void **out);
+void dev_free(titan_sim *s, void *p);
+int batch_threads(const titan_sim *s);
 
 // Engines (engine_gather.hip): build the device representation of the
 // selected engine after the state buffers exist, enqueue steps, compute the
@@ -89,6 +95,7 @@ void plan_order(titan_sim *s);  // fills perm (internal -> caller)
 int build_engines(titan_sim *s);
 int enqueue_steps(titan_sim *s, int64_t first_step, int64_t count);
 int compute_forces(titan_sim *s);
+StepConsts consts_for(const titan_sim *s, int64_t step, const float2 *trig);
 void destroy_engines(titan_sim *s);
 
 }  // namespace titan

@@ -73,6 +73,9 @@ class _Info(ctypes.Structure):
         ("device", ctypes.c_int32),
         ("paused", ctypes.c_int32),
         ("device_bytes", ctypes.c_int64),
+        ("batch_threads", ctypes.c_int32),
+        ("tune_batch_ms", ctypes.c_float),
+        ("tune_gather_ms", ctypes.c_float),
     ]
 
 
