@@ -62,6 +62,16 @@ def _load():
         lib.orc_run.argtypes = [ctypes.c_int64, _dp, ctypes.c_int64, _lp, _dp, _dp, _dp, _dp, _dp,
                                 ctypes.POINTER(_Params), ctypes.c_int64, ctypes.c_int64, _dp, _dp, _dp]
         lib.orc_run.restype = ctypes.c_int
+        _i32p = ctypes.POINTER(ctypes.c_int32)
+        _u64p = ctypes.POINTER(ctypes.c_uint64)
+        lib.orc_rollout_loss.argtypes = [ctypes.c_int64, _dp, ctypes.c_int64, _lp, _dp, _dp, _dp, _dp, _dp,
+                                         ctypes.POINTER(_Params), _i32p, ctypes.c_int32, ctypes.c_int64, _dp, _dp,
+                                         _dp, _u64p]
+        lib.orc_rollout_loss.restype = ctypes.c_int
+        lib.orc_rollout_grad.argtypes = [ctypes.c_int64, _dp, ctypes.c_int64, _lp, _dp, _dp, _dp, _dp, _dp,
+                                         ctypes.POINTER(_Params), _i32p, ctypes.c_int32, _dp, ctypes.c_int64, _dp,
+                                         _dp, _dp, _dp, _dp, _dp, _u64p]
+        lib.orc_rollout_grad.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -163,6 +173,44 @@ class System:
             F[s] = f
         return dX, V, F
 
+    # ---- rollout loss and its adjoint ---------------------------------------------
+
+    def _body(self, body):
+        b = np.zeros(self.n, np.int32) if body is None else np.ascontiguousarray(body, dtype=np.int32)
+        return b, int(b.max()) + 1 if b.size else 1
+
+    def rollout_loss(self, params: Params, nsteps: int, body=None):
+        """Per-body J_b = -(CoM_x after nsteps - CoM_x at start), and a hash of
+        every contact / friction-stick decision of the run."""
+        b, nb = self._body(body)
+        loss = np.empty(nb, np.float64)
+        sig = ctypes.c_uint64()
+        rc = _load().orc_rollout_loss(self.n, _ptr(self.mass), self.ns, _ptr(self.ends, _lp), _ptr(self.k),
+                                      _ptr(self.c), _ptr(self.rest), _ptr(self.amp), _ptr(self.phase),
+                                      ctypes.byref(params._c()), b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      nb, nsteps, _ptr(self.x0), _ptr(self.v0), _ptr(loss), ctypes.byref(sig))
+        if rc != 0:
+            raise MemoryError("oracle rollout failed")
+        return loss, sig.value
+
+    def rollout_grad(self, params: Params, nsteps: int, body=None, weights=None):
+        """Adjoint of J = sum_b w_b J_b: per-spring dJ/dk, dJ/dC, dJ/dS with
+        C = amp cos(phase), S = amp sin(phase).  Returns a dict with loss,
+        gk, gC, gS and the decision hash."""
+        b, nb = self._body(body)
+        w = np.ones(nb) if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+        loss = np.empty(nb, np.float64)
+        gk, gC, gS = (np.empty(self.ns, np.float64) for _ in range(3))
+        sig = ctypes.c_uint64()
+        rc = _load().orc_rollout_grad(self.n, _ptr(self.mass), self.ns, _ptr(self.ends, _lp), _ptr(self.k),
+                                      _ptr(self.c), _ptr(self.rest), _ptr(self.amp), _ptr(self.phase),
+                                      ctypes.byref(params._c()), b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      nb, _ptr(w), nsteps, _ptr(self.x0), _ptr(self.v0), _ptr(loss), _ptr(gk),
+                                      _ptr(gC), _ptr(gS), ctypes.byref(sig))
+        if rc != 0:
+            raise MemoryError("oracle rollout failed")
+        return dict(loss=loss, gk=gk, gC=gC, gS=gS, sig=sig.value)
+
     # ---- observables (plain sums) -------------------------------------------------
 
     def spring_stretch(self, x, t=0.0, omega=0.0):
@@ -200,3 +248,22 @@ class System:
     def com(self, x):
         x = _d(x).reshape(-1, 3)
         return np.sum(self.mass[:, None] * x, axis=0) / np.sum(self.mass)
+
+
+def voxel_grads(gC, gS, voxel_a, voxel_phi, sv_ptr, sv_idx):
+    """Chain rule from per-spring actuation-phasor gradients to per-voxel
+    amplitude and phase gradients.  A spring's phasor is the mean of its
+    voxels' a*(cos phi, sin phi), so with n_s voxels on spring s:
+    dJ/da_v   = sum_s (gC_s cos phi_v + gS_s sin phi_v) / n_s,
+    dJ/dphi_v = sum_s a_v (-gC_s sin phi_v + gS_s cos phi_v) / n_s."""
+    va = np.asarray(voxel_a, np.float64)
+    vp = np.asarray(voxel_phi, np.float64)
+    ga = np.zeros(va.size)
+    gp = np.zeros(va.size)
+    for s in range(len(sv_ptr) - 1):
+        vs = sv_idx[sv_ptr[s]:sv_ptr[s + 1]]
+        ns_ = len(vs)
+        for v in vs:
+            ga[v] += (gC[s] * np.cos(vp[v]) + gS[s] * np.sin(vp[v])) / ns_
+            gp[v] += va[v] * (-gC[s] * np.sin(vp[v]) + gS[s] * np.cos(vp[v])) / ns_
+    return ga, gp

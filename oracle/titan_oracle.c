@@ -146,3 +146,287 @@ int orc_run(int64_t n, const double *mass, int64_t ns, const int64_t *ends,
     free(f);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Reverse-mode gradient of a rollout (the adjoint of the step above).
+ *
+ * Loss: J = sum_b w_b * J_b,  J_b = -(CoM_x(x_N) - CoM_x(x_0)) over the masses
+ * of body b (mass-weighted; pinned masses weigh nothing).
+ * Gradients w.r.t. every spring's k and actuation phasor (C, S), where
+ * C = amp cos(phase), S = amp sin(phase), so that the rest length at time t
+ * is rest * (1 + C sin(omega t) + S cos(omega t)) -- the same function as
+ * rest * (1 + amp sin(omega t + phase)).
+ *
+ * The forward trajectory is stored whole (nsteps + 1 states) and the step is
+ * differentiated backwards in the order it was computed: position update,
+ * friction, velocity update, forces.  `sig` (optional) receives a hash of
+ * every contact and friction-stick decision of the run, so that a
+ * finite-difference check can discard perturbations that change them.
+ * Returns 0, or -2 when memory runs out.
+ * ------------------------------------------------------------------------ */
+
+static uint64_t fnv(uint64_t h, uint64_t v)
+{
+    for (int b = 0; b < 8; ++b) {
+        h ^= (v >> (8 * b)) & 0xff;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+/* One forward step that also records the contact/stick decisions in *sig. */
+static void step_sig(int64_t n, const double *mass, int64_t ns, const int64_t *ends, const double *k,
+                     const double *c, const double *rest, const double *amp, const double *phase,
+                     const orc_params *p, int64_t step, double *f, double *x, double *v, uint64_t *sig)
+{
+    const double dt = p->dt;
+    orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, (double)step * dt, x, v, f);
+    for (int64_t i = 0; i < n; ++i) {
+        double m = mass[i];
+        if (m == 0.0)
+            continue;
+        double F[3];
+        for (int q = 0; q < 3; ++q)
+            F[q] = f[3 * i + q] + m * p->g[q];
+        double z = x[3 * i + 2];
+        int contact = p->ground && z < 0.0;
+        double Fn = 0.0;
+        if (contact) {
+            Fn = -p->ground_k * z;
+            F[2] += Fn;
+        }
+        double w[3];
+        for (int q = 0; q < 3; ++q)
+            w[q] = v[3 * i + q] + dt * F[q] / m;
+        int stick = 0;
+        if (contact) {
+            double vt = sqrt(w[0] * w[0] + w[1] * w[1]);
+            if (vt > 0.0) {
+                double scale = 1.0 - p->mu * Fn * dt / (m * vt);
+                if (scale < 0.0) {
+                    scale = 0.0;
+                    stick = 1;
+                }
+                w[0] *= scale;
+                w[1] *= scale;
+            }
+        }
+        if (sig && (contact || stick))
+            *sig = fnv(fnv(*sig, (uint64_t)step * 0x9e3779b97f4a7c15ull + (uint64_t)i), (uint64_t)(contact + 2 * stick));
+        for (int q = 0; q < 3; ++q) {
+            v[3 * i + q] = w[q];
+            x[3 * i + q] += dt * w[q];
+        }
+    }
+}
+
+static void com_x(int64_t n, const double *mass, const int32_t *body, int32_t nbody, const double *x,
+                  double *com, double *mtot)
+{
+    for (int32_t b = 0; b < nbody; ++b) {
+        com[b] = 0.0;
+        mtot[b] = 0.0;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        com[body[i]] += mass[i] * x[3 * i];
+        mtot[body[i]] += mass[i];
+    }
+    for (int32_t b = 0; b < nbody; ++b)
+        com[b] = mtot[b] > 0.0 ? com[b] / mtot[b] : 0.0;
+}
+
+/* Forward only: per-body J_b into loss (nbody), decision hash into *sig. */
+int orc_rollout_loss(int64_t n, const double *mass, int64_t ns, const int64_t *ends, const double *k,
+                     const double *c, const double *rest, const double *amp, const double *phase,
+                     const orc_params *p, const int32_t *body, int32_t nbody, int64_t nsteps,
+                     const double *x0, const double *v0, double *loss, uint64_t *sig)
+{
+    double *x = (double *)malloc(sizeof(double) * 3 * (size_t)(n + 1));
+    double *v = (double *)malloc(sizeof(double) * 3 * (size_t)(n + 1));
+    double *f = (double *)malloc(sizeof(double) * 3 * (size_t)(n + 1));
+    double *c0 = (double *)malloc(sizeof(double) * (size_t)(2 * nbody + 2));
+    if (!x || !v || !f || !c0) {
+        free(x); free(v); free(f); free(c0);
+        return -2;
+    }
+    memcpy(x, x0, sizeof(double) * 3 * (size_t)n);
+    memcpy(v, v0, sizeof(double) * 3 * (size_t)n);
+    if (sig)
+        *sig = 14695981039346656037ull;
+    double *mt = c0 + nbody + 1;
+    com_x(n, mass, body, nbody, x, c0, mt);
+    for (int64_t s = 0; s < nsteps; ++s)
+        step_sig(n, mass, ns, ends, k, c, rest, amp, phase, p, s, f, x, v, sig);
+    com_x(n, mass, body, nbody, x, loss, mt);
+    for (int32_t b = 0; b < nbody; ++b)
+        loss[b] = -(loss[b] - c0[b]);
+    free(x); free(v); free(f); free(c0);
+    return 0;
+}
+
+int orc_rollout_grad(int64_t n, const double *mass, int64_t ns, const int64_t *ends, const double *k,
+                     const double *c, const double *rest, const double *amp, const double *phase,
+                     const orc_params *p, const int32_t *body, int32_t nbody, const double *wbody,
+                     int64_t nsteps, const double *x0, const double *v0, double *loss, double *gk,
+                     double *gC, double *gS, uint64_t *sig)
+{
+    const double dt = p->dt;
+    const size_t S = 3 * (size_t)(n > 0 ? n : 1);
+    double *X = (double *)malloc(sizeof(double) * S * (size_t)(nsteps + 1));
+    double *V = (double *)malloc(sizeof(double) * S * (size_t)(nsteps + 1));
+    double *f = (double *)malloc(sizeof(double) * S);
+    double *lx = (double *)malloc(sizeof(double) * S);
+    double *lv = (double *)malloc(sizeof(double) * S);
+    double *nlx = (double *)malloc(sizeof(double) * S);
+    double *nlv = (double *)malloc(sizeof(double) * S);
+    double *mu = (double *)malloc(sizeof(double) * S);
+    double *cm = (double *)malloc(sizeof(double) * (size_t)(2 * nbody + 2));
+    if (!X || !V || !f || !lx || !lv || !nlx || !nlv || !mu || !cm) {
+        free(X); free(V); free(f); free(lx); free(lv); free(nlx); free(nlv); free(mu); free(cm);
+        return -2;
+    }
+    /* forward, keeping every state */
+    memcpy(X, x0, sizeof(double) * 3 * (size_t)n);
+    memcpy(V, v0, sizeof(double) * 3 * (size_t)n);
+    if (sig)
+        *sig = 14695981039346656037ull;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        memcpy(X + S * (s + 1), X + S * s, sizeof(double) * 3 * (size_t)n);
+        memcpy(V + S * (s + 1), V + S * s, sizeof(double) * 3 * (size_t)n);
+        step_sig(n, mass, ns, ends, k, c, rest, amp, phase, p, s, f, X + S * (s + 1), V + S * (s + 1), sig);
+    }
+    double *mt = cm + nbody + 1;
+    double *c0 = cm;
+    com_x(n, mass, body, nbody, X, c0, mt);
+    double *cN = (double *)malloc(sizeof(double) * (size_t)(nbody + 1));
+    if (!cN) {
+        free(X); free(V); free(f); free(lx); free(lv); free(nlx); free(nlv); free(mu); free(cm);
+        return -2;
+    }
+    com_x(n, mass, body, nbody, X + S * nsteps, cN, mt);
+    for (int32_t b = 0; b < nbody; ++b)
+        loss[b] = -(cN[b] - c0[b]);
+    free(cN);
+
+    /* dJ/dx_N, dJ/dv_N */
+    memset(lx, 0, sizeof(double) * S);
+    memset(lv, 0, sizeof(double) * S);
+    for (int64_t i = 0; i < n; ++i)
+        if (mt[body[i]] > 0.0)
+            lx[3 * i] = -wbody[body[i]] * mass[i] / mt[body[i]];
+    for (int64_t s = 0; s < ns; ++s)
+        gk[s] = gC[s] = gS[s] = 0.0;
+
+    for (int64_t st = nsteps - 1; st >= 0; --st) {
+        const double *x = X + S * st, *v = V + S * st;
+        const double t = (double)st * dt;
+        orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, t, x, v, f);
+        /* masses: position update, friction, velocity update */
+        for (int64_t i = 0; i < n; ++i) {
+            double m = mass[i];
+            for (int q = 0; q < 3; ++q) {
+                nlx[3 * i + q] = lx[3 * i + q];
+                nlv[3 * i + q] = lv[3 * i + q];
+                mu[3 * i + q] = 0.0;
+            }
+            if (m == 0.0)
+                continue; /* pinned: its state never changes */
+            double F[3];
+            for (int q = 0; q < 3; ++q)
+                F[q] = f[3 * i + q] + m * p->g[q];
+            double z = x[3 * i + 2];
+            int contact = p->ground && z < 0.0;
+            double Fn = 0.0;
+            if (contact) {
+                Fn = -p->ground_k * z;
+                F[2] += Fn;
+            }
+            double w[3];
+            for (int q = 0; q < 3; ++q)
+                w[q] = v[3 * i + q] + dt * F[q] / m;
+            /* v_{n+1} also moves x_{n+1} = x_n + dt v_{n+1} */
+            double lvt[3], lw[3];
+            for (int q = 0; q < 3; ++q)
+                lvt[q] = lv[3 * i + q] + dt * lx[3 * i + q];
+            for (int q = 0; q < 3; ++q)
+                lw[q] = lvt[q];
+            double dz = 0.0; /* extra dJ/dz through the friction bound */
+            if (contact) {
+                double vt = sqrt(w[0] * w[0] + w[1] * w[1]);
+                if (vt > 0.0) {
+                    double beta = p->mu * Fn * dt / m;
+                    double sc = 1.0 - beta / vt;
+                    if (sc > 0.0) {
+                        double wh[2] = {w[0] / vt, w[1] / vt};
+                        double wl = wh[0] * lvt[0] + wh[1] * lvt[1];
+                        lw[0] = sc * lvt[0] + (beta / vt) * wh[0] * wl;
+                        lw[1] = sc * lvt[1] + (beta / vt) * wh[1] * wl;
+                        dz = wl * p->mu * dt * p->ground_k / m;
+                    } else {
+                        lw[0] = 0.0;
+                        lw[1] = 0.0;
+                    }
+                }
+            }
+            for (int q = 0; q < 3; ++q) {
+                mu[3 * i + q] = dt / m * lw[q];
+                nlv[3 * i + q] = lw[q];
+            }
+            nlx[3 * i + 2] += dz;
+            if (contact)
+                nlx[3 * i + 2] += -p->ground_k * mu[3 * i + 2];
+        }
+        /* springs */
+        for (int64_t s = 0; s < ns; ++s) {
+            int64_t i = ends[2 * s], j = ends[2 * s + 1];
+            double d[3], dv[3];
+            for (int q = 0; q < 3; ++q) {
+                d[q] = x[3 * j + q] - x[3 * i + q];
+                dv[q] = v[3 * j + q] - v[3 * i + q];
+            }
+            double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (len == 0.0)
+                continue;
+            double u[3] = {d[0] / len, d[1] / len, d[2] / len};
+            double sw = 0.0, cw = 1.0;
+            if (amp) {
+                sw = sin(p->omega * t);
+                cw = cos(p->omega * t);
+            }
+            double L = rest[s];
+            if (amp)
+                L = rest[s] * (1.0 + amp[s] * sin(p->omega * t + phase[s]));
+            double e = len - L;
+            double vr = dv[0] * u[0] + dv[1] * u[1] + dv[2] * u[2];
+            double cs = c ? c[s] : 0.0;
+            double mag = k[s] * e + cs * vr;
+            double dm[3], pu = 0.0;
+            for (int q = 0; q < 3; ++q) {
+                dm[q] = mu[3 * i + q] - mu[3 * j + q];
+                pu += dm[q] * u[q];
+            }
+            for (int q = 0; q < 3; ++q) {
+                double gd = pu * k[s] * u[q] + pu * (cs / len) * (dv[q] - u[q] * vr) +
+                            (mag / len) * (dm[q] - u[q] * pu);
+                nlx[3 * j + q] += gd;
+                nlx[3 * i + q] -= gd;
+                double gv = pu * cs * u[q];
+                nlv[3 * j + q] += gv;
+                nlv[3 * i + q] -= gv;
+            }
+            gk[s] += pu * e;
+            if (amp) {
+                gC[s] += pu * k[s] * (-rest[s] * sw);
+                gS[s] += pu * k[s] * (-rest[s] * cw);
+            }
+        }
+        double *tmp = lx;
+        lx = nlx;
+        nlx = tmp;
+        tmp = lv;
+        lv = nlv;
+        nlv = tmp;
+    }
+    free(X); free(V); free(f); free(lx); free(lv); free(nlx); free(nlv); free(mu); free(cm);
+    return 0;
+}
