@@ -213,6 +213,34 @@ int titan_set_state(titan_sim *sim, int64_t first, int64_t count, const float *p
  * stopped).  Only when no steps are held at a pause breakpoint. */
 int titan_set_step(titan_sim *sim, int64_t step);
 
+/* Change the constants of springs [first, first+count): k, damping and
+ * actuation (amp with phase), each array NULL to keep that part (the paper's
+ * Sec. IV-D pushes spring constants from the CPU into a running
+ * simulation).  In stream order: applies to steps enqueued after the call
+ * (while paused: from the breakpoint on).  Same value rules as
+ * titan_add_springs. */
+int titan_set_springs(titan_sim *sim, int64_t first, int64_t count, const float *k_n, const float *damping_n,
+                      const float *amp_n, const float *phase_n);
+
+/* Gradient of a rollout by the adjoint method: backward in time through the
+ * steps, with the forward states recomputed from checkpoints taken every
+ * `checkpoint_every` steps (memory: one state per checkpoint plus one
+ * segment of states).  The rollout starts from the current state (after all
+ * enqueued steps) at the current step index and runs `nsteps` steps; the
+ * simulation itself is not advanced.  Loss: J = sum_b w_b J_b with
+ * J_b = -(x-displacement of the centre of mass of body b), the
+ * mass-weighted mean over the body's masses.  body_weights: w_b per body
+ * (n_bodies values) or NULL for all 1.  Outputs (each may be NULL):
+ * loss_out[n_bodies] = J_b; grad_k[n_springs] = dJ/dk; grad_act_c and
+ * grad_act_s[n_springs] = dJ/dC and dJ/dS for the actuation phasor
+ * C = amp cos(phase), S = amp sin(phase) (the rest length at time t is
+ * rest (1 + C sin(omega t) + S cos(omega t))).  Needs every body to fit the
+ * batched engine's layout (TITAN_ESTATE otherwise); TITAN_ENONFINITE if the
+ * rollout blows up.  Differentiates the step exactly as computed, contact
+ * and friction included (their switches are not smoothed). */
+int titan_rollout_grad(titan_sim *sim, int64_t nsteps, int32_t checkpoint_every, const float *body_weights,
+                       float *loss_out, float *grad_k, float *grad_act_c, float *grad_act_s);
+
 /* Summed spring force on masses [first, first+count) at the current state
  * and the current step's time (blocks).  f_n3 receives N. */
 int titan_get_forces(titan_sim *sim, int64_t first, int64_t count, float *f_n3);

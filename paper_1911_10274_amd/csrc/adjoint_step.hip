@@ -1,0 +1,400 @@
+// Adjoint (reverse-mode, backward in time) of a rollout on the batched
+// layout: one workgroup per group of whole bodies, state in LDS.
+//
+// Loss: J = sum_b w_b * J_b, J_b = -(CoM_x(x_N) - CoM_x(x_0)) of body b; its
+// gradient with respect to x_N is the per-mass seed -w_b m_i / M_b (x).
+// Gradients: per spring, dJ/dk and dJ/d(C, S) of the actuation phasor
+// (rest length L0 (1 + C sin(omega t) + S cos(omega t))).
+//
+// One launch per call:
+//   1. forward nsteps steps, storing the state every K steps (checkpoints);
+//   2. for each segment, newest first: reload its checkpoint, recompute its K
+//      states into a segment buffer, then run K reverse steps.
+// A reverse step undoes, in reverse order, what a forward step did
+// (Sec. III-B's two passes):
+//   mass pass:   x' = x + dt v',  v' = friction(w),  w = v + dt F / m
+//                -> force adjoint mu_i = dt/m * dJ/dw_i (kept in LDS)
+//   spring pass: every spring's force depends on both ends' x and v and on
+//                (k, C, S): gather, per mass, the contributions of its springs
+//                from mu_i - mu_j; the spring's owner slot (lower internal
+//                index end) adds the parameter gradients.  No atomics.
+#include "step_device.h"
+
+namespace titan {
+
+namespace {
+
+// dJ/d(spring inputs) for one incidence of mass i: updates the adjoints of
+// x_i, v_i and returns the parameter-gradient contributions (k, C, S).
+template <bool ACT, bool DAMP, bool REST>
+__device__ __forceinline__ void spring_adjoint(const float4 &xi, const float4 &ui, const float4 &vi,
+                                               const float4 &xj, const float4 &uj, const float4 &vj,
+                                               const SpringConst &p, float sin_wt, float cos_wt,
+                                               const float4 &mi, const float4 &mj, float3 &lx, float3 &lv,
+                                               float &gk, float &gC, float &gS)
+{
+#pragma clang fp contract(off)
+    const float Rx = xj.x - xi.x, Ry = xj.y - xi.y, Rz = xj.z - xi.z;
+    const float ax = uj.x - ui.x, ay = uj.y - ui.y, az = uj.z - ui.z;
+    const float dx = Rx + ax, dy = Ry + ay, dz = Rz + az;
+    const float l2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    gk = gC = gS = 0.f;
+    if (!(l2 > 0.f))
+        return;  // no force, no gradient (also the padding slots)
+    const float il = __builtin_amdgcn_rsqf(l2);
+    const float l = l2 * il;
+    const float R2 = fmaf(Rx, Rx, fmaf(Ry, Ry, Rz * Rz));
+    const float r = R2 > 0.f ? R2 * __builtin_amdgcn_rsqf(R2) : 0.f;
+    const float Rda = fmaf(Rx, ax, fmaf(Ry, ay, Rz * az));
+    const float ada = fmaf(ax, ax, fmaf(ay, ay, az * az));
+    float e = fmaf(2.f, Rda, ada) * __builtin_amdgcn_rcpf(l + r);
+    const float L0 = REST ? p.L0 : r;
+    if (REST)
+        e += p.d0;
+    if (ACT)
+        e = fmaf(-L0, fmaf(p.act_c, sin_wt, p.act_s * cos_wt), e);
+    const float ux = dx * il, uy = dy * il, uz = dz * il;
+    const float dvx = vj.x - vi.x, dvy = vj.y - vi.y, dvz = vj.z - vi.z;
+    const float vr = DAMP ? fmaf(dvx, ux, fmaf(dvy, uy, dvz * uz)) : 0.f;
+    const float mag = DAMP ? fmaf(p.c, vr, p.k * e) : p.k * e;
+    // dm = mu_i - mu_j, pu = dm . u
+    const float mx = mi.x - mj.x, my = mi.y - mj.y, mz = mi.z - mj.z;
+    const float pu = fmaf(mx, ux, fmaf(my, uy, mz * uz));
+    // g_d = pu k u + pu (c / l)(dv - u vr) + (mag / l)(dm - u pu): the gradient
+    // with respect to d = x_j - x_i; mass i receives -g_d.
+    const float a1 = pu * p.k;
+    const float a2 = DAMP ? pu * p.c * il : 0.f;
+    const float a3 = mag * il;
+    const float gx = fmaf(a1, ux, fmaf(a2, fmaf(-ux, vr, dvx), a3 * fmaf(-ux, pu, mx)));
+    const float gy = fmaf(a1, uy, fmaf(a2, fmaf(-uy, vr, dvy), a3 * fmaf(-uy, pu, my)));
+    const float gz = fmaf(a1, uz, fmaf(a2, fmaf(-uz, vr, dvz), a3 * fmaf(-uz, pu, mz)));
+    lx.x -= gx;
+    lx.y -= gy;
+    lx.z -= gz;
+    if (DAMP) {
+        const float b = pu * p.c;
+        lv.x = fmaf(-b, ux, lv.x);
+        lv.y = fmaf(-b, uy, lv.y);
+        lv.z = fmaf(-b, uz, lv.z);
+    }
+    gk = pu * e;
+    if (ACT) {
+        gC = -(a1 * L0 * sin_wt);
+        gS = -(a1 * L0 * cos_wt);
+    }
+}
+
+// Mass pass of a reverse step for one mass: given the summed spring force f
+// at the step's starting state and the adjoints (lx, lv) of the state after
+// the step, returns the force adjoint mu = dt/m dJ/dw and updates (lx, lv) to
+// the adjoints of the starting state (minus the spring terms, added later).
+__device__ __forceinline__ float4 mass_adjoint(const float4 &xi, const float4 &ui, const float4 &vi, float fx,
+                                               float fy, float fz, const StepConsts &sc, float3 &lx, float3 &lv)
+{
+#pragma clang fp contract(off)
+    const float im = ui.w;
+    if (im == 0.f)
+        return make_float4(0.f, 0.f, 0.f, 0.f);  // pinned: nothing depends on its force
+    float ax = fmaf(fx, im, sc.gx);
+    float ay = fmaf(fy, im, sc.gy);
+    float az = fmaf(fz, im, sc.gz);
+    const float z = xi.z + ui.z;
+    const bool contact = sc.ground && z < 0.f;
+    float fn = 0.f;
+    if (contact) {
+        fn = -sc.ground_k * z;
+        az = fmaf(fn, im, az);
+    }
+    const float wx = fmaf(sc.dt, ax, vi.x);
+    const float wy = fmaf(sc.dt, ay, vi.y);
+    // v' moves x' too: adjoint of v' is lv + dt lx
+    const float tx = fmaf(sc.dt, lx.x, lv.x), ty = fmaf(sc.dt, lx.y, lv.y), tz = fmaf(sc.dt, lx.z, lv.z);
+    float wlx = tx, wly = ty;
+    float dzf = 0.f;
+    if (contact) {
+        const float vt = sqrtf(fmaf(wx, wx, wy * wy));
+        if (vt > 0.f) {
+            const float beta = sc.mu * fn * sc.dt * im;
+            const float s = 1.f - beta / vt;
+            if (s > 0.f) {
+                const float hx = wx / vt, hy = wy / vt;
+                const float wl = fmaf(hx, tx, hy * ty);
+                const float bv = beta / vt;
+                wlx = fmaf(s, tx, bv * hx * wl);
+                wly = fmaf(s, ty, bv * hy * wl);
+                dzf = wl * sc.mu * sc.dt * sc.ground_k * im;
+            } else {
+                wlx = 0.f;
+                wly = 0.f;
+            }
+        }
+    }
+    const float4 mu = make_float4(sc.dt * im * wlx, sc.dt * im * wly, sc.dt * im * tz, 0.f);
+    lv = make_float3(wlx, wly, tz);
+    lx.z += dzf;
+    if (contact)
+        lx.z = fmaf(-sc.ground_k, mu.z, lx.z);
+    return mu;
+}
+
+template <bool ACT, bool DAMP, bool DAMPV, bool REST, int T, int MAXM>
+__global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b, AdjointIO a, StepConsts sc)
+{
+    extern __shared__ float4 smem[];
+    const int cap = b.max_group;
+    float4 *sX = smem;
+    float4 *sU = smem + cap;
+    float4 *sV = smem + 2 * cap;
+    float4 *sM = smem + 3 * cap;
+    const int64_t n = g.n;
+    const int64_t m0 = b.mass_off[blockIdx.x];
+    const int nm = (int)(b.mass_off[blockIdx.x + 1] - m0);
+    const int tid = threadIdx.x;
+    const int K = a.K;
+
+    auto nbr = [&](int64_t e) { return (int)b.nbr_group[e]; };
+    auto state = [&](int r, float4 &xj, float4 &uj, float4 &vj) {
+        uj = sU[r];
+        xj = sX[r];
+        vj = DAMP ? sV[r] : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    // one forward step of the group in LDS (same arithmetic as every engine)
+    auto forward = [&](int s) {
+        const float2 tr = ACT ? a.trig[s] : make_float2(0.f, 1.f);
+        float4 nu[MAXM], nv[MAXM];
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) {
+            const int q = tid + k * T;
+            if (q < nm) {
+                const int64_t i = m0 + q;
+                const float4 xi = sX[q], ui = sU[q], vi = sV[q];
+                float fx = 0.f, fy = 0.f, fz = 0.f;
+                sum_forces<ACT, DAMP, DAMPV, REST, false>(g, g.slice_off[i >> 6] + (i & 63), slice_width(g, i),
+                                                          xi, ui, vi, tr, nbr, state, fx, fy, fz);
+                ok &= integrate_mass(xi, ui, vi, fx, fy, fz, sc, nu[k], nv[k]);
+            }
+        }
+        if (!ok)
+            atomicMin(a.first_bad, (unsigned long long)(sc.step + s));
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) {
+            const int q = tid + k * T;
+            if (q < nm) {
+                sU[q] = nu[k];
+                sV[q] = nv[k];
+            }
+        }
+        __syncthreads();
+    };
+
+    for (int q = tid; q < nm; q += T) {
+        const float4 u = a.U0[m0 + q], v = a.V0[m0 + q];
+        sX[q] = g.X0[m0 + q];
+        sU[q] = u;
+        sV[q] = v;
+        a.ckU[m0 + q] = u;
+        a.ckV[m0 + q] = v;
+    }
+    __syncthreads();
+
+    // 1. forward with checkpoints
+    const int nseg = (a.nsteps + K - 1) / K;
+    for (int s = 0; s < a.nsteps; ++s) {
+        forward(s);
+        if ((s + 1) % K == 0 && (s + 1) / K < nseg)
+            for (int q = tid; q < nm; q += T) {
+                a.ckU[(int64_t)((s + 1) / K) * n + m0 + q] = sU[q];
+                a.ckV[(int64_t)((s + 1) / K) * n + m0 + q] = sV[q];
+            }
+    }
+    for (int q = tid; q < nm; q += T)
+        a.dux[m0 + q] = sU[q].x - a.U0[m0 + q].x;
+
+    // 2. reverse, segment by segment
+    float3 lx[MAXM], lv[MAXM];
+#pragma unroll
+    for (int k = 0; k < MAXM; ++k) {
+        const int q = tid + k * T;
+        lx[k] = make_float3(q < nm ? a.seed[m0 + q] : 0.f, 0.f, 0.f);
+        lv[k] = make_float3(0.f, 0.f, 0.f);
+    }
+    for (int c = nseg - 1; c >= 0; --c) {
+        const int s0 = c * K;
+        const int len = min(K, a.nsteps - s0);
+        __syncthreads();
+        for (int q = tid; q < nm; q += T) {
+            sU[q] = a.ckU[(int64_t)c * n + m0 + q];
+            sV[q] = a.ckV[(int64_t)c * n + m0 + q];
+        }
+        __syncthreads();
+        for (int r = 0; r < len; ++r) {
+            for (int q = tid; q < nm; q += T) {
+                a.segU[(int64_t)r * n + m0 + q] = sU[q];
+                a.segV[(int64_t)r * n + m0 + q] = sV[q];
+            }
+            if (r + 1 < len)
+                forward(s0 + r);
+        }
+        for (int r = len - 1; r >= 0; --r) {
+            const int s = s0 + r;
+            const float2 tr = ACT ? a.trig[s] : make_float2(0.f, 1.f);
+            StepConsts scs = sc;
+            __syncthreads();
+            for (int q = tid; q < nm; q += T) {
+                sU[q] = a.segU[(int64_t)r * n + m0 + q];
+                sV[q] = a.segV[(int64_t)r * n + m0 + q];
+            }
+            __syncthreads();
+            // mass pass
+#pragma unroll
+            for (int k = 0; k < MAXM; ++k) {
+                const int q = tid + k * T;
+                if (q < nm) {
+                    const int64_t i = m0 + q;
+                    const float4 xi = sX[q], ui = sU[q], vi = sV[q];
+                    float fx = 0.f, fy = 0.f, fz = 0.f;
+                    sum_forces<ACT, DAMP, DAMPV, REST, false>(g, g.slice_off[i >> 6] + (i & 63), slice_width(g, i),
+                                                              xi, ui, vi, tr, nbr, state, fx, fy, fz);
+                    sM[q] = mass_adjoint(xi, ui, vi, fx, fy, fz, scs, lx[k], lv[k]);
+                }
+            }
+            __syncthreads();
+            // spring pass
+#pragma unroll
+            for (int k = 0; k < MAXM; ++k) {
+                const int q = tid + k * T;
+                if (q < nm) {
+                    const int64_t i = m0 + q;
+                    const float4 xi = sX[q], ui = sU[q], vi = sV[q], mi = sM[q];
+                    const int64_t base = g.slice_off[i >> 6] + (i & 63);
+                    const int width = slice_width(g, i);
+                    for (int w = 0; w < width; ++w) {
+                        const int64_t e = base + (int64_t)w * kSlice;
+                        const int jr = nbr(e);
+                        const SpringConst p = load_const<ACT, DAMPV, REST, false>(g, e);
+                        float gk, gC, gS;
+                        spring_adjoint<ACT, DAMP, REST>(xi, ui, vi, sX[jr], sU[jr],
+                                                        DAMP ? sV[jr] : make_float4(0.f, 0.f, 0.f, 0.f), p, tr.x,
+                                                        tr.y, mi, sM[jr], lx[k], lv[k], gk, gC, gS);
+                        if (jr > q) {  // owner slot of this spring: lower internal index end
+                            float4 acc = a.gslot[e];
+                            acc.x += gk;
+                            acc.y += gC;
+                            acc.z += gS;
+                            a.gslot[e] = acc;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <bool ACT, bool DAMP, bool DAMPV, bool REST, int T, int MAXM>
+hipError_t launch_tm(const GatherGraph &g, const BatchLayout &b, const AdjointIO &a, const StepConsts &sc,
+                     hipStream_t st)
+{
+    auto kern = adjoint_kernel<ACT, DAMP, DAMPV, REST, T, MAXM>;
+    const size_t lds = (size_t)b.max_group * 4 * sizeof(float4);
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)b.n_groups), dim3(T), lds, st, g, b, a, sc);
+    return hipGetLastError();
+}
+
+template <bool ACT, bool DAMP, bool DAMPV, bool REST>
+hipError_t launch4(const GatherGraph &g, const BatchLayout &b, const AdjointIO &a, const StepConsts &sc,
+                   hipStream_t st)
+{
+    constexpr int T = 256;
+    const int per = (b.max_group + T - 1) / T;
+    if (per <= 1)
+        return launch_tm<ACT, DAMP, DAMPV, REST, T, 1>(g, b, a, sc, st);
+    if (per <= 2)
+        return launch_tm<ACT, DAMP, DAMPV, REST, T, 2>(g, b, a, sc, st);
+    if (per <= 4)
+        return launch_tm<ACT, DAMP, DAMPV, REST, T, 4>(g, b, a, sc, st);
+    if (per <= 8)
+        return launch_tm<ACT, DAMP, DAMPV, REST, T, 8>(g, b, a, sc, st);
+    return hipErrorInvalidValue;
+}
+
+__global__ void gather_spring_grads(const float4 *gslot, const int64_t *owner_slot, int64_t ns, float *gk, float *gC,
+                                    float *gS)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns)
+        return;
+    const float4 v = gslot[owner_slot[s]];
+    gk[s] = v.x;
+    gC[s] = v.y;
+    gS[s] = v.z;
+}
+
+// J_b = -sum_{i in b} (m_i / M_b) * dux_i: one thread per body, masses of a
+// body contiguous, summed in index order (deterministic).
+__global__ void body_loss(const float *dux, const float *coef, const int64_t *body_off, int64_t nb, float *loss)
+{
+    const int64_t bdy = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (bdy >= nb)
+        return;
+    float acc = 0.f;
+    for (int64_t i = body_off[bdy]; i < body_off[bdy + 1]; ++i)
+        acc = fmaf(coef[i], dux[i], acc);
+    loss[bdy] = -acc;
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const GatherGraph &g, const BatchLayout &b, const AdjointIO &a, const StepConsts &sc,
+                          hipStream_t stream)
+{
+    if (b.n_groups == 0 || a.nsteps <= 0)
+        return hipSuccess;
+    const bool act = g.act_c != nullptr, dampv = g.c != nullptr, rest = g.d0 != nullptr;
+    const bool damp = dampv || g.c_uniform != 0.f;
+    const int key = (act ? 8 : 0) | (damp ? 4 : 0) | (dampv ? 2 : 0) | (rest ? 1 : 0);
+    switch (key) {
+    case 0: return launch4<false, false, false, false>(g, b, a, sc, stream);
+    case 1: return launch4<false, false, false, true>(g, b, a, sc, stream);
+    case 4: return launch4<false, true, false, false>(g, b, a, sc, stream);
+    case 5: return launch4<false, true, false, true>(g, b, a, sc, stream);
+    case 6: return launch4<false, true, true, false>(g, b, a, sc, stream);
+    case 7: return launch4<false, true, true, true>(g, b, a, sc, stream);
+    case 8: return launch4<true, false, false, false>(g, b, a, sc, stream);
+    case 9: return launch4<true, false, false, true>(g, b, a, sc, stream);
+    case 12: return launch4<true, true, false, false>(g, b, a, sc, stream);
+    case 13: return launch4<true, true, false, true>(g, b, a, sc, stream);
+    case 14: return launch4<true, true, true, false>(g, b, a, sc, stream);
+    case 15: return launch4<true, true, true, true>(g, b, a, sc, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_spring_grads(const float4 *gslot, const int64_t *owner_slot, int64_t ns, float *gk, float *gC,
+                               float *gS, hipStream_t stream)
+{
+    if (ns == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(gather_spring_grads, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, stream, gslot,
+                       owner_slot, ns, gk, gC, gS);
+    return hipGetLastError();
+}
+
+hipError_t launch_body_loss(const float *dux, const float *coef, const int64_t *body_off, int64_t nb, float *loss,
+                            hipStream_t stream)
+{
+    if (nb == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(body_loss, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, stream, dux, coef, body_off, nb,
+                       loss);
+    return hipGetLastError();
+}
+
+}  // namespace titan

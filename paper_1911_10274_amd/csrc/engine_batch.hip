@@ -83,9 +83,10 @@ static int time_gather(titan_sim *s, float4 *su, float4 *sv, float *ms)
     return TITAN_OK;
 }
 
-int build_batch_engine(titan_sim *s)
+int build_batch_engine(titan_sim *s, bool may_step)
 {
     s->batch = nullptr;
+    s->batch_step = false;
     const int64_t n = s->n;
     if (n == 0 || (s->h_slot_nbr.empty() && s->ns > 0))
         return TITAN_OK;
@@ -161,6 +162,11 @@ int build_batch_engine(titan_sim *s)
         be->lay.nbr_group = e;
     }
 
+    if (!may_step) {
+        s->batch = be;
+        return TITAN_OK;
+    }
+
     // Autotune: workgroup size of the batched kernel, and (AUTO) batched vs
     // the per-step gather engine, by timing kTuneSteps steps of each into
     // scratch buffers (the simulation state is not touched).
@@ -211,11 +217,10 @@ int build_batch_engine(titan_sim *s)
     const unsigned long long none = ~0ull;
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     HIP_TRY(s, hipMemcpy(s->first_bad, &none, sizeof none, hipMemcpyHostToDevice));
-    if (!use) {
-        delete be;
-        return TITAN_OK;
-    }
+    // The layout is kept whenever the system fits it: the adjoint runs on it
+    // even when the per-step gather engine steps the system.
     s->batch = be;
+    s->batch_step = use;
     return TITAN_OK;
 }
 
@@ -244,6 +249,152 @@ void destroy_batch_engine(titan_sim *s)
     s->batch = nullptr;
 }
 
-int batch_threads(const titan_sim *s) { return s->batch ? s->batch->threads : 0; }
+// Adjoint rollout on the batched layout (see adjoint_step.hip).
+int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weights, float *loss, float *gk,
+                 float *gC, float *gS)
+{
+    if (!s->batch)
+        return fail(TITAN_ESTATE, "the rollout gradient needs every body to fit one workgroup's LDS");
+    if (nsteps < 0 || K < 1)
+        return fail(TITAN_EINVAL, "need nsteps >= 0 and checkpoint interval >= 1");
+    if (nsteps > (int64_t)1 << 30)
+        return fail(TITAN_EINVAL, "nsteps too large");
+    if (s->paused && s->steps_req != s->step_enq)
+        return fail(TITAN_ESTATE, "steps are held at a pause breakpoint");
+    if (s->batch->lay.max_group > 8 * 256)
+        return fail(TITAN_ESTATE, "the rollout gradient supports groups of at most 2048 masses");
+    const int64_t n = s->n, ns = s->ns;
+    if (nsteps == 0) {
+        int32_t nb = 0;
+        for (int32_t b : s->h_body)
+            nb = std::max(nb, b + 1);
+        if (loss)
+            std::fill(loss, loss + nb, 0.f);
+        for (float *g : {gk, gC, gS})
+            if (g)
+                std::fill(g, g + ns, 0.f);
+        return TITAN_OK;
+    }
+    K = (int32_t)std::min<int64_t>(K, std::max<int64_t>(nsteps, 1));
+    const int64_t nseg = (nsteps + K - 1) / K;
+
+    // Bodies: contiguous internal ranges (plan_order), in rank order.
+    int32_t nb = 0;
+    for (int32_t b : s->h_body)
+        nb = std::max(nb, b + 1);
+    std::vector<int64_t> body_off{0};
+    std::vector<int32_t> rank_body;
+    for (int64_t a = 0; a < n;) {
+        const int32_t bd = s->h_body[s->perm[a]];
+        int64_t b = a + 1;
+        while (b < n && s->h_body[s->perm[b]] == bd)
+            ++b;
+        rank_body.push_back(bd);
+        body_off.push_back(b);
+        a = b;
+    }
+    const int64_t nruns = (int64_t)rank_body.size();
+    std::vector<double> mtot(nb, 0.0);
+    for (int64_t u = 0; u < n; ++u)
+        mtot[s->h_body[u]] += (double)s->h_mass[u];
+    std::vector<float> coef(n), seed(n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t u = s->perm[i];
+        const int32_t bd = s->h_body[u];
+        const double c = mtot[bd] > 0.0 ? (double)s->h_mass[u] / mtot[bd] : 0.0;
+        coef[i] = (float)c;
+        seed[i] = (float)(-(body_weights ? (double)body_weights[bd] : 1.0) * c);
+    }
+
+    // Buffers (released at the end of the call).
+    std::vector<void *> tmp;
+    auto get = [&](size_t bytes, void **p) {
+        const int rc = dev_alloc(s, bytes, p);
+        if (rc == TITAN_OK)
+            tmp.push_back(*p);
+        return rc;
+    };
+    auto cleanup = [&]() {
+        for (void *p : tmp)
+            dev_free(s, p);
+    };
+    AdjointIO a{};
+    float *dseed = nullptr, *dcoef = nullptr, *dloss = nullptr, *dgrad = nullptr;
+    int64_t *dboff = nullptr, *downer = nullptr;
+    float2 *dtrig = nullptr;
+    unsigned long long *dbad = nullptr;
+    int64_t nslots = 0;
+    {
+        std::vector<int64_t> last(1);
+        HIP_TRY(s, hipMemcpy(last.data(), s->gg.slice_off + s->gg.n_slices, sizeof(int64_t), hipMemcpyDeviceToHost));
+        nslots = last[0];
+    }
+    int rc = TITAN_OK;
+    if ((rc = get(sizeof(float4) * n * std::max<int64_t>(nseg, 1), (void **)&a.ckU)) ||
+        (rc = get(sizeof(float4) * n * std::max<int64_t>(nseg, 1), (void **)&a.ckV)) ||
+        (rc = get(sizeof(float4) * n * K, (void **)&a.segU)) || (rc = get(sizeof(float4) * n * K, (void **)&a.segV)) ||
+        (rc = get(sizeof(float4) * std::max<int64_t>(nslots, 1), (void **)&a.gslot)) ||
+        (rc = get(sizeof(float) * n, (void **)&dseed)) || (rc = get(sizeof(float) * n, (void **)&dcoef)) ||
+        (rc = get(sizeof(float) * n, (void **)&a.dux)) || (rc = get(sizeof(float) * nruns, (void **)&dloss)) ||
+        (rc = get(sizeof(float) * 3 * ns, (void **)&dgrad)) || (rc = get(sizeof(int64_t) * (nruns + 1), (void **)&dboff)) ||
+        (rc = get(sizeof(int64_t) * ns, (void **)&downer)) ||
+        (rc = get(sizeof(float2) * std::max<int64_t>(nsteps, 1), (void **)&dtrig)) ||
+        (rc = get(sizeof(unsigned long long), (void **)&dbad))) {
+        cleanup();
+        return rc;
+    }
+    const unsigned long long none = ~0ull;
+#define TRY(expr)                                              \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) {                                \
+            cleanup();                                         \
+            return titan::hip_fail(s, e_, #expr);              \
+        }                                                      \
+    } while (0)
+    TRY(hipMemcpyAsync(dseed, seed.data(), sizeof(float) * n, hipMemcpyHostToDevice, s->stream));
+    TRY(hipMemcpyAsync(dcoef, coef.data(), sizeof(float) * n, hipMemcpyHostToDevice, s->stream));
+    TRY(hipMemcpyAsync(dboff, body_off.data(), sizeof(int64_t) * (nruns + 1), hipMemcpyHostToDevice, s->stream));
+    TRY(hipMemcpyAsync(downer, s->h_owner_slot.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, s->stream));
+    TRY(hipMemcpyAsync(dbad, &none, sizeof none, hipMemcpyHostToDevice, s->stream));
+    TRY(hipMemsetAsync(a.gslot, 0, sizeof(float4) * std::max<int64_t>(nslots, 1), s->stream));
+    TRY(launch_trig_table(dtrig, s->step_enq, (int)nsteps, s->params.omega, s->params.dt, s->stream));
+    a.U0 = s->U[s->cur];
+    a.V0 = s->V[s->cur];
+    a.seed = dseed;
+    a.trig = dtrig;
+    a.first_bad = dbad;
+    a.nsteps = (int)nsteps;
+    a.K = K;
+    const StepConsts sc = consts_for(s, s->step_enq, dtrig);
+    TRY(launch_adjoint(s->gg, s->batch->lay, a, sc, s->stream));
+    TRY(launch_spring_grads(a.gslot, downer, ns, dgrad, dgrad + ns, dgrad + 2 * ns, s->stream));
+    TRY(launch_body_loss(a.dux, dcoef, dboff, nruns, dloss, s->stream));
+    std::vector<float> hgrad(3 * ns), hloss(nruns);
+    unsigned long long bad = ~0ull;
+    TRY(hipMemcpyAsync(hgrad.data(), dgrad, sizeof(float) * 3 * ns, hipMemcpyDeviceToHost, s->stream));
+    TRY(hipMemcpyAsync(hloss.data(), dloss, sizeof(float) * nruns, hipMemcpyDeviceToHost, s->stream));
+    TRY(hipMemcpyAsync(&bad, dbad, sizeof bad, hipMemcpyDeviceToHost, s->stream));
+    TRY(hipStreamSynchronize(s->stream));
+#undef TRY
+    cleanup();
+    if (bad != ~0ull)
+        return fail(TITAN_ENONFINITE, "the rollout produced a non-finite state at step %llu", bad);
+    if (gk)
+        std::copy(hgrad.begin(), hgrad.begin() + ns, gk);
+    if (gC)
+        std::copy(hgrad.begin() + ns, hgrad.begin() + 2 * ns, gC);
+    if (gS)
+        std::copy(hgrad.begin() + 2 * ns, hgrad.end(), gS);
+    if (loss) {
+        for (int32_t b = 0; b < nb; ++b)
+            loss[b] = 0.f;
+        for (int64_t r = 0; r < nruns; ++r)
+            loss[rank_body[r]] = hloss[r];
+    }
+    return TITAN_OK;
+}
+
+int batch_threads(const titan_sim *s) { return s->batch && s->batch_step ? s->batch->threads : 0; }
 
 }  // namespace titan

@@ -15,7 +15,7 @@
 
 namespace titan {
 
-int build_batch_engine(titan_sim *s);  // engine_batch.hip
+int build_batch_engine(titan_sim *s, bool may_step);  // engine_batch.hip
 int enqueue_batch_steps(titan_sim *s, int64_t first_step, int64_t count);
 void destroy_batch_engine(titan_sim *s);
 
@@ -235,6 +235,8 @@ static int build_gather(titan_sim *s, bool allow_tiled)
         d0.assign(slots, 0.f);
         L0.assign(slots, 1.f);
     }
+    s->h_owner_slot.assign(ns, -1);
+    s->h_other_slot.assign(ns, -1);
     for (int64_t i = 0; i < n; ++i) {
         const int64_t base = off[i / kSlice] + (i % kSlice);
         const int64_t t = i / kTile, a = t * kTile;
@@ -258,6 +260,10 @@ static int build_gather(titan_sim *s, bool allow_tiled)
                     nbr_local[e] = (uint16_t)(kTile + (std::lower_bound(hb, he, (int32_t)j) - hb));
             }
             nbr[e] = (int32_t)j;
+            if (j > i)
+                s->h_owner_slot[x.spring] = e;
+            else
+                s->h_other_slot[x.spring] = e;
             if (!k_uniform)
                 kk[e] = s->h_k[x.spring];
             if (!damp_uniform)
@@ -316,6 +322,7 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     }
     g.X0 = s->X0;
     s->tiled = tiled;
+    s->n_slots = slots;
     // keep the staging alive until the copies have run
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     s->h_slot_nbr.swap(nbr);  // for the batched engine's layout
@@ -332,17 +339,99 @@ int build_engines(titan_sim *s)
     if (int rc = build_gather(s, want != TITAN_ENGINE_GATHER))
         return rc;
     s->engine = s->tiled ? TITAN_ENGINE_TILED : TITAN_ENGINE_GATHER;
-    if (want == TITAN_ENGINE_BATCHED || want == TITAN_ENGINE_AUTO) {
-        const int rc = build_batch_engine(s);
-        if (rc == TITAN_OK && s->batch)
-            s->engine = TITAN_ENGINE_BATCHED;
-        else if (want == TITAN_ENGINE_BATCHED)
-            return rc != TITAN_OK ? rc : fail(TITAN_EINVAL, "the batched engine cannot run this system");
-        else if (rc != TITAN_OK)
-            return rc;
-    }
+    // The batched layout is built whenever the bodies fit it (the adjoint
+    // uses it); it steps the system when asked for, or when AUTO times it
+    // faster.
+    if (int rc = build_batch_engine(s, want == TITAN_ENGINE_BATCHED || want == TITAN_ENGINE_AUTO))
+        return rc;
+    if (s->batch && s->batch_step)
+        s->engine = TITAN_ENGINE_BATCHED;
+    else if (want == TITAN_ENGINE_BATCHED)
+        return fail(TITAN_EINVAL, "the batched engine cannot run this system (a body does not fit in LDS)");
     std::vector<int32_t>().swap(s->h_slot_nbr);
     return TITAN_OK;
+}
+
+// Spring constants changed after the device layout exists: both incidence
+// slots of every changed spring are rewritten on the device, in stream order.
+// A uniform stiffness/damping that stops being uniform, or actuation that
+// appears, gets its per-slot array first.
+int update_springs(titan_sim *s, int64_t first, int64_t count, const float *k, const float *damping,
+                   const float *amp, const float *phase)
+{
+    GatherGraph &g = s->gg;
+    const int64_t m = 2 * count;
+    std::vector<int64_t> slot(m);
+    for (int64_t q = 0; q < count; ++q) {
+        slot[2 * q] = s->h_owner_slot[first + q];
+        slot[2 * q + 1] = s->h_other_slot[first + q];
+    }
+    std::vector<void *> tmp;
+    auto cleanup = [&]() {
+        for (void *p : tmp)
+            dev_free(s, p);
+    };
+    int64_t *dslot = nullptr;
+    float *dval = nullptr;
+    if (int rc = dev_alloc(s, sizeof(int64_t) * std::max<int64_t>(m, 1), (void **)&dslot))
+        return rc;
+    tmp.push_back(dslot);
+    if (int rc = dev_alloc(s, sizeof(float) * std::max<int64_t>(m, 1), (void **)&dval)) {
+        cleanup();
+        return rc;
+    }
+    tmp.push_back(dval);
+    if (m)
+        HIP_TRY(s, hipMemcpyAsync(dslot, slot.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, s->stream));
+    std::vector<float> val(m);
+    // one per-slot array: allocate it (filled with `fill`) if absent, then scatter
+    auto apply = [&](const float **arr, float fill, auto value_of) -> int {
+        if (!*arr) {
+            float *p = nullptr;
+            if (int rc = dev_alloc(s, sizeof(float) * std::max<int64_t>(s->n_slots, 1), (void **)&p))
+                return rc;
+            HIP_TRY(s, launch_fill(p, fill, s->n_slots, s->stream));
+            *arr = p;
+        }
+        for (int64_t q = 0; q < count; ++q)
+            val[2 * q] = val[2 * q + 1] = value_of(first + q);
+        if (m)
+            HIP_TRY(s, hipMemcpyAsync(dval, val.data(), sizeof(float) * m, hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(s, launch_scatter(const_cast<float *>(*arr), dslot, dval, m, s->stream));
+        // the staging values are reused by the next array: wait for this one
+        HIP_TRY(s, hipStreamSynchronize(s->stream));
+        return TITAN_OK;
+    };
+    int rc = TITAN_OK;
+    if (k) {
+        bool uniform = count == s->ns;
+        for (int64_t q = 0; q < s->ns && uniform; ++q)
+            uniform = s->h_k[q] == s->h_k[0];
+        if (!g.k && uniform && s->ns > 0)
+            g.k_uniform = s->h_k[0];
+        else
+            rc = apply(&g.k, g.k_uniform, [&](int64_t q) { return s->h_k[q]; });
+    }
+    if (!rc && damping) {
+        bool uniform = true;
+        for (int64_t q = 0; q < s->ns && uniform; ++q)
+            uniform = s->h_damp[q] == s->h_damp[0];
+        if (!g.c && uniform && s->ns > 0)
+            g.c_uniform = s->h_damp[0];
+        else
+            rc = apply(&g.c, g.c_uniform, [&](int64_t q) { return s->h_damp[q]; });
+    }
+    if (!rc && amp) {
+        rc = apply(&g.act_c, 0.f, [&](int64_t q) {
+            return (float)((double)s->h_amp[q] * std::cos((double)s->h_phase[q]));
+        });
+        if (!rc)
+            rc = apply(&g.act_s, 0.f, [&](int64_t q) {
+                return (float)((double)s->h_amp[q] * std::sin((double)s->h_phase[q]));
+            });
+    }
+    cleanup();
+    return rc;
 }
 
 StepConsts consts_for(const titan_sim *s, int64_t step, const float2 *trig)
@@ -363,7 +452,7 @@ StepConsts consts_for(const titan_sim *s, int64_t step, const float2 *trig)
 
 int enqueue_steps(titan_sim *s, int64_t first_step, int64_t count)
 {
-    if (s->engine == TITAN_ENGINE_BATCHED && s->batch)
+    if (s->engine == TITAN_ENGINE_BATCHED && s->batch && s->batch_step)
         return enqueue_batch_steps(s, first_step, count);
     for (int64_t c0 = 0; c0 < count; c0 += kTrigChunk) {
         const int nc = (int)std::min<int64_t>(kTrigChunk, count - c0);

@@ -141,7 +141,37 @@ __global__ void trig_table_kernel(float2 *trig, int64_t first, int count, double
     trig[s] = make_float2((float)sin(ph), (float)cos(ph));
 }
 
+__global__ void scatter_kernel(float *dst, const int64_t *slot, const float *val, int64_t m)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < m)
+        dst[slot[q]] = val[q];
+}
+
+__global__ void fill_kernel(float *dst, float v, int64_t m)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < m)
+        dst[q] = v;
+}
+
 }  // namespace
+
+hipError_t launch_scatter(float *dst, const int64_t *slot, const float *val, int64_t m, hipStream_t stream)
+{
+    if (m <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, dst, slot, val, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float *dst, float v, int64_t m, hipStream_t stream)
+{
+    if (m <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, dst, v, m);
+    return hipGetLastError();
+}
 
 hipError_t launch_trig_table(float2 *trig, int64_t first, int count, double omega, double dt, hipStream_t stream)
 {

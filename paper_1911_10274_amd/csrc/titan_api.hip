@@ -715,6 +715,53 @@ extern "C" int titan_get_forces(titan_sim *s, int64_t first, int64_t count, floa
     return TITAN_OK;
 }
 
+extern "C" int titan_set_springs(titan_sim *s, int64_t first, int64_t count, const float *k, const float *damping,
+                                 const float *amp, const float *phase)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (first < 0 || count < 0 || first + count > (int64_t)s->h_k.size())
+        return fail(TITAN_EINVAL, "spring range [%lld, %lld) outside [0, %lld)", (long long)first,
+                    (long long)(first + count), (long long)s->h_k.size());
+    if ((amp == nullptr) != (phase == nullptr))
+        return fail(TITAN_EINVAL, "amp and phase must be given together");
+    for (int64_t q = 0; q < count; ++q) {
+        if (k && !(std::isfinite(k[q]) && k[q] >= 0.f))
+            return fail(TITAN_EINVAL, "spring %lld: k must be finite and >= 0", (long long)(first + q));
+        if (damping && !(std::isfinite(damping[q]) && damping[q] >= 0.f))
+            return fail(TITAN_EINVAL, "spring %lld: damping must be finite and >= 0", (long long)(first + q));
+        if (amp && !(std::isfinite(amp[q]) && std::isfinite(phase[q])))
+            return fail(TITAN_EINVAL, "spring %lld: non-finite actuation", (long long)(first + q));
+    }
+    for (int64_t q = 0; q < count; ++q) {
+        if (k)
+            s->h_k[first + q] = k[q];
+        if (damping)
+            s->h_damp[first + q] = damping[q];
+        if (amp) {
+            s->h_amp[first + q] = amp[q];
+            s->h_phase[first + q] = phase[q];
+        }
+    }
+    if (!s->finalized)
+        return TITAN_OK;
+    if (int rc = ready(s))
+        return rc;
+    return update_springs(s, first, count, k, damping, amp, phase);
+}
+
+extern "C" int titan_rollout_grad(titan_sim *s, int64_t nsteps, int32_t checkpoint_every, const float *body_weights,
+                                  float *loss_out, float *grad_k, float *grad_act_c, float *grad_act_s)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (int rc = ready(s))
+        return rc;
+    return rollout_grad(s, nsteps, checkpoint_every, body_weights, loss_out, grad_k, grad_act_c, grad_act_s);
+}
+
 extern "C" int titan_get_info(titan_sim *s, titan_info *info)
 {
     if (!s || !info)

@@ -83,6 +83,10 @@ struct StateIO {
     unsigned long long *first_bad;   // min step index that produced a non-finite value
 };
 
+// dst[slot[q]] = val[q] for q < m; dst[q] = v for q < m.
+hipError_t launch_scatter(float *dst, const int64_t *slot, const float *val, int64_t m, hipStream_t stream);
+hipError_t launch_fill(float *dst, float v, int64_t m, hipStream_t stream);
+
 // Batched engine: independent groups of whole bodies, each stepped by one
 // workgroup with its state resident in LDS.  Group q owns internal masses
 // [mass_off[q], mass_off[q+1]); nbr_group holds, per incidence slot of the
@@ -102,6 +106,28 @@ constexpr int kBatchThreadChoices[] = {256, 512, 1024};
 // sc.trig points at the clock entry of step0.
 hipError_t launch_batch(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc,
                         int nsteps, int threads, hipStream_t stream);
+
+// Buffers of one adjoint rollout (internal order, n = masses).
+struct AdjointIO {
+    const float4 *U0, *V0;    // starting state
+    float4 *ckU, *ckV;        // [ceil(nsteps/K) * n] checkpoints (state at steps 0, K, 2K, ...)
+    float4 *segU, *segV;      // [K * n] states of the segment being reversed
+    float4 *gslot;            // [slots] (dJ/dk, dJ/dC, dJ/dS, 0) on each spring's owner slot; zeroed
+    const float *seed;        // [n] dJ/dx_N (x component)
+    float *dux;               // [n] x-displacement over the rollout
+    const float2 *trig;       // clock entries of rollout steps 0 .. nsteps-1
+    unsigned long long *first_bad;
+    int nsteps, K;
+};
+
+hipError_t launch_adjoint(const GatherGraph &g, const BatchLayout &b, const AdjointIO &a, const StepConsts &sc,
+                          hipStream_t stream);
+// gk[s] = gslot[owner_slot[s]].x etc. (caller spring order)
+hipError_t launch_spring_grads(const float4 *gslot, const int64_t *owner_slot, int64_t ns, float *gk, float *gC,
+                               float *gS, hipStream_t stream);
+// loss[b] = -sum over internal masses [body_off[b], body_off[b+1]) of coef * dux
+hipError_t launch_body_loss(const float *dux, const float *coef, const int64_t *body_off, int64_t nb, float *loss,
+                            hipStream_t stream);
 
 // Launch one step (or, with forces_only, only the spring-force sum).  tiled:
 // stage each tile's masses and halo in LDS (needs nbr_local); otherwise every

@@ -61,11 +61,15 @@ struct titan_sim {
     // gather engine
     titan::GatherGraph gg{};
     bool tiled = false;  // gather engine runs the LDS-tiled kernel
+    int64_t n_slots = 0;  // incidence slots of the gather layout
     std::vector<int32_t> h_slot_nbr;  // per-slot neighbour (internal), kept only during finalize
+    std::vector<int64_t> h_owner_slot;  // per spring (caller order): its slot at the lower-index end
+    std::vector<int64_t> h_other_slot;  // per spring: its slot at the other end
     float2 *trig = nullptr;           // clock table: kTrigChunk entries + 1 for force queries
 
     // batched engine (null unless selected) and the tuner's measurements
     titan::BatchEngine *batch = nullptr;
+    bool batch_step = false;  // the batched engine steps the system
     float tune_batch_ms = 0.f;   // per step, best batched workgroup size
     float tune_gather_ms = 0.f;  // per step, gather engine (AUTO only)
 
@@ -87,6 +91,10 @@ int hip_fail(titan_sim *sim, hipError_t e, const char *what);
 int dev_alloc(titan_sim *s, size_t bytes, void **out);
 void dev_free(titan_sim *s, void *p);
 int batch_threads(const titan_sim *s);
+int update_springs(titan_sim *s, int64_t first, int64_t count, const float *k, const float *damping,
+                   const float *amp, const float *phase);
+int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weights, float *loss, float *gk,
+                 float *gC, float *gS);
 
 // Engines (engine_gather.hip): build the device representation of the
 // selected engine after the state buffers exist, enqueue steps, compute the

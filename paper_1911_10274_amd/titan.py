@@ -115,6 +115,8 @@ def _load():
         "titan_set_state": ([_vp, ctypes.c_int64, ctypes.c_int64, _fp, _fp, ctypes.c_int32], ctypes.c_int),
         "titan_get_forces": ([_vp, ctypes.c_int64, ctypes.c_int64, _fp], ctypes.c_int),
         "titan_set_step": ([_vp, ctypes.c_int64], ctypes.c_int),
+        "titan_set_springs": ([_vp, ctypes.c_int64, ctypes.c_int64, _fp, _fp, _fp, _fp], ctypes.c_int),
+        "titan_rollout_grad": ([_vp, ctypes.c_int64, ctypes.c_int32, _fp, _fp, _fp, _fp, _fp], ctypes.c_int),
         "titan_get_info": ([_vp, ctypes.POINTER(_Info)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -322,6 +324,32 @@ class Sim:
         v, vp = _f32(vel, (-1, 3)) if vel is not None else (None, None)
         count = (p if p is not None else v).shape[0]
         _check(lib.titan_set_state(self._h, first, count, pp, vp, STATE_DISPLACEMENT if displacement else 0))
+
+    def set_springs(self, first: int = 0, k=None, damping=None, amp=None, phase=None):
+        """Change spring constants (see titan_set_springs)."""
+        arrs = [a for a in (k, damping, amp, phase) if a is not None]
+        if not arrs:
+            return
+        count = int(np.asarray(arrs[0]).size)
+        ptrs, keep = [], []
+        for a in (k, damping, amp, phase):
+            arr, p = _f32(a, (count,)) if a is not None else (None, None)
+            keep.append(arr)
+            ptrs.append(p)
+        _check(lib.titan_set_springs(self._h, int(first), count, *ptrs))
+
+    def rollout_grad(self, nsteps: int, checkpoint_every: int = 50, body_weights=None):
+        """Adjoint gradient of J = sum_b w_b J_b (J_b = -CoM x-displacement of
+        body b after ``nsteps`` steps from the current state).  Returns
+        (loss per body, dJ/dk, dJ/dC, dJ/dS) as numpy arrays."""
+        info = self.info()
+        nb, ns = info["n_bodies"], info["n_springs"]
+        w, wp = _f32(body_weights, (nb,)) if body_weights is not None else (None, None)
+        loss = np.empty(nb, np.float32)
+        gk, gc, gs = (np.empty(ns, np.float32) for _ in range(3))
+        _check(lib.titan_rollout_grad(self._h, int(nsteps), int(checkpoint_every), wp, loss.ctypes.data_as(_fp),
+                                      gk.ctypes.data_as(_fp), gc.ctypes.data_as(_fp), gs.ctypes.data_as(_fp)))
+        return loss, gk, gc, gs
 
     def set_step(self, step: int):
         _check(lib.titan_set_step(self._h, int(step)))
