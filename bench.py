@@ -190,6 +190,41 @@ def bench_batched(T, robots_n: int, steps: int, loop_sample: int):
     return res
 
 
+def bench_adjoint(T, robots_n: int, steps: int, K: int):
+    """Gradient of the 500-step rollout loss (-CoM x-displacement) of 256
+    voxel robots with respect to every spring's stiffness and actuation, by
+    the checkpointed adjoint; timed against the forward rollout alone."""
+    import time as _t
+
+    import torch
+
+    from paper_1911_10274_amd import scenes
+
+    robots = scenes.robot_batch(robots_n, seed=4, side_lo=4, side_hi=8)
+    sc = scenes.concat(robots)
+    nm, ns = sc["pos"].shape[0], sc["ends"].shape[0]
+    tp = T.Params(dt=1e-4, gravity=(0.0, 0.0, -9.81), ground=True, ground_k=1e5, friction_mu=0.5,
+                  omega=2 * math.pi * 2, engine=T.ENGINE_BATCHED)
+    sim = T.sim_from_scene(sc, tp)
+    sim.finalize()
+    sim.rollout_grad(steps, K)  # warm-up
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = _t.perf_counter()
+    for _ in range(reps):
+        sim.rollout_grad(steps, K)
+    sec = (_t.perf_counter() - t0) / reps
+    ms_fwd = _timed_steps(sim, steps, torch.cuda.current_stream())
+    sim.close()
+    return {"workload": f"{robots_n} voxel robots, side U{{4..8}}, {steps}-step rollout, checkpoints every {K} "
+                        f"steps, gradients w.r.t. every spring's k and actuation phasor",
+            "robots": robots_n, "masses": nm, "springs": ns, "steps": steps, "checkpoint_every": K,
+            "value": steps / sec, "unit": "adjoint steps/s",
+            "robot_steps_per_s": robots_n * steps / sec,
+            "ms_per_gradient": sec * 1e3,
+            "forward_ms": ms_fwd, "gradient_over_forward": sec * 1e3 / ms_fwd}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +239,7 @@ def main():
     ap.add_argument("--robots", type=int, default=4096, help="voxel robots in the batched workload (0: skip)")
     ap.add_argument("--robot-steps", type=int, default=2000)
     ap.add_argument("--loop-sample", type=int, default=32)
+    ap.add_argument("--adjoint-robots", type=int, default=256, help="robots in the adjoint workload (0: skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -287,6 +323,8 @@ def main():
     sim.close()
     if args.robots > 0:
         out["batched"] = bench_batched(T, args.robots, args.robot_steps, args.loop_sample)
+    if args.adjoint_robots > 0:
+        out["adjoint"] = bench_adjoint(T, args.adjoint_robots, 500, 50)
     print(json.dumps(out))
 
 

@@ -248,6 +248,49 @@ int titan_get_forces(titan_sim *sim, int64_t first, int64_t count, float *f_n3);
 /* Fill *info. */
 int titan_get_info(titan_sim *sim, titan_info *info);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate: a multilayer perceptron trained on the simulator's own
+ * rollouts to predict a robot's centre-of-mass displacement from its layout
+ * and actuation, used to screen candidates before simulating them.
+ * Layers l = 0..L-1: z = x W_l^T + b_l; hidden layers apply GELU (exact erf
+ * form), the last is linear.  GEMMs run on BF16 matrix cores with FP32
+ * accumulation; weights and activations are rounded to bfloat16 for them,
+ * master weights and Adam moments stay FP32.  Loss: mean squared error.
+ * Parameters are one flat FP32 array: W_0 (dims[1] x dims[0], row-major),
+ * b_0 (dims[1]), W_1, b_1, ...
+ * ------------------------------------------------------------------------ */
+typedef struct titan_mlp titan_mlp;
+
+/* Create a network of n_layers layers with widths dims[0..n_layers]
+ * (1..65536 each).  stream / alloc as in titan_create.  Parameters start at
+ * zero: set them with titan_mlp_set_params. */
+int titan_mlp_create(int32_t n_layers, const int32_t *dims, void *stream, const titan_allocator *alloc,
+                     titan_mlp **out);
+int titan_mlp_destroy(titan_mlp *mlp);
+/* Number of parameters (length of the flat array), or -1 for NULL. */
+int64_t titan_mlp_param_count(titan_mlp *mlp);
+/* Copy all parameters in (resets the Adam state) or out. */
+int titan_mlp_set_params(titan_mlp *mlp, const float *params);
+int titan_mlp_get_params(titan_mlp *mlp, float *params);
+/* Keep a training set on the device: X (n x dims[0], stored as bfloat16),
+ * Y (n x dims[L], FP32 targets).  Replaces any previous set. */
+int titan_mlp_set_data(titan_mlp *mlp, int64_t n, const float *X, const float *Y);
+/* nsteps Adam steps (learning rate lr, beta1, beta2, eps) on mini-batches of
+ * `batch` rows of the training set; idx (nsteps x batch) lists the rows of
+ * each step.  loss_out (nsteps, may be NULL) receives each step's loss. */
+int titan_mlp_train(titan_mlp *mlp, int64_t nsteps, int32_t batch, const int64_t *idx, float lr, float beta1,
+                    float beta2, float eps, float *loss_out);
+/* Outputs (n x dims[L]) for inputs X (n x dims[0]). */
+int titan_mlp_predict(titan_mlp *mlp, int64_t n, const float *X, float *out);
+/* Loss and the gradient of every parameter (flat layout) on one batch. */
+int titan_mlp_grad(titan_mlp *mlp, int32_t batch, const float *X, const float *Y, float *loss, float *grads);
+/* The GEMM alone, on device arrays: C (M x N, FP32, row-major) = op(A) op(B)
+ * with op(A)[m][k] = ta ? A[k*lda + m] : A[m*lda + k] and
+ * op(B)[k][n] = tb ? B[n*ldb + k] : B[k*ldb + n] (bfloat16 bit patterns).
+ * Asynchronous on `stream`. */
+int titan_mlp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t *A_dev, int32_t lda, int32_t ta,
+                        const uint16_t *B_dev, int32_t ldb, int32_t tb, float *C_dev, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

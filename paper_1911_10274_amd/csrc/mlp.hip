@@ -1,0 +1,688 @@
+// Surrogate MLP: BF16 matrix-core (MFMA) GEMMs with FP32 accumulation and
+// fused epilogues, its backward pass and Adam, behind the titan_mlp_* C ABI.
+//
+// Network: x_0 = input; hidden layers z_l = x_l W_l^T + b_l,
+// x_{l+1} = GELU(z_l) (exact erf form); the last layer is linear.  Weights
+// and activations are stored in bfloat16 for the GEMMs, pre-activations and
+// the output in FP32; master weights and Adam moments in FP32.  Loss: mean
+// squared error.  Backward: dz_L = 2 (out - y) / (B O);
+// dW_l = dz_l^T x_l, db_l = column sums of dz_l,
+// dz_{l-1} = (dz_l W_l) * GELU'(z_{l-1})  -- the GELU derivative is applied in
+// the epilogue of the dgrad GEMM.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "titan.h"
+#include "titan_sim.h"
+
+namespace titan {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad(float z)
+{
+    return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+enum Epi { EPI_BIAS_GELU = 1, EPI_BIAS = 2, EPI_GELU_BWD = 3, EPI_F32 = 4 };
+
+struct GemmEpi {
+    const float *bias;  // [N]
+    float *Z;           // fp32 out (pre-activation / output / C), row stride ldz
+    const float *Zin;   // fp32 pre-activation read by EPI_GELU_BWD, row stride ldz
+    uint16_t *Yb;       // bf16 out, row stride ldy
+    int ldz, ldy;
+};
+
+constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;
+
+// C[M,N] = A[M,K] B[K,N] with A(m,k) = TA ? A[k*lda + m] : A[m*lda + k] and
+// B(k,n) = TB ? B[n*ldb + k] : B[k*ldb + n], all bf16; FP32 accumulate on
+// v_mfma_f32_32x32x16_bf16.  A 64x64 tile per workgroup, 32x32 per wave.
+// Tiles are staged in LDS with K contiguous per row (A) or column (B), so
+// each lane's 8 K-values of an MFMA operand are one 16-byte LDS read.
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const uint16_t *__restrict__ A, int lda,
+                                                   const uint16_t *__restrict__ Bm, int ldb, GemmEpi ep)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t sA[BM * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[BN * LDK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int wm = wave >> 1, wn = wave & 1;
+    f32x16_t acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        // A tile -> sA[m][k]
+        if (!TA) {
+            const int r = tid >> 2, c = (tid & 3) * 8;
+            const int m = m0 + r;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = k0 + c + e;
+                sA[r * LDK + c + e] = (m < M && k < K) ? A[(int64_t)m * lda + k] : (uint16_t)0;
+            }
+        } else {
+            const int kk = tid >> 3, c = (tid & 7) * 8;
+            const int k = k0 + kk;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int m = m0 + c + e;
+                sA[(c + e) * LDK + kk] = (m < M && k < K) ? A[(int64_t)k * lda + m] : (uint16_t)0;
+            }
+        }
+        // B tile -> sB[n][k]
+        if (TB) {
+            const int r = tid >> 2, c = (tid & 3) * 8;
+            const int n = n0 + r;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = k0 + c + e;
+                sB[r * LDK + c + e] = (n < N && k < K) ? Bm[(int64_t)n * ldb + k] : (uint16_t)0;
+            }
+        } else {
+            const int kk = tid >> 3, c = (tid & 7) * 8;
+            const int k = k0 + kk;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int n = n0 + c + e;
+                sB[(c + e) * LDK + kk] = (n < N && k < K) ? Bm[(int64_t)k * ldb + n] : (uint16_t)0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+            const bf16x8_t a = *(const bf16x8_t *)&sA[(wm * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5)];
+            const bf16x8_t b = *(const bf16x8_t *)&sB[(wn * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5)];
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    // D layout of the 32x32 MFMA: lane l holds column l % 32 and, for
+    // r = 0..15, row 8 (r / 4) + 4 (l / 32) + r % 4.
+    const int j = n0 + wn * 32 + (lane & 31);
+    if (j >= N)
+        return;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (i >= M)
+            continue;
+        const float v = acc[r];
+        if (EPI == EPI_BIAS_GELU) {
+            const float z = v + ep.bias[j];
+            ep.Z[(int64_t)i * ep.ldz + j] = z;
+            ep.Yb[(int64_t)i * ep.ldy + j] = f2bf(gelu(z));
+        } else if (EPI == EPI_BIAS) {
+            ep.Z[(int64_t)i * ep.ldz + j] = v + ep.bias[j];
+        } else if (EPI == EPI_GELU_BWD) {
+            ep.Yb[(int64_t)i * ep.ldy + j] = f2bf(v * gelu_grad(ep.Zin[(int64_t)i * ep.ldz + j]));
+        } else {
+            ep.Z[(int64_t)i * ep.ldz + j] = v;
+        }
+    }
+}
+
+template <bool TA, bool TB, int EPI>
+hipError_t gemm(int M, int N, int K, const uint16_t *A, int lda, const uint16_t *B, int ldb, const GemmEpi &ep,
+                hipStream_t st)
+{
+    if (M <= 0 || N <= 0)
+        return hipSuccess;
+    const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM));
+    hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, ep);
+    return hipGetLastError();
+}
+
+__global__ void to_bf16_kernel(const float *x, uint16_t *y, int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n)
+        y[q] = f2bf(x[q]);
+}
+
+__global__ void gather_rows_kernel(const uint16_t *X, const float *Y, const int64_t *idx, int B, int in, int out,
+                                   uint16_t *xb, float *yb)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nx = (int64_t)B * in;
+    if (q < nx) {
+        const int64_t b = q / in, c = q % in;
+        xb[q] = X[idx[b] * in + c];
+    } else if (q < nx + (int64_t)B * out) {
+        const int64_t r = q - nx, b = r / out, c = r % out;
+        yb[r] = Y[idx[b] * out + c];
+    }
+}
+
+// dz = bf16(2 (out - y) / (B O)); loss = mean (out - y)^2.  One workgroup, a
+// fixed summation order: deterministic.
+__global__ __launch_bounds__(256) void mse_kernel(const float *out, const float *y, int64_t n, uint16_t *dz,
+                                                  float *loss)
+{
+    __shared__ float red[256];
+    const int t = threadIdx.x;
+    float acc = 0.f;
+    for (int64_t q = t; q < n; q += 256) {
+        const float d = out[q] - y[q];
+        acc = fmaf(d, d, acc);
+        dz[q] = f2bf(2.f * d / (float)n);
+    }
+    red[t] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s)
+            red[t] += red[t + s];
+        __syncthreads();
+    }
+    if (t == 0)
+        *loss = red[0] / (float)n;
+}
+
+// db[j] = sum over the batch of dz[b][j] (one thread per column, in order)
+__global__ void bias_grad_kernel(const uint16_t *dz, int B, int N, float *db)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N)
+        return;
+    float acc = 0.f;
+    for (int b = 0; b < B; ++b)
+        acc += bf2f(dz[(int64_t)b * N + j]);
+    db[j] = acc;
+}
+
+__global__ void adam_kernel(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
+                            float eps, float bc1, float bc2)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n)
+        return;
+    const float gq = g[q];
+    const float mq = b1 * m[q] + (1.f - b1) * gq;
+    const float vq = b2 * v[q] + (1.f - b2) * gq * gq;
+    m[q] = mq;
+    v[q] = vq;
+    p[q] -= lr * (mq / bc1) / (sqrtf(vq / bc2) + eps);
+}
+
+hipError_t launch1d(void (*k)(const float *, uint16_t *, int64_t), const float *x, uint16_t *y, int64_t n,
+                    hipStream_t st)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, y, n);
+    return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace titan
+
+using namespace titan;
+
+// ---------------------------------------------------------------------------
+// the titan_mlp object
+// ---------------------------------------------------------------------------
+
+struct titan_mlp {
+    std::mutex mu;
+    hipStream_t stream = nullptr;
+    titan_allocator alloc{};
+    std::vector<std::pair<void *, size_t>> allocations;
+    int device = 0;
+    std::vector<int32_t> dims;        // n_layers + 1
+    std::vector<int64_t> woff, boff;  // offsets of W_l, b_l in the flat parameter array
+    std::vector<int64_t> wboff;       // offsets of W_l in the bf16 weight array
+    int64_t nparam = 0, nw = 0;
+    float *P = nullptr, *G = nullptr, *Mo = nullptr, *Vo = nullptr;  // params, grads, Adam moments
+    uint16_t *Wb = nullptr;                                          // bf16 weights
+    int64_t adam_t = 0;
+    // dataset
+    int64_t n_data = 0;
+    uint16_t *X = nullptr;
+    float *Y = nullptr;
+    // workspace for batches up to cap
+    int cap = 0;
+    std::vector<uint16_t *> xs;  // x_l, l = 0..L-1 (bf16)
+    std::vector<float *> zs;     // z_l (fp32)
+    uint16_t *dz[2] = {nullptr, nullptr};
+    float *yb = nullptr;
+    int64_t *idx = nullptr;
+    float *loss = nullptr;
+    int loss_cap = 0;
+    int L() const { return (int)dims.size() - 1; }
+};
+
+static int mlp_alloc(titan_mlp *m, size_t bytes, void **out)
+{
+    *out = nullptr;
+    bytes = std::max<size_t>(bytes, 256);
+    void *p = nullptr;
+    if (m->alloc.alloc) {
+        p = m->alloc.alloc(bytes, m->alloc.ctx);
+        if (!p)
+            return fail(TITAN_ENOMEM, "device allocator returned NULL for %zu bytes", bytes);
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(TITAN_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        }
+    }
+    m->allocations.push_back({p, bytes});
+    *out = p;
+    return TITAN_OK;
+}
+
+static void mlp_free(titan_mlp *m, void *p)
+{
+    for (size_t q = 0; q < m->allocations.size(); ++q)
+        if (m->allocations[q].first == p) {
+            (void)hipStreamSynchronize(m->stream);
+            if (m->alloc.release)
+                m->alloc.release(p, m->alloc.ctx);
+            else
+                (void)hipFree(p);
+            m->allocations.erase(m->allocations.begin() + q);
+            return;
+        }
+}
+
+#define MLP_TRY(expr)                                                         \
+    do {                                                                      \
+        hipError_t e_ = (expr);                                               \
+        if (e_ != hipSuccess)                                                 \
+            return fail(TITAN_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+static int ensure_cap(titan_mlp *m, int B)
+{
+    if (B <= m->cap)
+        return TITAN_OK;
+    for (auto *p : m->xs)
+        mlp_free(m, p);
+    for (auto *p : m->zs)
+        mlp_free(m, p);
+    for (auto *p : {(void *)m->dz[0], (void *)m->dz[1], (void *)m->yb, (void *)m->idx})
+        if (p)
+            mlp_free(m, p);
+    m->xs.assign(m->L(), nullptr);
+    m->zs.assign(m->L(), nullptr);
+    int maxd = 0;
+    for (int d : m->dims)
+        maxd = std::max(maxd, d);
+    for (int l = 0; l < m->L(); ++l) {
+        if (int rc = mlp_alloc(m, sizeof(uint16_t) * (size_t)B * m->dims[l], (void **)&m->xs[l]))
+            return rc;
+        if (int rc = mlp_alloc(m, sizeof(float) * (size_t)B * m->dims[l + 1], (void **)&m->zs[l]))
+            return rc;
+    }
+    for (int q = 0; q < 2; ++q)
+        if (int rc = mlp_alloc(m, sizeof(uint16_t) * (size_t)B * maxd, (void **)&m->dz[q]))
+            return rc;
+    if (int rc = mlp_alloc(m, sizeof(float) * (size_t)B * m->dims.back(), (void **)&m->yb))
+        return rc;
+    if (int rc = mlp_alloc(m, sizeof(int64_t) * (size_t)B, (void **)&m->idx))
+        return rc;
+    m->cap = B;
+    return TITAN_OK;
+}
+
+static int refresh_bf16(titan_mlp *m)
+{
+    for (int l = 0; l < m->L(); ++l)
+        MLP_TRY(launch1d(to_bf16_kernel, m->P + m->woff[l], m->Wb + m->wboff[l],
+                         (int64_t)m->dims[l] * m->dims[l + 1], m->stream));
+    return TITAN_OK;
+}
+
+// Forward of a batch already in xs[0]; output in zs[L-1].
+static int forward(titan_mlp *m, int B)
+{
+    const int L = m->L();
+    for (int l = 0; l < L; ++l) {
+        const int in = m->dims[l], out = m->dims[l + 1];
+        GemmEpi ep{};
+        ep.bias = m->P + m->boff[l];
+        ep.Z = m->zs[l];
+        ep.ldz = out;
+        if (l < L - 1) {
+            ep.Yb = m->xs[l + 1];
+            ep.ldy = out;
+            MLP_TRY((gemm<false, true, EPI_BIAS_GELU>(B, out, in, m->xs[l], in, m->Wb + m->wboff[l], in, ep, m->stream)));
+        } else {
+            MLP_TRY((gemm<false, true, EPI_BIAS>(B, out, in, m->xs[l], in, m->Wb + m->wboff[l], in, ep, m->stream)));
+        }
+    }
+    return TITAN_OK;
+}
+
+// Loss and gradients of a batch in xs[0] / yb; loss value to *loss_dev.
+static int backward(titan_mlp *m, int B, float *loss_dev)
+{
+    const int L = m->L();
+    if (int rc = forward(m, B))
+        return rc;
+    const int O = m->dims[L];
+    hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(256), 0, m->stream, m->zs[L - 1], m->yb, (int64_t)B * O, m->dz[0],
+                       loss_dev);
+    MLP_TRY(hipGetLastError());
+    int cur = 0;
+    for (int l = L - 1; l >= 0; --l) {
+        const int in = m->dims[l], out = m->dims[l + 1];
+        uint16_t *dz = m->dz[cur];
+        GemmEpi ew{};
+        ew.Z = m->G + m->woff[l];
+        ew.ldz = in;
+        MLP_TRY((gemm<true, false, EPI_F32>(out, in, B, dz, out, m->xs[l], in, ew, m->stream)));
+        hipLaunchKernelGGL(bias_grad_kernel, dim3((out + 255) / 256), dim3(256), 0, m->stream, dz, B, out,
+                           m->G + m->boff[l]);
+        MLP_TRY(hipGetLastError());
+        if (l > 0) {
+            GemmEpi ed{};
+            ed.Zin = m->zs[l - 1];
+            ed.ldz = in;
+            ed.Yb = m->dz[1 - cur];
+            ed.ldy = in;
+            MLP_TRY((gemm<false, false, EPI_GELU_BWD>(B, in, out, dz, out, m->Wb + m->wboff[l], in, ed, m->stream)));
+            cur = 1 - cur;
+        }
+    }
+    return TITAN_OK;
+}
+
+static int upload_batch_f32(titan_mlp *m, int B, const float *X, const float *Y)
+{
+    const int in = m->dims[0];
+    float *tmp = nullptr;
+    if (int rc = mlp_alloc(m, sizeof(float) * (size_t)B * in, (void **)&tmp))
+        return rc;
+    MLP_TRY(hipMemcpyAsync(tmp, X, sizeof(float) * (size_t)B * in, hipMemcpyHostToDevice, m->stream));
+    MLP_TRY(launch1d(to_bf16_kernel, tmp, m->xs[0], (int64_t)B * in, m->stream));
+    if (Y)
+        MLP_TRY(hipMemcpyAsync(m->yb, Y, sizeof(float) * (size_t)B * m->dims.back(), hipMemcpyHostToDevice,
+                               m->stream));
+    MLP_TRY(hipStreamSynchronize(m->stream));
+    mlp_free(m, tmp);
+    return TITAN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+
+extern "C" int titan_mlp_create(int32_t n_layers, const int32_t *dims, void *stream, const titan_allocator *alloc,
+                                titan_mlp **out)
+{
+    if (!out || !dims || n_layers < 1 || n_layers > 64)
+        return fail(TITAN_EINVAL, "need out, dims and 1..64 layers");
+    *out = nullptr;
+    for (int l = 0; l <= n_layers; ++l)
+        if (dims[l] < 1 || dims[l] > (1 << 16))
+            return fail(TITAN_EINVAL, "layer width %d out of range", dims[l]);
+    if (alloc && (!alloc->alloc || !alloc->release))
+        return fail(TITAN_EINVAL, "allocator needs both alloc and release");
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
+        (void)hipGetLastError();
+        return fail(TITAN_EDEVICE, "no usable HIP device");
+    }
+    titan_mlp *m = new (std::nothrow) titan_mlp();
+    if (!m)
+        return fail(TITAN_ENOMEM, "out of host memory");
+    m->stream = (hipStream_t)stream;
+    if (alloc)
+        m->alloc = *alloc;
+    (void)hipGetDevice(&m->device);
+    m->dims.assign(dims, dims + n_layers + 1);
+    int64_t off = 0, wb = 0;
+    for (int l = 0; l < n_layers; ++l) {
+        m->woff.push_back(off);
+        off += (int64_t)dims[l] * dims[l + 1];
+        m->boff.push_back(off);
+        off += dims[l + 1];
+        m->wboff.push_back(wb);
+        wb += (int64_t)dims[l] * dims[l + 1];
+    }
+    m->nparam = off;
+    m->nw = wb;
+    int rc = TITAN_OK;
+    if ((rc = mlp_alloc(m, sizeof(float) * off, (void **)&m->P)) || (rc = mlp_alloc(m, sizeof(float) * off, (void **)&m->G)) ||
+        (rc = mlp_alloc(m, sizeof(float) * off, (void **)&m->Mo)) ||
+        (rc = mlp_alloc(m, sizeof(float) * off, (void **)&m->Vo)) ||
+        (rc = mlp_alloc(m, sizeof(uint16_t) * wb, (void **)&m->Wb))) {
+        titan_mlp_destroy(m);
+        return rc;
+    }
+    if (hipMemsetAsync(m->P, 0, sizeof(float) * off, m->stream) != hipSuccess ||
+        hipMemsetAsync(m->Mo, 0, sizeof(float) * off, m->stream) != hipSuccess ||
+        hipMemsetAsync(m->Vo, 0, sizeof(float) * off, m->stream) != hipSuccess) {
+        titan_mlp_destroy(m);
+        return fail(TITAN_EDEVICE, "hipMemsetAsync failed");
+    }
+    *out = m;
+    return TITAN_OK;
+}
+
+extern "C" int titan_mlp_destroy(titan_mlp *m)
+{
+    if (!m)
+        return TITAN_OK;
+    {
+        std::lock_guard<std::mutex> lk(m->mu);
+        (void)hipStreamSynchronize(m->stream);
+        for (auto &a : m->allocations) {
+            if (m->alloc.release)
+                m->alloc.release(a.first, m->alloc.ctx);
+            else
+                (void)hipFree(a.first);
+        }
+        m->allocations.clear();
+    }
+    delete m;
+    return TITAN_OK;
+}
+
+extern "C" int64_t titan_mlp_param_count(titan_mlp *m) { return m ? m->nparam : -1; }
+
+extern "C" int titan_mlp_set_params(titan_mlp *m, const float *params)
+{
+    if (!m || !params)
+        return fail(TITAN_EINVAL, "mlp or params is NULL");
+    std::lock_guard<std::mutex> lk(m->mu);
+    for (int64_t q = 0; q < m->nparam; ++q)
+        if (!std::isfinite(params[q]))
+            return fail(TITAN_EINVAL, "parameter %lld is not finite", (long long)q);
+    MLP_TRY(hipMemcpyAsync(m->P, params, sizeof(float) * m->nparam, hipMemcpyHostToDevice, m->stream));
+    MLP_TRY(hipMemsetAsync(m->Mo, 0, sizeof(float) * m->nparam, m->stream));
+    MLP_TRY(hipMemsetAsync(m->Vo, 0, sizeof(float) * m->nparam, m->stream));
+    m->adam_t = 0;
+    if (int rc = refresh_bf16(m))
+        return rc;
+    MLP_TRY(hipStreamSynchronize(m->stream));
+    return TITAN_OK;
+}
+
+extern "C" int titan_mlp_get_params(titan_mlp *m, float *params)
+{
+    if (!m || !params)
+        return fail(TITAN_EINVAL, "mlp or params is NULL");
+    std::lock_guard<std::mutex> lk(m->mu);
+    MLP_TRY(hipMemcpyAsync(params, m->P, sizeof(float) * m->nparam, hipMemcpyDeviceToHost, m->stream));
+    MLP_TRY(hipStreamSynchronize(m->stream));
+    return TITAN_OK;
+}
+
+extern "C" int titan_mlp_set_data(titan_mlp *m, int64_t n, const float *X, const float *Y)
+{
+    if (!m || n < 0 || (n > 0 && (!X || !Y)))
+        return fail(TITAN_EINVAL, "bad dataset arguments");
+    std::lock_guard<std::mutex> lk(m->mu);
+    const int in = m->dims[0], out = m->dims.back();
+    if (m->X)
+        mlp_free(m, m->X);
+    if (m->Y)
+        mlp_free(m, m->Y);
+    m->X = nullptr;
+    m->Y = nullptr;
+    m->n_data = 0;
+    if (int rc = mlp_alloc(m, sizeof(uint16_t) * (size_t)std::max<int64_t>(n, 1) * in, (void **)&m->X))
+        return rc;
+    if (int rc = mlp_alloc(m, sizeof(float) * (size_t)std::max<int64_t>(n, 1) * out, (void **)&m->Y))
+        return rc;
+    // convert in chunks through an FP32 staging buffer
+    const int64_t chunk = 16384;
+    float *tmp = nullptr;
+    if (int rc = mlp_alloc(m, sizeof(float) * (size_t)chunk * in, (void **)&tmp))
+        return rc;
+    for (int64_t a = 0; a < n; a += chunk) {
+        const int64_t c = std::min(chunk, n - a);
+        MLP_TRY(hipMemcpyAsync(tmp, X + a * in, sizeof(float) * (size_t)c * in, hipMemcpyHostToDevice, m->stream));
+        MLP_TRY(launch1d(to_bf16_kernel, tmp, m->X + a * in, c * in, m->stream));
+        MLP_TRY(hipStreamSynchronize(m->stream));
+    }
+    mlp_free(m, tmp);
+    if (n)
+        MLP_TRY(hipMemcpyAsync(m->Y, Y, sizeof(float) * (size_t)n * out, hipMemcpyHostToDevice, m->stream));
+    MLP_TRY(hipStreamSynchronize(m->stream));
+    m->n_data = n;
+    return TITAN_OK;
+}
+
+extern "C" int titan_mlp_train(titan_mlp *m, int64_t nsteps, int32_t batch, const int64_t *idx, float lr, float beta1,
+                               float beta2, float eps, float *loss_out)
+{
+    if (!m || nsteps < 0 || batch < 1 || (nsteps > 0 && !idx))
+        return fail(TITAN_EINVAL, "bad training arguments");
+    if (!(std::isfinite(lr) && lr >= 0 && beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0))
+        return fail(TITAN_EINVAL, "bad optimiser settings");
+    std::lock_guard<std::mutex> lk(m->mu);
+    if (m->n_data == 0)
+        return fail(TITAN_ESTATE, "no dataset (titan_mlp_set_data)");
+    for (int64_t q = 0; q < nsteps * (int64_t)batch; ++q)
+        if (idx[q] < 0 || idx[q] >= m->n_data)
+            return fail(TITAN_EINVAL, "sample index %lld out of range", (long long)idx[q]);
+    if (int rc = ensure_cap(m, batch))
+        return rc;
+    int64_t *didx = nullptr;
+    float *dloss = nullptr;
+    if (int rc = mlp_alloc(m, sizeof(int64_t) * (size_t)std::max<int64_t>(nsteps * batch, 1), (void **)&didx))
+        return rc;
+    if (int rc = mlp_alloc(m, sizeof(float) * (size_t)std::max<int64_t>(nsteps, 1), (void **)&dloss))
+        return rc;
+    if (nsteps)
+        MLP_TRY(hipMemcpyAsync(didx, idx, sizeof(int64_t) * nsteps * batch, hipMemcpyHostToDevice, m->stream));
+    const int in = m->dims[0], out = m->dims.back();
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const int64_t tot = (int64_t)batch * (in + out);
+        hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, m->stream, m->X,
+                           m->Y, didx + s * batch, batch, in, out, m->xs[0], m->yb);
+        MLP_TRY(hipGetLastError());
+        if (int rc = backward(m, batch, dloss + s))
+            return rc;
+        m->adam_t += 1;
+        const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)m->adam_t));
+        const float bc2 = (float)(1.0 - std::pow((double)beta2, (double)m->adam_t));
+        hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((m->nparam + 255) / 256)), dim3(256), 0, m->stream, m->P,
+                           m->G, m->Mo, m->Vo, m->nparam, lr, beta1, beta2, eps, bc1, bc2);
+        MLP_TRY(hipGetLastError());
+        if (int rc = refresh_bf16(m))
+            return rc;
+    }
+    if (loss_out && nsteps)
+        MLP_TRY(hipMemcpyAsync(loss_out, dloss, sizeof(float) * nsteps, hipMemcpyDeviceToHost, m->stream));
+    MLP_TRY(hipStreamSynchronize(m->stream));
+    mlp_free(m, didx);
+    mlp_free(m, dloss);
+    return TITAN_OK;
+}
+
+extern "C" int titan_mlp_predict(titan_mlp *m, int64_t n, const float *X, float *out)
+{
+    if (!m || n < 0 || (n > 0 && (!X || !out)))
+        return fail(TITAN_EINVAL, "bad predict arguments");
+    std::lock_guard<std::mutex> lk(m->mu);
+    const int in = m->dims[0], O = m->dims.back();
+    const int B = 4096;
+    if (int rc = ensure_cap(m, std::min<int64_t>(std::max<int64_t>(n, 1), B)))
+        return rc;
+    for (int64_t a = 0; a < n; a += m->cap) {
+        const int c = (int)std::min<int64_t>(m->cap, n - a);
+        if (int rc = upload_batch_f32(m, c, X + a * in, nullptr))
+            return rc;
+        if (int rc = forward(m, c))
+            return rc;
+        MLP_TRY(hipMemcpyAsync(out + a * O, m->zs[m->L() - 1], sizeof(float) * (size_t)c * O, hipMemcpyDeviceToHost,
+                               m->stream));
+        MLP_TRY(hipStreamSynchronize(m->stream));
+    }
+    return TITAN_OK;
+}
+
+extern "C" int titan_mlp_grad(titan_mlp *m, int32_t batch, const float *X, const float *Y, float *loss,
+                              float *grads)
+{
+    if (!m || batch < 1 || !X || !Y)
+        return fail(TITAN_EINVAL, "bad gradient arguments");
+    std::lock_guard<std::mutex> lk(m->mu);
+    if (int rc = ensure_cap(m, batch))
+        return rc;
+    if (int rc = upload_batch_f32(m, batch, X, Y))
+        return rc;
+    float *dloss = nullptr;
+    if (int rc = mlp_alloc(m, sizeof(float), (void **)&dloss))
+        return rc;
+    if (int rc = backward(m, batch, dloss))
+        return rc;
+    if (loss)
+        MLP_TRY(hipMemcpyAsync(loss, dloss, sizeof(float), hipMemcpyDeviceToHost, m->stream));
+    if (grads)
+        MLP_TRY(hipMemcpyAsync(grads, m->G, sizeof(float) * m->nparam, hipMemcpyDeviceToHost, m->stream));
+    MLP_TRY(hipStreamSynchronize(m->stream));
+    mlp_free(m, dloss);
+    return TITAN_OK;
+}
+
+extern "C" int titan_mlp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t *A_dev, int32_t lda, int32_t ta,
+                                   const uint16_t *B_dev, int32_t ldb, int32_t tb, float *C_dev, void *stream)
+{
+    if (M < 0 || N < 0 || K < 0 || !A_dev || !B_dev || !C_dev)
+        return fail(TITAN_EINVAL, "bad gemm arguments");
+    GemmEpi ep{};
+    ep.Z = C_dev;
+    ep.ldz = N;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (!ta && !tb)
+        e = gemm<false, false, EPI_F32>(M, N, K, A_dev, lda, B_dev, ldb, ep, st);
+    else if (!ta && tb)
+        e = gemm<false, true, EPI_F32>(M, N, K, A_dev, lda, B_dev, ldb, ep, st);
+    else if (ta && !tb)
+        e = gemm<true, false, EPI_F32>(M, N, K, A_dev, lda, B_dev, ldb, ep, st);
+    else
+        e = gemm<true, true, EPI_F32>(M, N, K, A_dev, lda, B_dev, ldb, ep, st);
+    if (e != hipSuccess)
+        return fail(TITAN_EDEVICE, "gemm launch: %s", hipGetErrorString(e));
+    return TITAN_OK;
+}

@@ -118,6 +118,19 @@ def _load():
         "titan_set_springs": ([_vp, ctypes.c_int64, ctypes.c_int64, _fp, _fp, _fp, _fp], ctypes.c_int),
         "titan_rollout_grad": ([_vp, ctypes.c_int64, ctypes.c_int32, _fp, _fp, _fp, _fp, _fp], ctypes.c_int),
         "titan_get_info": ([_vp, ctypes.POINTER(_Info)], ctypes.c_int),
+        "titan_mlp_create": ([ctypes.c_int32, _i32p, _vp, ctypes.POINTER(_Allocator), ctypes.POINTER(_vp)],
+                             ctypes.c_int),
+        "titan_mlp_destroy": ([_vp], ctypes.c_int),
+        "titan_mlp_param_count": ([_vp], ctypes.c_int64),
+        "titan_mlp_set_params": ([_vp, _fp], ctypes.c_int),
+        "titan_mlp_get_params": ([_vp, _fp], ctypes.c_int),
+        "titan_mlp_set_data": ([_vp, ctypes.c_int64, _fp, _fp], ctypes.c_int),
+        "titan_mlp_train": ([_vp, ctypes.c_int64, ctypes.c_int32, _i64p, ctypes.c_float, ctypes.c_float,
+                             ctypes.c_float, ctypes.c_float, _fp], ctypes.c_int),
+        "titan_mlp_predict": ([_vp, ctypes.c_int64, _fp, _fp], ctypes.c_int),
+        "titan_mlp_grad": ([_vp, ctypes.c_int32, _fp, _fp, _fp, _fp], ctypes.c_int),
+        "titan_mlp_gemm_bf16": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32,
+                                 ctypes.c_int32, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -369,3 +382,89 @@ def sim_from_scene(scene: dict, params: Params, rest=None, **kw) -> Sim:
         sim.add_springs(scene["ends"], scene["k"], damping=scene.get("damping"), rest=rest,
                         amp=scene.get("amp"), phase=scene.get("phase"))
     return sim
+
+
+class Mlp:
+    """The surrogate network (``titan_mlp``).  ``dims``: layer widths."""
+
+    def __init__(self, dims, stream=None, memory: str = "torch"):
+        import torch
+
+        self.dims = [int(d) for d in dims]
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        self._mem = _TorchMemory(torch.cuda.current_device(), handle) if memory == "torch" else None
+        d = np.asarray(self.dims, np.int32)
+        h = _vp()
+        _check(lib.titan_mlp_create(len(self.dims) - 1, d.ctypes.data_as(_i32p), _vp(handle) if handle else None,
+                                    ctypes.byref(self._mem.c) if self._mem else None, ctypes.byref(h)))
+        self._h = h
+        self.n_params = int(lib.titan_mlp_param_count(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.titan_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        p, pp = _f32(flat, (self.n_params,))
+        _check(lib.titan_mlp_set_params(self._h, pp))
+
+    def get_params(self):
+        out = np.empty(self.n_params, np.float32)
+        _check(lib.titan_mlp_get_params(self._h, out.ctypes.data_as(_fp)))
+        return out
+
+    def set_data(self, X, Y):
+        x, xp = _f32(X, (-1, self.dims[0]))
+        y, yp = _f32(Y, (-1, self.dims[-1]))
+        _check(lib.titan_mlp_set_data(self._h, x.shape[0], xp, yp))
+
+    def train(self, idx, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        """Adam steps over the rows listed by idx (nsteps x batch)."""
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        nsteps, batch = idx.shape
+        loss = np.empty(nsteps, np.float32)
+        _check(lib.titan_mlp_train(self._h, nsteps, batch, idx.ctypes.data_as(_i64p), lr, beta1, beta2, eps,
+                                   loss.ctypes.data_as(_fp)))
+        return loss
+
+    def predict(self, X):
+        x, xp = _f32(X, (-1, self.dims[0]))
+        out = np.empty((x.shape[0], self.dims[-1]), np.float32)
+        _check(lib.titan_mlp_predict(self._h, x.shape[0], xp, out.ctypes.data_as(_fp)))
+        return out
+
+    def grad(self, X, Y):
+        x, xp = _f32(X, (-1, self.dims[0]))
+        y, yp = _f32(Y, (-1, self.dims[-1]))
+        loss = np.empty(1, np.float32)
+        g = np.empty(self.n_params, np.float32)
+        _check(lib.titan_mlp_grad(self._h, x.shape[0], xp, yp, loss.ctypes.data_as(_fp), g.ctypes.data_as(_fp)))
+        return float(loss[0]), g
+
+
+def gemm_bf16(A, B, ta=False, tb=False, M=None, N=None, K=None, stream=None):
+    """C = op(A) op(B) on the MFMA GEMM kernel; A, B are torch int16/uint16
+    (bfloat16 bit patterns) CUDA tensors, C a new float32 CUDA tensor."""
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if M is None:
+        M = A.shape[1] if ta else A.shape[0]
+        K = A.shape[0] if ta else A.shape[1]
+        N = B.shape[0] if tb else B.shape[1]
+    lda = A.shape[1]
+    ldb = B.shape[1]
+    C = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    _check(lib.titan_mlp_gemm_bf16(M, N, K, _vp(A.data_ptr()), lda, int(ta), _vp(B.data_ptr()), ldb, int(tb),
+                                   _vp(C.data_ptr()), _vp(stream.cuda_stream) if stream.cuda_stream else None))
+    return C

@@ -132,7 +132,7 @@ def test_gradient_ascent_moves_the_robot_further():
             ph = torch.atan2(s, c)
             c.copy_(a * torch.cos(ph))
             s.copy_(a * torch.sin(ph))
-        losses.append(float(J.sum()))
+        losses.append(float(J.detach().sum()))
     print("losses", losses)
     assert losses[-1] < losses[0]
     sim.close()
