@@ -213,6 +213,11 @@ int titan_set_state(titan_sim *sim, int64_t first, int64_t count, const float *p
  * stopped).  Only when no steps are held at a pause breakpoint. */
 int titan_set_step(titan_sim *sim, int64_t step);
 
+/* Centre-of-mass displacement of every body after all enqueued steps
+ * (blocks): disp_nb3[b] = sum_i m_i (x_i - x0_i) / M_b over the masses of
+ * body b (n_bodies x 3 floats). */
+int titan_get_body_displacement(titan_sim *sim, float *disp_nb3);
+
 /* Change the constants of springs [first, first+count): k, damping and
  * actuation (amp with phase), each array NULL to keep that part (the paper's
  * Sec. IV-D pushes spring constants from the CPU into a running

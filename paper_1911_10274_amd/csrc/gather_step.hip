@@ -148,6 +148,26 @@ __global__ void scatter_kernel(float *dst, const int64_t *slot, const float *val
         dst[slot[q]] = val[q];
 }
 
+// disp[b] = sum_i w_i u_i over body b's internal masses [off[b], off[b+1]),
+// w_i = m_i / M_b: the body's centre-of-mass displacement (one thread per
+// body, masses in index order).
+__global__ void body_disp_kernel(const float4 *U, const float *w, const int64_t *off, int64_t nb, float *disp)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb)
+        return;
+    float x = 0.f, y = 0.f, z = 0.f;
+    for (int64_t i = off[b]; i < off[b + 1]; ++i) {
+        const float4 u = U[i];
+        x = fmaf(w[i], u.x, x);
+        y = fmaf(w[i], u.y, y);
+        z = fmaf(w[i], u.z, z);
+    }
+    disp[3 * b] = x;
+    disp[3 * b + 1] = y;
+    disp[3 * b + 2] = z;
+}
+
 __global__ void fill_kernel(float *dst, float v, int64_t m)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -162,6 +182,16 @@ hipError_t launch_scatter(float *dst, const int64_t *slot, const float *val, int
     if (m <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, dst, slot, val, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_body_disp(const float4 *U, const float *w, const int64_t *off, int64_t nb, float *disp,
+                            hipStream_t stream)
+{
+    if (nb <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(body_disp_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, stream, U, w, off, nb,
+                       disp);
     return hipGetLastError();
 }
 

@@ -751,6 +751,77 @@ extern "C" int titan_set_springs(titan_sim *s, int64_t first, int64_t count, con
     return update_springs(s, first, count, k, damping, amp, phase);
 }
 
+extern "C" int titan_get_body_displacement(titan_sim *s, float *disp)
+{
+    if (!s || !disp)
+        return fail(TITAN_EINVAL, "sim or disp is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (int rc = ready(s))
+        return rc;
+    const int64_t n = s->n;
+    int32_t nb = 0;
+    for (int32_t b : s->h_body)
+        nb = std::max(nb, b + 1);
+    if (nb == 0)
+        return TITAN_OK;
+    // bodies are contiguous internal ranges (largest first)
+    std::vector<int64_t> off{0};
+    std::vector<int32_t> rank_body;
+    for (int64_t a = 0; a < n;) {
+        const int32_t bd = s->h_body[s->perm[a]];
+        int64_t b = a + 1;
+        while (b < n && s->h_body[s->perm[b]] == bd)
+            ++b;
+        rank_body.push_back(bd);
+        off.push_back(b);
+        a = b;
+    }
+    std::vector<double> mt(nb, 0.0);
+    for (int64_t u = 0; u < n; ++u)
+        mt[s->h_body[u]] += (double)s->h_mass[u];
+    std::vector<float> w(n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t u = s->perm[i];
+        const double m = mt[s->h_body[u]];
+        w[i] = m > 0.0 ? (float)((double)s->h_mass[u] / m) : 0.f;
+    }
+    const int64_t nr = (int64_t)rank_body.size();
+    float *dw = nullptr, *dd = nullptr;
+    int64_t *doff = nullptr;
+    if (int rc = dev_alloc(s, sizeof(float) * std::max<int64_t>(n, 1), (void **)&dw))
+        return rc;
+    if (int rc = dev_alloc(s, sizeof(float) * 3 * nr, (void **)&dd)) {
+        dev_free(s, dw);
+        return rc;
+    }
+    if (int rc = dev_alloc(s, sizeof(int64_t) * (nr + 1), (void **)&doff)) {
+        dev_free(s, dw);
+        dev_free(s, dd);
+        return rc;
+    }
+    std::vector<float> h(3 * nr);
+    hipError_t e = hipMemcpyAsync(dw, w.data(), sizeof(float) * n, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(doff, off.data(), sizeof(int64_t) * (nr + 1), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = launch_body_disp(s->U[s->cur], dw, doff, nr, dd, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h.data(), dd, sizeof(float) * 3 * nr, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s->stream);
+    dev_free(s, dw);
+    dev_free(s, dd);
+    dev_free(s, doff);
+    if (e != hipSuccess)
+        return hip_fail(s, e, "body displacement");
+    for (int32_t b = 0; b < nb; ++b)
+        disp[3 * b] = disp[3 * b + 1] = disp[3 * b + 2] = 0.f;
+    for (int64_t r = 0; r < nr; ++r)
+        for (int c = 0; c < 3; ++c)
+            disp[3 * rank_body[r] + c] = h[3 * r + c];
+    return check_bad(s);
+}
+
 extern "C" int titan_rollout_grad(titan_sim *s, int64_t nsteps, int32_t checkpoint_every, const float *body_weights,
                                   float *loss_out, float *grad_k, float *grad_act_c, float *grad_act_s)
 {

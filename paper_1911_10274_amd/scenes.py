@@ -330,3 +330,123 @@ def concat(robots: list[dict]) -> dict:
         damping=cat("damping"), amp=cat("amp"), phase=cat("phase"), body=body,
         mass_ptr=mass_ptr, spring_ptr=spring_ptr,
     )
+
+
+# ----------------------------------------------------------------------------
+# Many small voxel robots at once (surrogate datasets)
+# ----------------------------------------------------------------------------
+
+def small_robot_batch(count: int, seed: int, side_lo: int = 3, side_hi: int = 8, *, grid: int = 8,
+                      p_occ: float = 0.6, voxel: float = 0.1, mass: float = 0.1, k: float = 1.0e4,
+                      damping: float = 1.0, amp_max: float = 0.15) -> dict:
+    """``count`` voxel robots of side <= ``grid``, built together.
+
+    Same rules as :func:`voxel_robot` (Bernoulli occupancy, largest
+    6-connected component, masses at distinct corners, springs on all 28
+    corner pairs of every kept voxel, lowest corners at z = 0, per-spring
+    actuation = polar form of the mean voxel phasor), with a bulk draw order
+    from ``Generator(PCG64(seed))``: sides (count), then occupancy uniforms,
+    phases U(0, 2 pi) and amplitudes U(0, amp_max), each ``count x grid^3``;
+    a robot of side s uses the first s^3 values of its row, voxel index
+    ix + s*iy + s^2*iz.  Voxels sit at the same (ix, iy, iz) of a
+    ``grid^3`` frame, which the returned ``occ``, ``vox_a``, ``vox_phi``
+    arrays ([count, grid, grid, grid], index [iz, iy, ix]) describe.
+
+    Returns one concatenated scene (as :func:`concat`) plus those grids.
+    """
+    from scipy import ndimage
+
+    G = grid
+    G3 = G ** 3
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sides = rng.integers(side_lo, side_hi + 1, size=count)
+    U = rng.random((count, G3))
+    PH = rng.uniform(0.0, 2.0 * math.pi, size=(count, G3))
+    AM = rng.uniform(0.0, amp_max, size=(count, G3))
+
+    occ = np.zeros((count, G, G, G), bool)
+    vphi = np.zeros((count, G, G, G))
+    vamp = np.zeros((count, G, G, G))
+    for s in range(side_lo, side_hi + 1):
+        rs = np.flatnonzero(sides == s)
+        if rs.size == 0:
+            continue
+        occ[rs, :s, :s, :s] = (U[rs, :s ** 3] < p_occ).reshape(-1, s, s, s)
+        vphi[rs, :s, :s, :s] = PH[rs, :s ** 3].reshape(-1, s, s, s)
+        vamp[rs, :s, :s, :s] = AM[rs, :s ** 3].reshape(-1, s, s, s)
+
+    # largest face-connected component of every robot in one labelling pass
+    struct = np.zeros((3, 3, 3, 3), bool)
+    struct[1] = ndimage.generate_binary_structure(3, 1)
+    lab, nlab = ndimage.label(occ, structure=struct)
+    flat = lab.reshape(count, G3)
+    keep = np.zeros((count, G3), bool)
+    if nlab:
+        sizes = np.bincount(lab.ravel(), minlength=nlab + 1)
+        robot_of = np.zeros(nlab + 1, np.int64)
+        rr, cc = np.nonzero(flat)
+        robot_of[flat[rr, cc]] = rr
+        labels = np.arange(1, nlab + 1)
+        # per robot: the largest label, ties to the lowest label (raster order)
+        order = np.lexsort((labels, -sizes[1:], robot_of[1:]))
+        first = np.ones(order.size, bool)
+        first[1:] = robot_of[1:][order][1:] != robot_of[1:][order][:-1]
+        best = np.zeros(count, np.int64)
+        best[robot_of[1:][order][first]] = labels[order][first]
+        keep = (flat == best[:, None]) & (flat > 0)
+    empty = ~keep.any(axis=1)
+    keep[empty, 0] = True
+    keep3 = keep.reshape(count, G, G, G)
+    occ = keep3
+    vphi = np.where(keep3, vphi, 0.0)
+    vamp = np.where(keep3, vamp, 0.0)
+
+    # kept voxels: (robot, ix, iy, iz)
+    r_v, z_v, y_v, x_v = np.nonzero(keep3)
+    nv = r_v.size
+    C1 = G + 1
+    C3 = C1 ** 3
+    corner = np.empty((nv, 8), np.int64)
+    for c, (ox, oy, oz) in enumerate(_VOXEL_CORNERS):
+        corner[:, c] = r_v * C3 + (x_v + ox) + C1 * (y_v + oy) + C1 * C1 * (z_v + oz)
+    used = np.unique(corner)
+    mid = np.searchsorted(used, corner)  # global mass index per voxel corner
+    pa = np.array([p[0] for p in _VOXEL_PAIRS])
+    pb = np.array([p[1] for p in _VOXEL_PAIRS])
+    e0 = mid[:, pa].ravel()
+    e1 = mid[:, pb].ravel()
+    lo = np.minimum(e0, e1)
+    hi = np.maximum(e0, e1)
+    vox_of_pair = np.repeat(np.arange(nv), len(_VOXEL_PAIRS))
+    key = lo * used.size + hi
+    order = np.lexsort((vox_of_pair, key))
+    key_s = key[order]
+    firstk = np.ones(key_s.size, bool)
+    firstk[1:] = key_s[1:] != key_s[:-1]
+    spring_of_pair = np.cumsum(firstk) - 1
+    uniq = order[firstk]
+    ends = np.stack([lo[uniq], hi[uniq]], axis=1)
+    nsp = ends.shape[0]
+    sv_idx = vox_of_pair[order]
+    cnt = np.bincount(spring_of_pair, minlength=nsp).astype(np.float64)
+    va = vamp[r_v, z_v, y_v, x_v]
+    vp = vphi[r_v, z_v, y_v, x_v]
+    cs = np.bincount(spring_of_pair, weights=(va * np.cos(vp))[sv_idx], minlength=nsp) / cnt
+    sn = np.bincount(spring_of_pair, weights=(va * np.sin(vp))[sv_idx], minlength=nsp) / cnt
+
+    robot = used // C3
+    rem = used % C3
+    cx, cy, cz = rem % C1, (rem // C1) % C1, rem // (C1 * C1)
+    zmin = np.full(count, np.iinfo(np.int64).max)
+    np.minimum.at(zmin, robot, cz)
+    pos = np.stack([cx, cy, cz - zmin[robot]], axis=1).astype(np.float64) * voxel
+    mass_ptr = np.concatenate([[0], np.cumsum(np.bincount(robot, minlength=count))]).astype(np.int64)
+    spring_ptr = np.concatenate([[0], np.cumsum(np.bincount(robot[ends[:, 0]], minlength=count))]).astype(np.int64)
+    n = used.size
+    return dict(
+        pos=pos.astype(np.float32), vel=np.zeros((n, 3), np.float32), mass=np.full(n, mass, np.float32),
+        ends=ends.astype(np.int64), k=np.full(nsp, k, np.float32), damping=np.full(nsp, damping, np.float32),
+        amp=np.hypot(cs, sn).astype(np.float32), phase=np.arctan2(sn, cs).astype(np.float32),
+        body=robot.astype(np.int32), mass_ptr=mass_ptr, spring_ptr=spring_ptr, sides=sides,
+        occ=occ, vox_a=vamp, vox_phi=vphi,
+    )

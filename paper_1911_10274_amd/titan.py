@@ -115,6 +115,7 @@ def _load():
         "titan_set_state": ([_vp, ctypes.c_int64, ctypes.c_int64, _fp, _fp, ctypes.c_int32], ctypes.c_int),
         "titan_get_forces": ([_vp, ctypes.c_int64, ctypes.c_int64, _fp], ctypes.c_int),
         "titan_set_step": ([_vp, ctypes.c_int64], ctypes.c_int),
+        "titan_get_body_displacement": ([_vp, _fp], ctypes.c_int),
         "titan_set_springs": ([_vp, ctypes.c_int64, ctypes.c_int64, _fp, _fp, _fp, _fp], ctypes.c_int),
         "titan_rollout_grad": ([_vp, ctypes.c_int64, ctypes.c_int32, _fp, _fp, _fp, _fp, _fp], ctypes.c_int),
         "titan_get_info": ([_vp, ctypes.POINTER(_Info)], ctypes.c_int),
@@ -337,6 +338,13 @@ class Sim:
         v, vp = _f32(vel, (-1, 3)) if vel is not None else (None, None)
         count = (p if p is not None else v).shape[0]
         _check(lib.titan_set_state(self._h, first, count, pp, vp, STATE_DISPLACEMENT if displacement else 0))
+
+    def body_displacement(self):
+        """(n_bodies, 3) centre-of-mass displacement of every body."""
+        nb = self.info()["n_bodies"]
+        out = np.empty((nb, 3), np.float32)
+        _check(lib.titan_get_body_displacement(self._h, out.ctypes.data_as(_fp)))
+        return out
 
     def set_springs(self, first: int = 0, k=None, damping=None, amp=None, phase=None):
         """Change spring constants (see titan_set_springs)."""
