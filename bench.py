@@ -33,8 +33,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "tiled_step_lattice100.md")
+# the kernel and the host code that lays out its input (the counters depend on both)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1911_10274_amd", "csrc", f)
-                  for f in ("gather_step.hip", "step_device.h", "titan_internal.h")]
+                  for f in ("gather_step.hip", "step_device.h", "titan_internal.h", "engine_gather.hip")]
 
 
 def algorithmic_bytes(n_masses: int, n_springs: int) -> int:

@@ -202,14 +202,37 @@ __global__ __launch_bounds__(256) void mse_kernel(const float *out, const float 
 }
 
 // db[j] = sum over the batch of dz[b][j] (one thread per column, in order)
-__global__ void bias_grad_kernel(const uint16_t *dz, int B, int N, float *db)
+// Bias gradient db[j] = sum over rows b of dz[b, j], in two passes with a
+// fixed summation order (so the result does not depend on scheduling):
+// workgroup (x, y) sums rows [y*kBiasRows, (y+1)*kBiasRows) of 64 columns,
+// four row phases per column combined in order; then each column adds its
+// partial sums in row-chunk order.
+constexpr int kBiasRows = 64;
+
+__global__ __launch_bounds__(256) void bias_partial_kernel(const uint16_t *dz, int B, int N, float *part)
+{
+    __shared__ float red[4][64];
+    const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + c;
+    const int r0 = blockIdx.y * kBiasRows, r1 = min(B, r0 + kBiasRows);
+    float acc = 0.f;
+    if (j < N)
+        for (int b = r0 + ph; b < r1; b += 4)
+            acc += bf2f(dz[(int64_t)b * N + j]);
+    red[ph][c] = acc;
+    __syncthreads();
+    if (ph == 0 && j < N)
+        part[(int64_t)blockIdx.y * N + j] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+__global__ void bias_final_kernel(const float *part, int chunks, int N, float *db)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N)
         return;
     float acc = 0.f;
-    for (int b = 0; b < B; ++b)
-        acc += bf2f(dz[(int64_t)b * N + j]);
+    for (int y = 0; y < chunks; ++y)
+        acc += part[(int64_t)y * N + j];
     db[j] = acc;
 }
 
@@ -268,6 +291,7 @@ struct titan_mlp {
     std::vector<float *> zs;     // z_l (fp32)
     uint16_t *dz[2] = {nullptr, nullptr};
     float *yb = nullptr;
+    float *bpart = nullptr;  // bias-gradient partial sums, ceil(cap / kBiasRows) x widest layer
     int64_t *idx = nullptr;
     float *loss = nullptr;
     int loss_cap = 0;
@@ -324,7 +348,7 @@ static int ensure_cap(titan_mlp *m, int B)
         mlp_free(m, p);
     for (auto *p : m->zs)
         mlp_free(m, p);
-    for (auto *p : {(void *)m->dz[0], (void *)m->dz[1], (void *)m->yb, (void *)m->idx})
+    for (auto *p : {(void *)m->dz[0], (void *)m->dz[1], (void *)m->yb, (void *)m->idx, (void *)m->bpart})
         if (p)
             mlp_free(m, p);
     m->xs.assign(m->L(), nullptr);
@@ -344,6 +368,8 @@ static int ensure_cap(titan_mlp *m, int B)
     if (int rc = mlp_alloc(m, sizeof(float) * (size_t)B * m->dims.back(), (void **)&m->yb))
         return rc;
     if (int rc = mlp_alloc(m, sizeof(int64_t) * (size_t)B, (void **)&m->idx))
+        return rc;
+    if (int rc = mlp_alloc(m, sizeof(float) * (size_t)((B + kBiasRows - 1) / kBiasRows) * maxd, (void **)&m->bpart))
         return rc;
     m->cap = B;
     return TITAN_OK;
@@ -396,8 +422,12 @@ static int backward(titan_mlp *m, int B, float *loss_dev)
         ew.Z = m->G + m->woff[l];
         ew.ldz = in;
         MLP_TRY((gemm<true, false, EPI_F32>(out, in, B, dz, out, m->xs[l], in, ew, m->stream)));
-        hipLaunchKernelGGL(bias_grad_kernel, dim3((out + 255) / 256), dim3(256), 0, m->stream, dz, B, out,
-                           m->G + m->boff[l]);
+        const int chunks = (B + kBiasRows - 1) / kBiasRows;
+        hipLaunchKernelGGL(bias_partial_kernel, dim3((out + 63) / 64, chunks), dim3(256), 0, m->stream, dz, B, out,
+                           m->bpart);
+        MLP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(bias_final_kernel, dim3((out + 255) / 256), dim3(256), 0, m->stream, m->bpart, chunks,
+                           out, m->G + m->boff[l]);
         MLP_TRY(hipGetLastError());
         if (l > 0) {
             GemmEpi ed{};
