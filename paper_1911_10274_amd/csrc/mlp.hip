@@ -201,7 +201,6 @@ __global__ __launch_bounds__(256) void mse_kernel(const float *out, const float 
         *loss = red[0] / (float)n;
 }
 
-// db[j] = sum over the batch of dz[b][j] (one thread per column, in order)
 // Bias gradient db[j] = sum over rows b of dz[b, j], in two passes with a
 // fixed summation order (so the result does not depend on scheduling):
 // workgroup (x, y) sums rows [y*kBiasRows, (y+1)*kBiasRows) of 64 columns,
