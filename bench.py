@@ -226,6 +226,53 @@ def bench_adjoint(T, robots_n: int, steps: int, K: int):
             "forward_ms": ms_fwd, "gradient_over_forward": sec * 1e3 / ms_fwd}
 
 
+def bench_surrogate(T, batch: int = 1024, steps: int = 60, gemm_n: int = 8192):
+    """Training throughput of the surrogate network (1536 -> 512 x 4 -> 3,
+    Adam) on the library's BF16 MFMA kernels at the training batch size, and
+    the MFMA GEMM kernel alone on one large square product."""
+    import numpy as np
+    import torch
+
+    dims = [1536, 512, 512, 512, 512, 3]
+    rng = np.random.Generator(np.random.PCG64(11))
+    n = 16 * batch
+    X = rng.standard_normal((n, dims[0])).astype(np.float32)
+    Y = rng.standard_normal((n, dims[-1])).astype(np.float32)
+    net = T.Mlp(dims)
+    params = np.concatenate([np.concatenate([rng.uniform(-1, 1, dims[l] * dims[l + 1]) * math.sqrt(3.0 / dims[l]),
+                                             np.zeros(dims[l + 1])]) for l in range(len(dims) - 1)])
+    net.set_params(params.astype(np.float32))
+    net.set_data(X, Y)
+    idx = rng.integers(0, n, (steps, batch))
+    net.train(idx[:5])  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net.train(idx)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    net.close()
+    macs = sum(dims[l] * dims[l + 1] for l in range(len(dims) - 1))
+    train_flops = 3 * 2 * macs * batch * steps  # forward, data gradient, weight gradient
+    # bf16 bit patterns of magnitude below 1 (sign and top exponent bit clear)
+    A = torch.randint(-2**15, 2**15, (gemm_n, gemm_n), dtype=torch.int16, device="cuda") & 0x3F7F
+    B = torch.randint(-2**15, 2**15, (gemm_n, gemm_n), dtype=torch.int16, device="cuda") & 0x3F7F
+    T.gemm_bf16(A, B)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    ev0.record()
+    for _ in range(reps):
+        T.gemm_bf16(A, B)
+    ev1.record()
+    torch.cuda.synchronize()
+    gms = ev0.elapsed_time(ev1) / reps
+    gflops = 2.0 * gemm_n ** 3 / (gms * 1e-3)
+    return {"workload": f"surrogate MLP 1536-512x4-3 (1,576,451 parameters), batch {batch}, {steps} Adam steps",
+            "train_ms_per_step": sec * 1e3 / steps, "train_tflops": train_flops / sec / 1e12,
+            "gemm": {"shape": [gemm_n, gemm_n, gemm_n], "ms": gms, "tflops": gflops / 1e12,
+                     "frac_of_bf16_peak": gflops / 2.5e15}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +283,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate training / GEMM figures")
     ap.add_argument("--engine", choices=("tiled", "gather"), default="tiled")
     ap.add_argument("--robots", type=int, default=4096, help="voxel robots in the batched workload (0: skip)")
     ap.add_argument("--robot-steps", type=int, default=2000)
@@ -326,6 +374,8 @@ def main():
         out["batched"] = bench_batched(T, args.robots, args.robot_steps, args.loop_sample)
     if args.adjoint_robots > 0:
         out["adjoint"] = bench_adjoint(T, args.adjoint_robots, 500, 50)
+    if not args.no_surrogate:
+        out["surrogate"] = bench_surrogate(T)
     print(json.dumps(out))
 
 

@@ -55,62 +55,130 @@ struct GemmEpi {
     int ldz, ldy;
 };
 
-constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;
+constexpr int BM = 64, BN = 64, BK = 64, LDK = BK + 8;
+
+// Epilogue of output element (i, j) with accumulated value v.
+template <int EPI>
+__device__ __forceinline__ void epi_store(int i, int j, float v, const GemmEpi &ep)
+{
+    if (EPI == EPI_BIAS_GELU) {
+        const float z = v + ep.bias[j];
+        ep.Z[(int64_t)i * ep.ldz + j] = z;
+        ep.Yb[(int64_t)i * ep.ldy + j] = f2bf(gelu(z));
+    } else if (EPI == EPI_BIAS) {
+        ep.Z[(int64_t)i * ep.ldz + j] = v + ep.bias[j];
+    } else if (EPI == EPI_GELU_BWD) {
+        ep.Yb[(int64_t)i * ep.ldy + j] = f2bf(v * gelu_grad(ep.Zin[(int64_t)i * ep.ldz + j]));
+    } else {
+        ep.Z[(int64_t)i * ep.ldz + j] = v;
+    }
+}
+
+struct GemmArgs {
+    int M, N, K;
+    const uint16_t *A;
+    int lda;
+    const uint16_t *B;
+    int ldb;
+    int kslice;   // K range of one split (a multiple of BK)
+    float *part;  // split-K partial sums [splits][M][N], or null: epilogue here
+};
+
+// One operand tile (64 rows x BK of K) moved global -> registers -> LDS, the
+// LDS tile holding K contiguous per row.  KCONTIG: element (r, k) at
+// P[r * ld + k] (K contiguous in memory), else at P[k * ld + r].  Each of the
+// 256 threads moves two 16-byte chunks of 8 elements; vector loads when the
+// chunk is in range and aligned, element loads with zero fill otherwise.
+template <bool KCONTIG>
+struct TileMove {
+    uint4 v[2];
+
+    __device__ __forceinline__ void load(const uint16_t *P, int ld, int r0, int R, int k0, int kend, bool vec,
+                                         int tid)
+    {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + 256 * q;
+            const int hi = c >> 3, lo = (c & 7) * 8;
+            // KCONTIG: row r0 + hi, K k0 + lo .. +8; else K k0 + hi, rows r0 + lo .. +8
+            const int row = KCONTIG ? r0 + hi : r0 + lo, k = KCONTIG ? k0 + lo : k0 + hi;
+            const bool full = KCONTIG ? (row < R && k + 8 <= kend) : (k < kend && row + 8 <= R);
+            if (vec && full) {
+                v[q] = KCONTIG ? *(const uint4 *)(P + (int64_t)row * ld + k) : *(const uint4 *)(P + (int64_t)k * ld + row);
+            } else {
+                uint32_t w[4];
+#pragma unroll
+                for (int e = 0; e < 8; e += 2) {
+                    uint32_t x0 = 0, x1 = 0;
+                    if (KCONTIG) {
+                        if (row < R && k + e < kend)
+                            x0 = P[(int64_t)row * ld + k + e];
+                        if (row < R && k + e + 1 < kend)
+                            x1 = P[(int64_t)row * ld + k + e + 1];
+                    } else {
+                        if (k < kend && row + e < R)
+                            x0 = P[(int64_t)k * ld + row + e];
+                        if (k < kend && row + e + 1 < R)
+                            x1 = P[(int64_t)k * ld + row + e + 1];
+                    }
+                    w[e / 2] = x0 | x1 << 16;
+                }
+                v[q] = make_uint4(w[0], w[1], w[2], w[3]);
+            }
+        }
+    }
+
+    __device__ __forceinline__ void store(uint16_t *S, int tid) const
+    {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + 256 * q;
+            const int hi = c >> 3, lo = (c & 7) * 8;
+            if (KCONTIG) {
+                *(uint4 *)&S[hi * LDK + lo] = v[q];
+            } else {
+                const uint32_t w[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    S[(lo + e) * LDK + hi] = (uint16_t)(w[e / 2] >> (16 * (e & 1)));
+            }
+        }
+    }
+};
 
 // C[M,N] = A[M,K] B[K,N] with A(m,k) = TA ? A[k*lda + m] : A[m*lda + k] and
 // B(k,n) = TB ? B[n*ldb + k] : B[k*ldb + n], all bf16; FP32 accumulate on
-// v_mfma_f32_32x32x16_bf16.  A 64x64 tile per workgroup, 32x32 per wave.
-// Tiles are staged in LDS with K contiguous per row (A) or column (B), so
-// each lane's 8 K-values of an MFMA operand are one 16-byte LDS read.
+// v_mfma_f32_32x32x16_bf16.  A 64x64 tile per workgroup, 32x32 per wave;
+// workgroup z takes K range [z*kslice, (z+1)*kslice).  Tiles are staged in
+// LDS with K contiguous per row (A) or column (B), so each lane's 8 K-values
+// of an MFMA operand are one 16-byte LDS read; the next K tile is loaded into
+// registers while the current one is multiplied.
 template <bool TA, bool TB, int EPI>
-__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const uint16_t *__restrict__ A, int lda,
-                                                   const uint16_t *__restrict__ Bm, int ldb, GemmEpi ep)
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, GemmEpi ep)
 {
     __shared__ __attribute__((aligned(16))) uint16_t sA[BM * LDK];
     __shared__ __attribute__((aligned(16))) uint16_t sB[BN * LDK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int wm = wave >> 1, wn = wave & 1;
+    const int kb = blockIdx.z * g.kslice, ke = min(g.K, kb + g.kslice);
+    const bool va = (g.lda % 8 == 0) && (((uintptr_t)g.A & 15) == 0);
+    const bool vb = (g.ldb % 8 == 0) && (((uintptr_t)g.B & 15) == 0);
+    TileMove<!TA> ta;
+    TileMove<TB> tb;
     f32x16_t acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        // A tile -> sA[m][k]
-        if (!TA) {
-            const int r = tid >> 2, c = (tid & 3) * 8;
-            const int m = m0 + r;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int k = k0 + c + e;
-                sA[r * LDK + c + e] = (m < M && k < K) ? A[(int64_t)m * lda + k] : (uint16_t)0;
-            }
-        } else {
-            const int kk = tid >> 3, c = (tid & 7) * 8;
-            const int k = k0 + kk;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int m = m0 + c + e;
-                sA[(c + e) * LDK + kk] = (m < M && k < K) ? A[(int64_t)k * lda + m] : (uint16_t)0;
-            }
-        }
-        // B tile -> sB[n][k]
-        if (TB) {
-            const int r = tid >> 2, c = (tid & 3) * 8;
-            const int n = n0 + r;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int k = k0 + c + e;
-                sB[r * LDK + c + e] = (n < N && k < K) ? Bm[(int64_t)n * ldb + k] : (uint16_t)0;
-            }
-        } else {
-            const int kk = tid >> 3, c = (tid & 7) * 8;
-            const int k = k0 + kk;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int n = n0 + c + e;
-                sB[(c + e) * LDK + kk] = (n < N && k < K) ? Bm[(int64_t)k * ldb + n] : (uint16_t)0;
-            }
-        }
+    if (kb < ke) {
+        ta.load(g.A, g.lda, m0, g.M, kb, ke, va, tid);
+        tb.load(g.B, g.ldb, n0, g.N, kb, ke, vb, tid);
+    }
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+        ta.store(sA, tid);
+        tb.store(sB, tid);
         __syncthreads();
+        if (k0 + BK < ke) {
+            ta.load(g.A, g.lda, m0, g.M, k0 + BK, ke, va, tid);
+            tb.load(g.B, g.ldb, n0, g.N, k0 + BK, ke, vb, tid);
+        }
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
             const bf16x8_t a = *(const bf16x8_t *)&sA[(wm * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5)];
@@ -123,36 +191,62 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const ui
     // D layout of the 32x32 MFMA: lane l holds column l % 32 and, for
     // r = 0..15, row 8 (r / 4) + 4 (l / 32) + r % 4.
     const int j = n0 + wn * 32 + (lane & 31);
-    if (j >= N)
+    if (j >= g.N)
         return;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int i = m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (i >= M)
+        if (i >= g.M)
             continue;
-        const float v = acc[r];
-        if (EPI == EPI_BIAS_GELU) {
-            const float z = v + ep.bias[j];
-            ep.Z[(int64_t)i * ep.ldz + j] = z;
-            ep.Yb[(int64_t)i * ep.ldy + j] = f2bf(gelu(z));
-        } else if (EPI == EPI_BIAS) {
-            ep.Z[(int64_t)i * ep.ldz + j] = v + ep.bias[j];
-        } else if (EPI == EPI_GELU_BWD) {
-            ep.Yb[(int64_t)i * ep.ldy + j] = f2bf(v * gelu_grad(ep.Zin[(int64_t)i * ep.ldz + j]));
-        } else {
-            ep.Z[(int64_t)i * ep.ldz + j] = v;
-        }
+        if (g.part)
+            g.part[((int64_t)blockIdx.z * g.M + i) * g.N + j] = acc[r];
+        else
+            epi_store<EPI>(i, j, acc[r], ep);
     }
 }
 
+// Split-K: sum the partials of each output element in split order, then the
+// epilogue.
+template <int EPI>
+__global__ void gemm_reduce_kernel(int M, int N, int splits, const float *part, GemmEpi ep)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)M * N)
+        return;
+    float v = 0.f;
+    for (int z = 0; z < splits; ++z)
+        v += part[(int64_t)z * M * N + q];
+    epi_store<EPI>((int)(q / N), (int)(q % N), v, ep);
+}
+
+// Workgroups a GEMM aims for before it splits K.
+constexpr int kGemmTarget = 768;
+
+// part (capacity part_cap floats) enables split-K when the output has too few
+// tiles; null: one pass.
 template <bool TA, bool TB, int EPI>
 hipError_t gemm(int M, int N, int K, const uint16_t *A, int lda, const uint16_t *B, int ldb, const GemmEpi &ep,
-                hipStream_t st)
+                hipStream_t st, float *part = nullptr, int64_t part_cap = 0)
 {
     if (M <= 0 || N <= 0)
         return hipSuccess;
-    const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM));
-    hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, ep);
+    const int tiles = ((N + BN - 1) / BN) * ((M + BM - 1) / BM);
+    const int kt = std::max(1, (K + BK - 1) / BK);
+    int splits = 1;
+    if (part && tiles < kGemmTarget)
+        splits = std::max(1, std::min(kGemmTarget / tiles, kt / 2));
+    while (splits > 1 && (int64_t)splits * M * N > part_cap)
+        --splits;
+    const int kslice = ((kt + splits - 1) / splits) * BK;
+    splits = std::max(1, (K + kslice - 1) / kslice);
+    GemmArgs g{M, N, K, A, lda, B, ldb, kslice, splits > 1 ? part : nullptr};
+    const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)splits);
+    hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, g, ep);
+    if (splits > 1) {
+        const int64_t n = (int64_t)M * N;
+        hipLaunchKernelGGL(gemm_reduce_kernel<EPI>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, M, N, splits,
+                           part, ep);
+    }
     return hipGetLastError();
 }
 
@@ -291,6 +385,8 @@ struct titan_mlp {
     uint16_t *dz[2] = {nullptr, nullptr};
     float *yb = nullptr;
     float *bpart = nullptr;  // bias-gradient partial sums, ceil(cap / kBiasRows) x widest layer
+    float *gpart = nullptr;  // split-K partial sums of the GEMMs
+    int64_t gpart_cap = 0;   // floats in gpart
     int64_t *idx = nullptr;
     float *loss = nullptr;
     int loss_cap = 0;
@@ -347,7 +443,8 @@ static int ensure_cap(titan_mlp *m, int B)
         mlp_free(m, p);
     for (auto *p : m->zs)
         mlp_free(m, p);
-    for (auto *p : {(void *)m->dz[0], (void *)m->dz[1], (void *)m->yb, (void *)m->idx, (void *)m->bpart})
+    for (auto *p : {(void *)m->dz[0], (void *)m->dz[1], (void *)m->yb, (void *)m->idx, (void *)m->bpart,
+                    (void *)m->gpart})
         if (p)
             mlp_free(m, p);
     m->xs.assign(m->L(), nullptr);
@@ -369,6 +466,9 @@ static int ensure_cap(titan_mlp *m, int B)
     if (int rc = mlp_alloc(m, sizeof(int64_t) * (size_t)B, (void **)&m->idx))
         return rc;
     if (int rc = mlp_alloc(m, sizeof(float) * (size_t)((B + kBiasRows - 1) / kBiasRows) * maxd, (void **)&m->bpart))
+        return rc;
+    m->gpart_cap = 4 * std::max<int64_t>((int64_t)B * maxd, (int64_t)maxd * maxd);
+    if (int rc = mlp_alloc(m, sizeof(float) * (size_t)m->gpart_cap, (void **)&m->gpart))
         return rc;
     m->cap = B;
     return TITAN_OK;
@@ -395,9 +495,11 @@ static int forward(titan_mlp *m, int B)
         if (l < L - 1) {
             ep.Yb = m->xs[l + 1];
             ep.ldy = out;
-            MLP_TRY((gemm<false, true, EPI_BIAS_GELU>(B, out, in, m->xs[l], in, m->Wb + m->wboff[l], in, ep, m->stream)));
+            MLP_TRY((gemm<false, true, EPI_BIAS_GELU>(B, out, in, m->xs[l], in, m->Wb + m->wboff[l], in, ep, m->stream,
+                                                      m->gpart, m->gpart_cap)));
         } else {
-            MLP_TRY((gemm<false, true, EPI_BIAS>(B, out, in, m->xs[l], in, m->Wb + m->wboff[l], in, ep, m->stream)));
+            MLP_TRY((gemm<false, true, EPI_BIAS>(B, out, in, m->xs[l], in, m->Wb + m->wboff[l], in, ep, m->stream,
+                                                 m->gpart, m->gpart_cap)));
         }
     }
     return TITAN_OK;
@@ -420,7 +522,8 @@ static int backward(titan_mlp *m, int B, float *loss_dev)
         GemmEpi ew{};
         ew.Z = m->G + m->woff[l];
         ew.ldz = in;
-        MLP_TRY((gemm<true, false, EPI_F32>(out, in, B, dz, out, m->xs[l], in, ew, m->stream)));
+        MLP_TRY((gemm<true, false, EPI_F32>(out, in, B, dz, out, m->xs[l], in, ew, m->stream, m->gpart,
+                                            m->gpart_cap)));
         const int chunks = (B + kBiasRows - 1) / kBiasRows;
         hipLaunchKernelGGL(bias_partial_kernel, dim3((out + 63) / 64, chunks), dim3(256), 0, m->stream, dz, B, out,
                            m->bpart);
@@ -434,7 +537,8 @@ static int backward(titan_mlp *m, int B, float *loss_dev)
             ed.ldz = in;
             ed.Yb = m->dz[1 - cur];
             ed.ldy = in;
-            MLP_TRY((gemm<false, false, EPI_GELU_BWD>(B, in, out, dz, out, m->Wb + m->wboff[l], in, ed, m->stream)));
+            MLP_TRY((gemm<false, false, EPI_GELU_BWD>(B, in, out, dz, out, m->Wb + m->wboff[l], in, ed, m->stream,
+                                                      m->gpart, m->gpart_cap)));
             cur = 1 - cur;
         }
     }
