@@ -33,6 +33,8 @@ class _Params(ctypes.Structure):
         ("ground_k", ctypes.c_double),
         ("mu", ctypes.c_double),
         ("omega", ctypes.c_double),
+        ("wave", ctypes.c_int32),
+        ("period", ctypes.c_double),
     ]
 
 
@@ -57,7 +59,8 @@ def _load():
         lib = ctypes.CDLL(build())
         lib.orc_rest_lengths.argtypes = [ctypes.c_int64, _lp, _dp, _dp]
         lib.orc_spring_forces.argtypes = [ctypes.c_int64, ctypes.c_int64, _lp, _dp, _dp, _dp, _dp, _dp,
-                                          ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
+                                          ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                          _dp, _dp, _dp]
         lib.orc_integrate.argtypes = [ctypes.c_int64, _dp, ctypes.POINTER(_Params), _dp, _dp, _dp]
         lib.orc_run.argtypes = [ctypes.c_int64, _dp, ctypes.c_int64, _lp, _dp, _dp, _dp, _dp, _dp,
                                 ctypes.POINTER(_Params), ctypes.c_int64, ctypes.c_int64, _dp, _dp, _dp]
@@ -92,11 +95,14 @@ class Params:
     ground_k: float = 1.0e5
     mu: float = 0.5
     omega: float = 0.0
+    wave: bool = False    # wave actuation (Eqs. 3-5): a scene's phase holds the offsets t_o
+    period: float = 1.0   # wave period t_p, s
 
     @classmethod
     def from_dict(cls, d: dict) -> "Params":
         return cls(dt=d["dt"], gravity=tuple(d["gravity"]), ground=bool(d["ground"]),
-                   ground_k=d["ground_k"], mu=d["mu"], omega=d["omega"])
+                   ground_k=d["ground_k"], mu=d["mu"], omega=d["omega"], wave=bool(d.get("wave", False)),
+                   period=d.get("period", 1.0))
 
     def _c(self) -> _Params:
         p = _Params()
@@ -106,7 +112,21 @@ class Params:
         p.ground_k = self.ground_k
         p.mu = self.mu
         p.omega = self.omega
+        p.wave = 1 if self.wave else 0
+        p.period = self.period
         return p
+
+
+def wave_offsets(pos, ends, body=None) -> np.ndarray:
+    """Per-spring actuation offsets of the wave mode (Sec. IV-B, Eq. 5): the
+    smaller reference x of the spring's two ends minus the smallest reference
+    x of its body, in FP64 from the given positions."""
+    x = _d(pos).reshape(-1, 3)[:, 0]
+    e = np.asarray(ends, dtype=np.int64).reshape(-1, 2)
+    b = np.zeros(x.shape[0], np.int64) if body is None else np.asarray(body, dtype=np.int64)
+    xmin = np.full(int(b.max()) + 1 if b.size else 1, np.inf)
+    np.minimum.at(xmin, b, x)
+    return np.minimum(x[e[:, 0]], x[e[:, 1]]) - xmin[b[e[:, 0]]]
 
 
 class System:
@@ -132,13 +152,13 @@ class System:
             _load().orc_rest_lengths(self.ns, _ptr(self.ends, _lp), _ptr(self.x0), _ptr(rest))
         self.rest = _d(rest)
 
-    def spring_forces(self, x, v, t, omega):
+    def spring_forces(self, x, v, t, omega, wave=False, period=1.0):
         x = _d(x).reshape(-1, 3)
         v = _d(v).reshape(-1, 3)
         f = np.empty((self.n, 3), np.float64)
         _load().orc_spring_forces(self.n, self.ns, _ptr(self.ends, _lp), _ptr(self.k), _ptr(self.c),
-                                  _ptr(self.rest), _ptr(self.amp), _ptr(self.phase), omega, t,
-                                  _ptr(x), _ptr(v), _ptr(f))
+                                  _ptr(self.rest), _ptr(self.amp), _ptr(self.phase), omega, 1 if wave else 0,
+                                  period, t, _ptr(x), _ptr(v), _ptr(f))
         return f
 
     def run(self, params: Params, x, v, step0: int, nsteps: int, want_forces: bool = False):
@@ -197,6 +217,8 @@ class System:
         """Adjoint of J = sum_b w_b J_b: per-spring dJ/dk, dJ/dC, dJ/dS with
         C = amp cos(phase), S = amp sin(phase).  Returns a dict with loss,
         gk, gC, gS and the decision hash."""
+        if params.wave:
+            raise ValueError("the rollout adjoint covers phasor actuation only")
         b, nb = self._body(body)
         w = np.ones(nb) if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
         loss = np.empty(nb, np.float64)

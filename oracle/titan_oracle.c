@@ -21,6 +21,11 @@
  *     at most mu * F_n * dt / m.
  *   - Sec. IV-B Eq. 4: actuation scales the rest length by
  *     1 + amp * sin(omega * t + phase), t = n * dt at the start of step n.
+ *   - Sec. IV-B Eqs. 3-5 (wave mode, the worm): the rest length is scaled by
+ *     1 + amp * sin(omega * tau) with tau = (t - t_o) mod period, the modulo
+ *     taken non-negative (tau in [0, period)); the per-spring offset t_o is
+ *     passed in the phase array.  Eq. 5 defines t_o from the reference
+ *     positions: the smaller x of the two ends minus the body's smallest x.
  *
  * Accumulation is a serial scatter loop over springs in index order
  * (Sec. III-B's "apply to each corresponding mass"), all in double precision.
@@ -37,7 +42,20 @@ typedef struct {
     double ground_k;  /* penalty stiffness, N/m */
     double mu;        /* Coulomb friction coefficient */
     double omega;     /* actuation angular frequency, rad/s */
+    int32_t wave;     /* nonzero: wave actuation (Eqs. 3-5), phase = offset t_o */
+    double period;    /* wave actuation period t_p, s */
 } orc_params;
+
+/* Factor by which spring s's rest length exceeds its base length at time t:
+ * the rest length is rest * (1 + factor). */
+static double act_factor(double amp, double phase, double omega, double t, int wave, double period)
+{
+    if (!wave)
+        return amp * sin(omega * t + phase);
+    double u = t - phase;                          /* T - t_o */
+    double tau = u - period * floor(u / period);   /* in [0, period) */
+    return amp * sin(omega * tau);
+}
 
 /* Rest length of every spring = distance between its ends at the given
  * positions (x: n*3 doubles). */
@@ -57,6 +75,7 @@ void orc_rest_lengths(int64_t ns, const int64_t *ends, const double *x, double *
 void orc_spring_forces(int64_t n, int64_t ns, const int64_t *ends,
                        const double *k, const double *c, const double *rest,
                        const double *amp, const double *phase, double omega,
+                       int32_t wave, double period,
                        double t, const double *x, const double *v, double *f)
 {
     memset(f, 0, sizeof(double) * 3 * (size_t)n);
@@ -73,7 +92,7 @@ void orc_spring_forces(int64_t n, int64_t ns, const int64_t *ends,
         double u[3] = {d[0] / len, d[1] / len, d[2] / len};
         double L = rest[s];
         if (amp)
-            L = rest[s] * (1.0 + amp[s] * sin(omega * t + phase[s]));
+            L = rest[s] * (1.0 + act_factor(amp[s], phase[s], omega, t, wave, period));
         double mag = k[s] * (len - L);
         if (c)
             mag += c[s] * (dv[0] * u[0] + dv[1] * u[1] + dv[2] * u[2]);
@@ -138,7 +157,7 @@ int orc_run(int64_t n, const double *mass, int64_t ns, const int64_t *ends,
         return -2;
     for (int64_t s = 0; s < nsteps; ++s) {
         double t = (double)(step0 + s) * p->dt;
-        orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, t, x, v, f);
+        orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, p->wave, p->period, t, x, v, f);
         if (f_last && s == nsteps - 1)
             memcpy(f_last, f, sizeof(double) * 3 * (size_t)n);
         orc_integrate(n, mass, p, f, x, v);
@@ -180,7 +199,8 @@ static void step_sig(int64_t n, const double *mass, int64_t ns, const int64_t *e
                      const orc_params *p, int64_t step, double *f, double *x, double *v, uint64_t *sig)
 {
     const double dt = p->dt;
-    orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, (double)step * dt, x, v, f);
+    orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, p->wave, p->period, (double)step * dt, x, v,
+                      f);
     for (int64_t i = 0; i < n; ++i) {
         double m = mass[i];
         if (m == 0.0)
@@ -270,6 +290,8 @@ int orc_rollout_grad(int64_t n, const double *mass, int64_t ns, const int64_t *e
                      int64_t nsteps, const double *x0, const double *v0, double *loss, double *gk,
                      double *gC, double *gS, uint64_t *sig)
 {
+    if (p->wave)
+        return -1; /* the adjoint covers phasor actuation only */
     const double dt = p->dt;
     const size_t S = 3 * (size_t)(n > 0 ? n : 1);
     double *X = (double *)malloc(sizeof(double) * S * (size_t)(nsteps + 1));
@@ -320,7 +342,7 @@ int orc_rollout_grad(int64_t n, const double *mass, int64_t ns, const int64_t *e
     for (int64_t st = nsteps - 1; st >= 0; --st) {
         const double *x = X + S * st, *v = V + S * st;
         const double t = (double)st * dt;
-        orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, t, x, v, f);
+        orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, p->wave, p->period, t, x, v, f);
         /* masses: position update, friction, velocity update */
         for (int64_t i = 0; i < n; ++i) {
             double m = mass[i];

@@ -333,6 +333,34 @@ def concat(robots: list[dict]) -> dict:
 
 
 # ----------------------------------------------------------------------------
+# Worms (wave actuation, Sec. IV-B)
+# ----------------------------------------------------------------------------
+
+
+def worm(nx: int = 27, ny: int = 5, nz: int = 3, *, spacing: float = 0.1, origin=(0.0, 0.0, 0.0),
+         mass: float = 0.1, k: float = 1.0e4, damping: float = 1.0, c: float = 0.2) -> dict:
+    """A worm: an nx x ny x nz lattice (26-neighbourhood springs, no random
+    draws) lying on the ground, long along x, every spring actuated with
+    expansion constant ``c`` (the ``amp`` array; ``phase`` is zero).  The
+    default 27 x 5 x 3 lattice has 3,392 springs."""
+    w = lattice(nx, ny, nz, spacing=spacing, origin=origin, mass=mass, k=k, damping=damping)
+    ns = w["ends"].shape[0]
+    w["amp"] = np.full(ns, c, np.float32)
+    w["phase"] = np.zeros(ns, np.float32)
+    return w
+
+
+def worm_batch(count: int = 100, *, gap: float = 0.3, **kw) -> dict:
+    """``count`` identical worms side by side along y, ``gap`` metres apart,
+    as independent bodies (100 default worms: 339,200 springs)."""
+    ny = kw.get("ny", 5)
+    spacing = kw.get("spacing", 0.1)
+    x0, y0, z0 = kw.pop("origin", (0.0, 0.0, 0.0))
+    step = (ny - 1) * spacing + gap
+    return concat([worm(origin=(x0, y0 + q * step, z0), **kw) for q in range(count)])
+
+
+# ----------------------------------------------------------------------------
 # Many small voxel robots at once (surrogate datasets)
 # ----------------------------------------------------------------------------
 
