@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TITAN_ABI_VERSION 1
+#define TITAN_ABI_VERSION 2
 
 /* Status codes. */
 #define TITAN_OK 0
@@ -75,6 +75,19 @@ extern "C" {
                                   step (falls back to GATHER when a tile's
                                   neighbourhood does not fit in LDS) */
 
+/* Actuation law of the rest lengths (titan_params.actuation); L0 is a
+ * spring's base rest length and amp its amplitude (titan_add_springs). */
+#define TITAN_ACT_PHASOR 0 /* L0 (1 + amp sin(omega t + phase)), t = n dt at
+                              the start of step n (Sec. IV-B Eq. 4 with a
+                              per-spring phase) */
+#define TITAN_ACT_WAVE 1   /* the worm's travelling wave (Sec. IV-B Eqs. 3-5):
+                              L0 (1 + amp sin(omega tau)), tau = (t - t_o) mod
+                              wave_period taken in [0, wave_period); the
+                              offset t_o of a spring is the smaller reference x
+                              of its two ends minus the smallest reference x of
+                              its body (Eq. 5), computed by the library; the
+                              phase array is not used.  No rollout adjoint. */
+
 typedef struct titan_sim titan_sim;
 
 /* Simulation parameters (SI units).  Taken by value at each call that
@@ -88,6 +101,8 @@ typedef struct titan_params {
     double ground_k;    /* ground penalty stiffness, N/m (>= 0) */
     double friction_mu; /* Coulomb friction coefficient (>= 0) */
     double omega;       /* actuation angular frequency, rad/s */
+    int32_t actuation;  /* TITAN_ACT_*; fixed once the system is finalized */
+    double wave_period; /* TITAN_ACT_WAVE: period t_p, s (> 0) */
 } titan_params;
 
 /* Optional device-memory provider.  alloc returns a device pointer aligned

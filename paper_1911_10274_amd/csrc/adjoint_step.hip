@@ -170,8 +170,9 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
                 const int64_t i = m0 + q;
                 const float4 xi = sX[q], ui = sU[q], vi = sV[q];
                 float fx = 0.f, fy = 0.f, fz = 0.f;
-                sum_forces<ACT, DAMP, DAMPV, REST, false>(g, g.slice_off[i >> 6] + (i & 63), slice_width(g, i),
-                                                          xi, ui, vi, tr, nbr, state, fx, fy, fz);
+                sum_forces<ACT, DAMP, DAMPV, REST, false, false>(g, g.slice_off[i >> 6] + (i & 63),
+                                                                 slice_width(g, i), xi, ui, vi, Clock{tr, 0.0}, sc,
+                                                                 nbr, state, fx, fy, fz);
                 ok &= integrate_mass(xi, ui, vi, fx, fy, fz, sc, nu[k], nv[k]);
             }
         }
@@ -255,8 +256,9 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
                     const int64_t i = m0 + q;
                     const float4 xi = sX[q], ui = sU[q], vi = sV[q];
                     float fx = 0.f, fy = 0.f, fz = 0.f;
-                    sum_forces<ACT, DAMP, DAMPV, REST, false>(g, g.slice_off[i >> 6] + (i & 63), slice_width(g, i),
-                                                              xi, ui, vi, tr, nbr, state, fx, fy, fz);
+                    sum_forces<ACT, DAMP, DAMPV, REST, false, false>(g, g.slice_off[i >> 6] + (i & 63),
+                                                                     slice_width(g, i), xi, ui, vi, Clock{tr, 0.0},
+                                                                     sc, nbr, state, fx, fy, fz);
                     sM[q] = mass_adjoint(xi, ui, vi, fx, fy, fz, scs, lx[k], lv[k]);
                 }
             }

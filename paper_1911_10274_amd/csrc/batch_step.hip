@@ -11,7 +11,7 @@ namespace titan {
 
 namespace {
 
-template <bool ACT, bool DAMP, bool DAMPV, bool REST, int T, int MAXM>
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, int T, int MAXM>
 __global__ __launch_bounds__(T) void batch_step_kernel(GatherGraph g, BatchLayout b, StateIO io, StepConsts sc,
                                                        int nsteps)
 {
@@ -31,7 +31,7 @@ __global__ __launch_bounds__(T) void batch_step_kernel(GatherGraph g, BatchLayou
     __syncthreads();
 
     for (int s = 0; s < nsteps; ++s) {
-        const float2 tr = ACT ? sc.trig[s] : make_float2(0.f, 1.f);
+        const Clock ck{(ACT && !WAVE) ? sc.trig[s] : make_float2(0.f, 1.f), (double)(sc.step + s) * sc.dt64};
         float4 nu[MAXM], nv[MAXM];
         bool ok = true;
 #pragma unroll
@@ -42,8 +42,8 @@ __global__ __launch_bounds__(T) void batch_step_kernel(GatherGraph g, BatchLayou
                 const float4 xi = sX[q], ui = sU[q], vi = sV[q];
                 const int64_t base = g.slice_off[i >> 6] + (i & 63);
                 float fx = 0.f, fy = 0.f, fz = 0.f;
-                sum_forces<ACT, DAMP, DAMPV, REST, false>(
-                    g, base, slice_width(g, i), xi, ui, vi, tr, [&](int64_t e) { return (int)b.nbr_group[e]; },
+                sum_forces<ACT, DAMP, DAMPV, REST, false, WAVE>(
+                    g, base, slice_width(g, i), xi, ui, vi, ck, sc, [&](int64_t e) { return (int)b.nbr_group[e]; },
                     [&](int r, float4 &xj, float4 &uj, float4 &vj) {
                         uj = sU[r];
                         xj = sX[r];
@@ -73,11 +73,11 @@ __global__ __launch_bounds__(T) void batch_step_kernel(GatherGraph g, BatchLayou
     }
 }
 
-template <bool ACT, bool DAMP, bool DAMPV, bool REST, int T, int MAXM>
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, int T, int MAXM>
 hipError_t launch_tm(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc,
                      int nsteps, hipStream_t st)
 {
-    auto kern = batch_step_kernel<ACT, DAMP, DAMPV, REST, T, MAXM>;
+    auto kern = batch_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, T, MAXM>;
     const size_t lds = (size_t)b.max_group * 3 * sizeof(float4);
     if (lds > 65536) {
         const hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -89,30 +89,30 @@ hipError_t launch_tm(const GatherGraph &g, const BatchLayout &b, const StateIO &
     return hipGetLastError();
 }
 
-template <bool ACT, bool DAMP, bool DAMPV, bool REST, int T>
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, int T>
 hipError_t launch_t(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc, int nsteps,
                     hipStream_t st)
 {
     const int per = (b.max_group + T - 1) / T;
     if (per <= 1)
-        return launch_tm<ACT, DAMP, DAMPV, REST, T, 1>(g, b, io, sc, nsteps, st);
+        return launch_tm<ACT, WAVE, DAMP, DAMPV, REST, T, 1>(g, b, io, sc, nsteps, st);
     if (per <= 2)
-        return launch_tm<ACT, DAMP, DAMPV, REST, T, 2>(g, b, io, sc, nsteps, st);
+        return launch_tm<ACT, WAVE, DAMP, DAMPV, REST, T, 2>(g, b, io, sc, nsteps, st);
     if (per <= 4)
-        return launch_tm<ACT, DAMP, DAMPV, REST, T, 4>(g, b, io, sc, nsteps, st);
+        return launch_tm<ACT, WAVE, DAMP, DAMPV, REST, T, 4>(g, b, io, sc, nsteps, st);
     if (per <= 8)
-        return launch_tm<ACT, DAMP, DAMPV, REST, T, 8>(g, b, io, sc, nsteps, st);
+        return launch_tm<ACT, WAVE, DAMP, DAMPV, REST, T, 8>(g, b, io, sc, nsteps, st);
     return hipErrorInvalidValue;
 }
 
-template <bool ACT, bool DAMP, bool DAMPV, bool REST>
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST>
 hipError_t launch4(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc, int nsteps,
                    int threads, hipStream_t st)
 {
     switch (threads) {
-    case 256: return launch_t<ACT, DAMP, DAMPV, REST, 256>(g, b, io, sc, nsteps, st);
-    case 512: return launch_t<ACT, DAMP, DAMPV, REST, 512>(g, b, io, sc, nsteps, st);
-    case 1024: return launch_t<ACT, DAMP, DAMPV, REST, 1024>(g, b, io, sc, nsteps, st);
+    case 256: return launch_t<ACT, WAVE, DAMP, DAMPV, REST, 256>(g, b, io, sc, nsteps, st);
+    case 512: return launch_t<ACT, WAVE, DAMP, DAMPV, REST, 512>(g, b, io, sc, nsteps, st);
+    case 1024: return launch_t<ACT, WAVE, DAMP, DAMPV, REST, 1024>(g, b, io, sc, nsteps, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -124,22 +124,29 @@ hipError_t launch_batch(const GatherGraph &g, const BatchLayout &b, const StateI
 {
     if (b.n_groups == 0 || nsteps <= 0)
         return hipSuccess;
-    const bool act = g.act_c != nullptr, dampv = g.c != nullptr, rest = g.d0 != nullptr;
+    const bool act = g.act_c != nullptr, wave = act && g.t_off != nullptr, dampv = g.c != nullptr,
+               rest = g.d0 != nullptr;
     const bool damp = dampv || g.c_uniform != 0.f;
-    const int key = (act ? 8 : 0) | (damp ? 4 : 0) | (dampv ? 2 : 0) | (rest ? 1 : 0);
+    const int key = (act ? 8 : 0) | (damp ? 4 : 0) | (dampv ? 2 : 0) | (rest ? 1 : 0) | (wave ? 16 : 0);
     switch (key) {
-    case 0: return launch4<false, false, false, false>(g, b, io, sc, nsteps, threads, stream);
-    case 1: return launch4<false, false, false, true>(g, b, io, sc, nsteps, threads, stream);
-    case 4: return launch4<false, true, false, false>(g, b, io, sc, nsteps, threads, stream);
-    case 5: return launch4<false, true, false, true>(g, b, io, sc, nsteps, threads, stream);
-    case 6: return launch4<false, true, true, false>(g, b, io, sc, nsteps, threads, stream);
-    case 7: return launch4<false, true, true, true>(g, b, io, sc, nsteps, threads, stream);
-    case 8: return launch4<true, false, false, false>(g, b, io, sc, nsteps, threads, stream);
-    case 9: return launch4<true, false, false, true>(g, b, io, sc, nsteps, threads, stream);
-    case 12: return launch4<true, true, false, false>(g, b, io, sc, nsteps, threads, stream);
-    case 13: return launch4<true, true, false, true>(g, b, io, sc, nsteps, threads, stream);
-    case 14: return launch4<true, true, true, false>(g, b, io, sc, nsteps, threads, stream);
-    case 15: return launch4<true, true, true, true>(g, b, io, sc, nsteps, threads, stream);
+    case 0: return launch4<false, false, false, false, false>(g, b, io, sc, nsteps, threads, stream);
+    case 1: return launch4<false, false, false, false, true>(g, b, io, sc, nsteps, threads, stream);
+    case 4: return launch4<false, false, true, false, false>(g, b, io, sc, nsteps, threads, stream);
+    case 5: return launch4<false, false, true, false, true>(g, b, io, sc, nsteps, threads, stream);
+    case 6: return launch4<false, false, true, true, false>(g, b, io, sc, nsteps, threads, stream);
+    case 7: return launch4<false, false, true, true, true>(g, b, io, sc, nsteps, threads, stream);
+    case 8: return launch4<true, false, false, false, false>(g, b, io, sc, nsteps, threads, stream);
+    case 9: return launch4<true, false, false, false, true>(g, b, io, sc, nsteps, threads, stream);
+    case 12: return launch4<true, false, true, false, false>(g, b, io, sc, nsteps, threads, stream);
+    case 13: return launch4<true, false, true, false, true>(g, b, io, sc, nsteps, threads, stream);
+    case 14: return launch4<true, false, true, true, false>(g, b, io, sc, nsteps, threads, stream);
+    case 15: return launch4<true, false, true, true, true>(g, b, io, sc, nsteps, threads, stream);
+    case 24: return launch4<true, true, false, false, false>(g, b, io, sc, nsteps, threads, stream);
+    case 25: return launch4<true, true, false, false, true>(g, b, io, sc, nsteps, threads, stream);
+    case 28: return launch4<true, true, true, false, false>(g, b, io, sc, nsteps, threads, stream);
+    case 29: return launch4<true, true, true, false, true>(g, b, io, sc, nsteps, threads, stream);
+    case 30: return launch4<true, true, true, true, false>(g, b, io, sc, nsteps, threads, stream);
+    case 31: return launch4<true, true, true, true, true>(g, b, io, sc, nsteps, threads, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -206,13 +206,32 @@ static int build_gather(titan_sim *s, bool allow_tiled)
         damp_uniform &= s->h_damp[q] == s->h_damp[0];
         k_uniform &= s->h_k[q] == s->h_k[0];
     }
+    const bool wave = act && s->params.actuation == TITAN_ACT_WAVE;
     std::vector<float> sC, sS, sD0, sL0;
-    if (act) {
+    std::vector<double> sT;
+    if (act && !wave) {
         sC.resize(ns);
         sS.resize(ns);
         for (int64_t q = 0; q < ns; ++q) {
             sC[q] = (float)((double)s->h_amp[q] * std::cos((double)s->h_phase[q]));
             sS[q] = (float)((double)s->h_amp[q] * std::sin((double)s->h_phase[q]));
+        }
+    }
+    if (wave) {
+        // Sec. IV-B, Eq. 5: offset t_o = smaller reference x of the two ends
+        // minus the smallest reference x of the body
+        int32_t nb = 0;
+        for (int32_t b : s->h_body)
+            nb = std::max(nb, b + 1);
+        std::vector<double> xmin(nb, INFINITY);
+        for (int64_t i = 0; i < n; ++i)
+            xmin[s->h_body[i]] = std::min(xmin[s->h_body[i]], (double)s->h_pos[3 * i]);
+        sC.resize(ns);
+        sT.resize(ns);
+        for (int64_t q = 0; q < ns; ++q) {
+            const int64_t a = s->h_ends[2 * q], b = s->h_ends[2 * q + 1];
+            sC[q] = s->h_amp[q];
+            sT[q] = std::min((double)s->h_pos[3 * a], (double)s->h_pos[3 * b]) - xmin[s->h_body[a]];
         }
     }
     if (rest) {
@@ -243,13 +262,17 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     if (tiled)
         nbr_local.assign(slots, 0);
     std::vector<float> kk, cc, ac, as, d0, L0;
+    std::vector<double> to;
     if (!k_uniform)
         kk.assign(slots, 0.f);
     if (!damp_uniform)
         cc.assign(slots, 0.f);
     if (act) {
         ac.assign(slots, 0.f);
-        as.assign(slots, 0.f);
+        if (wave)
+            to.assign(slots, 0.0);
+        else
+            as.assign(slots, 0.f);
     }
     if (rest) {
         d0.assign(slots, 0.f);
@@ -290,7 +313,10 @@ static int build_gather(titan_sim *s, bool allow_tiled)
                 cc[e] = s->h_damp[x.spring];
             if (act) {
                 ac[e] = sC[x.spring];
-                as[e] = sS[x.spring];
+                if (wave)
+                    to[e] = sT[x.spring];
+                else
+                    as[e] = sS[x.spring];
             }
             if (rest) {
                 d0[e] = sD0[x.spring];
@@ -331,8 +357,13 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     if (act) {
         if (int rc = put(s, ac, &g.act_c))
             return rc;
-        if (int rc = put(s, as, &g.act_s))
-            return rc;
+        if (wave) {
+            if (int rc = put(s, to, &g.t_off))
+                return rc;
+        } else {
+            if (int rc = put(s, as, &g.act_s))
+                return rc;
+        }
     }
     if (rest) {
         if (int rc = put(s, d0, &g.d0))
@@ -441,7 +472,12 @@ int update_springs(titan_sim *s, int64_t first, int64_t count, const float *k, c
         else
             rc = apply(&g.c, g.c_uniform, [&](int64_t q) { return s->h_damp[q]; });
     }
-    if (!rc && amp) {
+    if (!rc && amp && g.t_off) {
+        // wave law: the amplitude is the factor; the offsets stay those of Eq. 5
+        rc = apply(&g.act_c, 0.f, [&](int64_t q) { return s->h_amp[q]; });
+    } else if (!rc && amp && s->params.actuation == TITAN_ACT_WAVE) {
+        rc = fail(TITAN_ESTATE, "wave actuation must be present when the system is finalized");
+    } else if (!rc && amp) {
         rc = apply(&g.act_c, 0.f, [&](int64_t q) {
             return (float)((double)s->h_amp[q] * std::cos((double)s->h_phase[q]));
         });
@@ -467,6 +503,9 @@ StepConsts consts_for(const titan_sim *s, int64_t step, const float2 *trig)
     sc.mu = (float)p.friction_mu;
     sc.trig = trig;
     sc.step = step;
+    sc.dt64 = p.dt;
+    sc.period = p.wave_period;
+    sc.omega = p.omega;
     return sc;
 }
 

@@ -20,7 +20,7 @@ namespace titan {
 
 namespace {
 
-template <bool ACT, bool DAMP, bool DAMPV, bool REST, bool FORCES>
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool FORCES>
 __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateIO io, StepConsts sc)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -31,9 +31,9 @@ __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateI
     const float4 xi = g.X0[i];
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
     float fx = 0.f, fy = 0.f, fz = 0.f;
-    const float2 tr = ACT ? *sc.trig : make_float2(0.f, 1.f);
-    sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0>(
-        g, base, slice_width(g, i), xi, ui, vi, tr, [&](int64_t e) { return stream_load(g.nbr + e); },
+    const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), (double)sc.step * sc.dt64};
+    sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE>(
+        g, base, slice_width(g, i), xi, ui, vi, ck, sc, [&](int64_t e) { return stream_load(g.nbr + e); },
         [&](int j, float4 &xj, float4 &uj, float4 &vj) {
             uj = io.U_in[j];
             xj = g.X0[j];
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateI
         atomicMin(io.first_bad, (unsigned long long)sc.step);
 }
 
-template <bool ACT, bool DAMP, bool DAMPV, bool REST, bool FORCES>
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool FORCES>
 __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateIO io, StepConsts sc)
 {
     extern __shared__ float4 smem[];
@@ -90,9 +90,9 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
 
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
     float fx = 0.f, fy = 0.f, fz = 0.f;
-    const float2 tr = ACT ? *sc.trig : make_float2(0.f, 1.f);
-    sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0>(
-        g, base, slice_width(g, i), xi, ui, vi, tr, [&](int64_t e) { return (int)stream_load(g.nbr_local + e); },
+    const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), (double)sc.step * sc.dt64};
+    sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE>(
+        g, base, slice_width(g, i), xi, ui, vi, ck, sc, [&](int64_t e) { return (int)stream_load(g.nbr_local + e); },
         [&](int q, float4 &xj, float4 &uj, float4 &vj) {
             uj = sU[q];
             xj = sX[q];
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
         atomicMin(io.first_bad, (unsigned long long)sc.step);
 }
 
-template <bool ACT, bool DAMP, bool DAMPV, bool REST>
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST>
 hipError_t launch4(const GatherGraph &g, const StateIO &io, const StepConsts &sc, bool forces, bool tiled,
                    hipStream_t st)
 {
@@ -119,15 +119,15 @@ hipError_t launch4(const GatherGraph &g, const StateIO &io, const StepConsts &sc
         const dim3 grid((unsigned)g.n_tiles), block(kTile);
         const size_t lds = (size_t)g.max_local * sizeof(float4) * (DAMP ? 3 : 2);
         if (forces)
-            hipLaunchKernelGGL((tiled_step_kernel<ACT, DAMP, DAMPV, REST, true>), grid, block, lds, st, g, io, sc);
+            hipLaunchKernelGGL((tiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, true>), grid, block, lds, st, g, io, sc);
         else
-            hipLaunchKernelGGL((tiled_step_kernel<ACT, DAMP, DAMPV, REST, false>), grid, block, lds, st, g, io, sc);
+            hipLaunchKernelGGL((tiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, false>), grid, block, lds, st, g, io, sc);
     } else {
         const dim3 grid((unsigned)((g.n + 255) / 256)), block(256);
         if (forces)
-            hipLaunchKernelGGL((untiled_step_kernel<ACT, DAMP, DAMPV, REST, true>), grid, block, 0, st, g, io, sc);
+            hipLaunchKernelGGL((untiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, true>), grid, block, 0, st, g, io, sc);
         else
-            hipLaunchKernelGGL((untiled_step_kernel<ACT, DAMP, DAMPV, REST, false>), grid, block, 0, st, g, io, sc);
+            hipLaunchKernelGGL((untiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, false>), grid, block, 0, st, g, io, sc);
     }
     return hipGetLastError();
 }
@@ -217,24 +217,31 @@ hipError_t launch_gather_step(const GatherGraph &g, const StateIO &io, const Ste
 {
     if (g.n == 0)
         return hipSuccess;
-    const bool act = g.act_c != nullptr, dampv = g.c != nullptr, rest = g.d0 != nullptr;
+    const bool act = g.act_c != nullptr, wave = act && g.t_off != nullptr, dampv = g.c != nullptr,
+               rest = g.d0 != nullptr;
     const bool damp = dampv || g.c_uniform != 0.f;
     tiled = tiled && g.nbr_local != nullptr;
-    // (ACT, DAMP, DAMPV, REST); DAMPV implies DAMP.
-    const int key = (act ? 8 : 0) | (damp ? 4 : 0) | (dampv ? 2 : 0) | (rest ? 1 : 0);
+    // (ACT, WAVE, DAMP, DAMPV, REST); WAVE implies ACT, DAMPV implies DAMP.
+    const int key = (act ? 8 : 0) | (damp ? 4 : 0) | (dampv ? 2 : 0) | (rest ? 1 : 0) | (wave ? 16 : 0);
     switch (key) {
-    case 0: return launch4<false, false, false, false>(g, io, sc, forces_only, tiled, stream);
-    case 1: return launch4<false, false, false, true>(g, io, sc, forces_only, tiled, stream);
-    case 4: return launch4<false, true, false, false>(g, io, sc, forces_only, tiled, stream);
-    case 5: return launch4<false, true, false, true>(g, io, sc, forces_only, tiled, stream);
-    case 6: return launch4<false, true, true, false>(g, io, sc, forces_only, tiled, stream);
-    case 7: return launch4<false, true, true, true>(g, io, sc, forces_only, tiled, stream);
-    case 8: return launch4<true, false, false, false>(g, io, sc, forces_only, tiled, stream);
-    case 9: return launch4<true, false, false, true>(g, io, sc, forces_only, tiled, stream);
-    case 12: return launch4<true, true, false, false>(g, io, sc, forces_only, tiled, stream);
-    case 13: return launch4<true, true, false, true>(g, io, sc, forces_only, tiled, stream);
-    case 14: return launch4<true, true, true, false>(g, io, sc, forces_only, tiled, stream);
-    case 15: return launch4<true, true, true, true>(g, io, sc, forces_only, tiled, stream);
+    case 0: return launch4<false, false, false, false, false>(g, io, sc, forces_only, tiled, stream);
+    case 1: return launch4<false, false, false, false, true>(g, io, sc, forces_only, tiled, stream);
+    case 4: return launch4<false, false, true, false, false>(g, io, sc, forces_only, tiled, stream);
+    case 5: return launch4<false, false, true, false, true>(g, io, sc, forces_only, tiled, stream);
+    case 6: return launch4<false, false, true, true, false>(g, io, sc, forces_only, tiled, stream);
+    case 7: return launch4<false, false, true, true, true>(g, io, sc, forces_only, tiled, stream);
+    case 8: return launch4<true, false, false, false, false>(g, io, sc, forces_only, tiled, stream);
+    case 9: return launch4<true, false, false, false, true>(g, io, sc, forces_only, tiled, stream);
+    case 12: return launch4<true, false, true, false, false>(g, io, sc, forces_only, tiled, stream);
+    case 13: return launch4<true, false, true, false, true>(g, io, sc, forces_only, tiled, stream);
+    case 14: return launch4<true, false, true, true, false>(g, io, sc, forces_only, tiled, stream);
+    case 15: return launch4<true, false, true, true, true>(g, io, sc, forces_only, tiled, stream);
+    case 24: return launch4<true, true, false, false, false>(g, io, sc, forces_only, tiled, stream);
+    case 25: return launch4<true, true, false, false, true>(g, io, sc, forces_only, tiled, stream);
+    case 28: return launch4<true, true, true, false, false>(g, io, sc, forces_only, tiled, stream);
+    case 29: return launch4<true, true, true, false, true>(g, io, sc, forces_only, tiled, stream);
+    case 30: return launch4<true, true, true, true, false>(g, io, sc, forces_only, tiled, stream);
+    case 31: return launch4<true, true, true, true, true>(g, io, sc, forces_only, tiled, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -31,7 +31,40 @@ struct SpringConst {
     float act_s;  // amp sin(phase)
     float d0;     // |R| - L0 (only with explicit rest lengths)
     float L0;     // rest length (only with explicit rest lengths)
+    double t_off; // wave-law offset t_o (only with the wave law)
 };
+
+// Actuation clock of one step: (sin, cos)(omega t_n) for the phasor law, and
+// t_n = n dt itself in FP64 for the wave law.
+struct Clock {
+    float2 tr;
+    double t;
+};
+
+// Actuation factor of one incidence: the rest length is L0 (1 + factor).
+// Phasor law: C sin(omega t) + S cos(omega t) = amp sin(omega t + phase).
+// Wave law (Sec. IV-B, Eqs. 3-4): amp sin(omega tau) with
+// tau = (t - t_o) mod t_p in [0, t_p).  The fold is done in FP64 with the same
+// operations as its definition, so which period a spring is in -- the
+// factor jumps at the period boundary -- does not depend on FP32 rounding.
+template <bool ACT, bool WAVE>
+__device__ __forceinline__ float act_factor(const SpringConst &p, const Clock &ck, const StepConsts &sc)
+{
+#pragma clang fp contract(off)
+    if (!ACT)
+        return 0.f;
+    if (!WAVE)
+        return fmaf(p.act_c, ck.tr.x, p.act_s * ck.tr.y);
+    const double u = ck.t - p.t_off;
+    const double tau = u - sc.period * floor(u / sc.period);
+    // omega tau reaches tens of radians: reduce it to [-pi, pi] in FP64
+    // before the FP32 sine, so the argument's rounding is that of a number
+    // below pi, not of omega tau
+    constexpr double kTwoPi = 6.283185307179586, kInvTwoPi = 0.15915494309189535;
+    const double arg = sc.omega * tau;
+    const double red = arg - kTwoPi * rint(arg * kInvTwoPi);
+    return p.act_c * sinf((float)red);
+}
 
 // Every floating-point operation below is spelled out: contraction of
 // multiplies and adds into FMAs is switched off and the FMAs that are wanted
@@ -45,8 +78,7 @@ struct SpringConst {
 template <bool ACT, bool DAMP, bool REST>
 __device__ __forceinline__ void spring_force(const float4 &xi, const float4 &ui, const float4 &vi,
                                              const float4 &xj, const float4 &uj, const float4 &vj,
-                                             const SpringConst &p, float sin_wt, float cos_wt,
-                                             float &fx, float &fy, float &fz)
+                                             const SpringConst &p, float act, float &fx, float &fy, float &fz)
 {
 #pragma clang fp contract(off)
     const float Rx = xj.x - xi.x, Ry = xj.y - xi.y, Rz = xj.z - xi.z;
@@ -68,9 +100,9 @@ __device__ __forceinline__ void spring_force(const float4 &xi, const float4 &ui,
     if (REST) {
         stretch += p.d0;
         if (ACT)
-            stretch = fmaf(-p.L0, fmaf(p.act_c, sin_wt, p.act_s * cos_wt), stretch);
+            stretch = fmaf(-p.L0, act, stretch);
     } else if (ACT) {
-        stretch = fmaf(-r, fmaf(p.act_c, sin_wt, p.act_s * cos_wt), stretch);
+        stretch = fmaf(-r, act, stretch);
     }
     const float ux = dx * il, uy = dy * il, uz = dz * il;
     float mag = p.k * stretch;
@@ -142,16 +174,17 @@ __device__ __forceinline__ T const_load(const T *p)
 
 // NT: the constants are streamed once per launch (gather engines); the
 // batched engine reads them every step of a launch and keeps them cached.
-template <bool ACT, bool DAMPV, bool REST, bool NT>
+template <bool ACT, bool DAMPV, bool REST, bool NT, bool WAVE = false>
 __device__ __forceinline__ SpringConst load_const(const GatherGraph &g, int64_t e)
 {
     SpringConst p;
     p.k = g.k ? const_load<NT>(g.k + e) : g.k_uniform;
     p.c = DAMPV ? const_load<NT>(g.c + e) : g.c_uniform;
     p.act_c = ACT ? const_load<NT>(g.act_c + e) : 0.f;
-    p.act_s = ACT ? const_load<NT>(g.act_s + e) : 0.f;
+    p.act_s = (ACT && !WAVE) ? const_load<NT>(g.act_s + e) : 0.f;
     p.d0 = REST ? const_load<NT>(g.d0 + e) : 0.f;
     p.L0 = REST ? const_load<NT>(g.rest + e) : 0.f;
+    p.t_off = WAVE ? const_load<NT>(g.t_off + e) : 0.0;
     return p;
 }
 
@@ -164,10 +197,11 @@ __device__ __forceinline__ SpringConst load_const(const GatherGraph &g, int64_t 
 // fetches that neighbour's state.
 constexpr int kUnroll = TITAN_UNROLL;
 
-template <bool ACT, bool DAMP, bool DAMPV, bool REST, bool NT, class Nbr, class State>
+template <bool ACT, bool DAMP, bool DAMPV, bool REST, bool NT, bool WAVE, class Nbr, class State>
 __device__ __forceinline__ void sum_forces(const GatherGraph &g, int64_t base, int width, const float4 &xi,
-                                           const float4 &ui, const float4 &vi, float2 tr, Nbr nbr,
-                                           State state, float &fx, float &fy, float &fz)
+                                           const float4 &ui, const float4 &vi, const Clock &ck,
+                                           const StepConsts &sc, Nbr nbr, State state, float &fx, float &fy,
+                                           float &fz)
 {
     int w = 0;
     for (; w + kUnroll <= width; w += kUnroll) {
@@ -177,22 +211,23 @@ __device__ __forceinline__ void sum_forces(const GatherGraph &g, int64_t base, i
         for (int u = 0; u < kUnroll; ++u) {
             const int64_t e = base + (int64_t)(w + u) * kSlice;
             ref[u] = nbr(e);
-            p[u] = load_const<ACT, DAMPV, REST, NT>(g, e);
+            p[u] = load_const<ACT, DAMPV, REST, NT, WAVE>(g, e);
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             float4 xj, uj, vj;
             state(ref[u], xj, uj, vj);
-            spring_force<ACT, DAMP, REST>(xi, ui, vi, xj, uj, vj, p[u], tr.x, tr.y, fx, fy, fz);
+            spring_force<ACT, DAMP, REST>(xi, ui, vi, xj, uj, vj, p[u], act_factor<ACT, WAVE>(p[u], ck, sc), fx, fy,
+                                          fz);
         }
     }
     for (; w < width; ++w) {
         const int64_t e = base + (int64_t)w * kSlice;
         const int ref = nbr(e);
-        const SpringConst p = load_const<ACT, DAMPV, REST, NT>(g, e);
+        const SpringConst p = load_const<ACT, DAMPV, REST, NT, WAVE>(g, e);
         float4 xj, uj, vj;
         state(ref, xj, uj, vj);
-        spring_force<ACT, DAMP, REST>(xi, ui, vi, xj, uj, vj, p, tr.x, tr.y, fx, fy, fz);
+        spring_force<ACT, DAMP, REST>(xi, ui, vi, xj, uj, vj, p, act_factor<ACT, WAVE>(p, ck, sc), fx, fy, fz);
     }
 }
 

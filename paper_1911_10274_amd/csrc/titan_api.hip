@@ -143,6 +143,10 @@ static int check_params(const titan_params *p)
         return fail(TITAN_EINVAL, "omega must be finite");
     if (p->engine < TITAN_ENGINE_AUTO || p->engine > TITAN_ENGINE_TILED)
         return fail(TITAN_EINVAL, "unknown engine %d", p->engine);
+    if (p->actuation != TITAN_ACT_PHASOR && p->actuation != TITAN_ACT_WAVE)
+        return fail(TITAN_EINVAL, "unknown actuation %d", p->actuation);
+    if (p->actuation == TITAN_ACT_WAVE && !(std::isfinite(p->wave_period) && p->wave_period > 0))
+        return fail(TITAN_EINVAL, "wave_period must be finite and > 0 (got %g)", p->wave_period);
     return TITAN_OK;
 }
 
@@ -312,6 +316,8 @@ extern "C" int titan_set_params(titan_sim *s, const titan_params *p)
         return rc;
     if (s->finalized && p->engine != s->params.engine && p->engine != TITAN_ENGINE_AUTO)
         return fail(TITAN_ESTATE, "the engine can only be chosen before the first step");
+    if (s->finalized && p->actuation != s->params.actuation)
+        return fail(TITAN_ESTATE, "the actuation law can only be chosen before the first step");
     const int32_t engine = s->finalized ? s->params.engine : p->engine;
     s->params = *p;
     s->params.engine = engine;
@@ -828,6 +834,8 @@ extern "C" int titan_rollout_grad(titan_sim *s, int64_t nsteps, int32_t checkpoi
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
+    if (s->params.actuation != TITAN_ACT_PHASOR)
+        return fail(TITAN_ESTATE, "the rollout adjoint covers phasor actuation only");
     if (int rc = ready(s))
         return rc;
     return rollout_grad(s, nsteps, checkpoint_every, body_weights, loss_out, grad_k, grad_act_c, grad_act_s);

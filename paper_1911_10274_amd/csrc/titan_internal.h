@@ -20,7 +20,10 @@ struct StepConsts {
     float mu;
     int32_t ground;
     const float2 *trig;  // entry of this step (gather engines) or of the chunk's first step (batched)
-    int64_t step;        // step index n (for the non-finite report)
+    int64_t step;        // step index n (first step of the chunk, batched)
+    double dt64;         // dt in FP64: the wave law's clock t_n = n * dt64
+    double period;       // wave law: period t_p
+    double omega;        // wave law: angular frequency
 };
 
 // Largest number of steps whose clock entries one table holds.
@@ -66,6 +69,7 @@ struct GatherGraph {
     const float *c;            // [slots] damping, or null: c_uniform
     const float *act_c;        // [slots] amp*cos(phase), or null: no actuation
     const float *act_s;        // [slots] amp*sin(phase)
+    const double *t_off;       // [slots] wave-law offsets t_o, or null: phasor law (act_s used)
     const float *d0;           // [slots] |R| - rest (FP64-rounded), or null: rest = |R|
     const float *rest;         // [slots] rest length (with d0)
     const float4 *X0;          // [n] reference positions (w unused)

@@ -30,6 +30,8 @@ ENGINE_AUTO = 0
 ENGINE_GATHER = 1
 ENGINE_BATCHED = 2
 ENGINE_TILED = 3
+ACT_PHASOR = 0
+ACT_WAVE = 1
 
 _ERR_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE", ENONFINITE: "ENONFINITE"}
 
@@ -49,6 +51,8 @@ class _Params(ctypes.Structure):
         ("ground_k", ctypes.c_double),
         ("friction_mu", ctypes.c_double),
         ("omega", ctypes.c_double),
+        ("actuation", ctypes.c_int32),
+        ("wave_period", ctypes.c_double),
     ]
 
 
@@ -170,6 +174,8 @@ class Params:
     friction_mu: float = 0.5
     omega: float = 0.0
     engine: int = ENGINE_AUTO
+    actuation: int = ACT_PHASOR
+    wave_period: float = 1.0
 
     def _c(self) -> _Params:
         p = _Params()
@@ -180,6 +186,8 @@ class Params:
         p.ground_k = self.ground_k
         p.friction_mu = self.friction_mu
         p.omega = self.omega
+        p.actuation = int(self.actuation)
+        p.wave_period = self.wave_period
         return p
 
 
