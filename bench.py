@@ -226,6 +226,34 @@ def bench_adjoint(T, robots_n: int, steps: int, K: int):
             "forward_ms": ms_fwd, "gradient_over_forward": sec * 1e3 / ms_fwd}
 
 
+def bench_worms(T, count: int = 100, steps: int = 10000):
+    """The paper's worm swarm (Sec. IV-B): ``count`` 27 x 5 x 3 worms
+    (339,200 springs for 100), wave actuation omega = 20, t_p = 1 s, c = 0.2,
+    dt = 1e-4: one simulated second, batched engine and plain engine."""
+    import torch
+
+    from paper_1911_10274_amd import scenes
+
+    sc = scenes.worm_batch(count)
+    ns = sc["ends"].shape[0]
+    out = {"workload": f"{count} worms (27x5x3 lattice each), wave actuation, {steps} steps of dt = 1e-4",
+           "worms": count, "masses": sc["pos"].shape[0], "springs": ns, "steps": steps}
+    for name, eng in (("batched", T.ENGINE_BATCHED), ("plain", T.ENGINE_TILED)):
+        tp = T.Params(dt=1e-4, gravity=(0.0, 0.0, -9.81), ground=True, ground_k=1e5, friction_mu=0.5, omega=20.0,
+                      engine=eng, actuation=T.ACT_WAVE, wave_period=1.0)
+        sim = T.sim_from_scene(sc, tp)
+        sim.finalize()
+        sim.step(100)
+        sim.sync()
+        ms = _timed_steps(sim, steps, torch.cuda.current_stream())
+        if name == "batched":
+            out["com_dx_m_after_1s"] = [float(d) for d in sim.body_displacement()[:, 0][:3]]
+        sim.close()
+        out[name] = {"spring_updates_per_s": ns * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+                     "times_real_time": steps * 1e-4 / (ms * 1e-3)}
+    return out
+
+
 def bench_surrogate(T, batch: int = 1024, steps: int = 60, gemm_n: int = 8192):
     """Training throughput of the surrogate network (1536 -> 512 x 4 -> 3,
     Adam) on the library's BF16 MFMA kernels at the training batch size, and
@@ -284,6 +312,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate training / GEMM figures")
+    ap.add_argument("--worms", type=int, default=100, help="worms in the wave-actuation workload (0: skip)")
     ap.add_argument("--engine", choices=("tiled", "gather"), default="tiled")
     ap.add_argument("--robots", type=int, default=4096, help="voxel robots in the batched workload (0: skip)")
     ap.add_argument("--robot-steps", type=int, default=2000)
@@ -374,6 +403,8 @@ def main():
         out["batched"] = bench_batched(T, args.robots, args.robot_steps, args.loop_sample)
     if args.adjoint_robots > 0:
         out["adjoint"] = bench_adjoint(T, args.adjoint_robots, 500, 50)
+    if args.worms > 0:
+        out["worms"] = bench_worms(T, args.worms)
     if not args.no_surrogate:
         out["surrogate"] = bench_surrogate(T)
     print(json.dumps(out))
