@@ -157,7 +157,11 @@ int titan_destroy(titan_sim *sim);
  * NULL for zero.  mass_n: kg, >= 0; 0 marks a pinned mass that never moves.
  * body_n: NULL, or the independent body each mass belongs to (>= 0); springs
  * may not join masses of different bodies.  *first_out (may be NULL) gets the
- * index of the first new mass.  Only before the first titan_step. */
+ * index of the first new mass.  After the first step (a topology edit,
+ * Sec. III-C, applied from the next enqueued step on): the new masses start
+ * with zero displacement from pos and must form new bodies (ids above every
+ * existing id) or join the only body of a single-body system; the device
+ * layout is rebuilt before the next step. */
 int titan_add_masses(titan_sim *sim, int64_t n, const float *pos_n3, const float *vel_n3,
                      const float *mass_n, const int32_t *body_n, int64_t *first_out);
 
@@ -166,11 +170,29 @@ int titan_add_masses(titan_sim *sim, int64_t n, const float *pos_n3, const float
  * stiffness N/m (>= 0).  damping_n: axial damping N*s/m (>= 0) or NULL for 0.
  * rest_n: rest lengths (> 0) or NULL for the initial lengths.  amp_n,
  * phase_n: actuation (both or neither; Sec. IV-B Eq. 4): the rest length at
- * time t is rest * (1 + amp*sin(omega*t + phase)).  Only before the first
- * titan_step.  *first_out (may be NULL) gets the first new spring's index. */
+ * time t is rest * (1 + amp*sin(omega*t + phase)).  *first_out (may be NULL)
+ * gets the first new spring's index.  After the first step (a topology edit,
+ * Sec. III-C, applied from the next enqueued step on): a NULL rest length
+ * means the distance between the ends after the steps already enqueued (the
+ * call waits for them), which must be > 0; the device layout is rebuilt
+ * before the next step, with spare slots per row for later additions. */
 int titan_add_springs(titan_sim *sim, int64_t n, const int64_t *ends_n2, const float *k_n,
                       const float *damping_n, const float *rest_n, const float *amp_n,
                       const float *phase_n, int64_t *first_out);
+
+/* Remove n springs (indices from titan_add_springs; repeats and springs
+ * already removed are ignored) -- Sec. III-C's deletion.  Applies from the
+ * next enqueued step on (while paused at a breakpoint: from the breakpoint
+ * on).  The spring keeps its index; on a current device layout the removal
+ * is O(1) per spring: its two incidence slots get k = 0 and no damping, so the
+ * ends add an exact zero where its force was and every other result is
+ * bitwise unchanged.  Layouts rebuilt later leave it out. */
+int titan_remove_springs(titan_sim *sim, int64_t n, const int64_t *springs_n);
+
+/* Remove n masses: every spring touching them is removed (as above) and the
+ * masses stay where they are, pinned (mass 0) and at rest.  Indices are kept.
+ * Cost O(springs) to find the touching springs. */
+int titan_remove_masses(titan_sim *sim, int64_t n, const int64_t *masses_n);
 
 /* Replace the parameters.  Takes effect for steps enqueued after this call
  * (while paused at a breakpoint: from the breakpoint on).  The engine field

@@ -333,7 +333,9 @@ __global__ void gather_spring_grads(const float4 *gslot, const int64_t *owner_sl
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= ns)
         return;
-    const float4 v = gslot[owner_slot[s]];
+    // a removed spring has no slot and no gradient
+    const int64_t e = owner_slot[s];
+    const float4 v = e >= 0 ? gslot[e] : make_float4(0.f, 0.f, 0.f, 0.f);
     gk[s] = v.x;
     gC[s] = v.y;
     gS[s] = v.z;

@@ -149,8 +149,11 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     // Incidence rows (internal order), each sorted by the neighbour's caller
     // index (then spring index): the summation order, hence the result, does
     // not depend on the internal order or on the tiling.
+    auto live = [&](int64_t q) { return s->h_removed.empty() || !s->h_removed[q]; };
     std::vector<int32_t> deg(n, 0);
     for (int64_t q = 0; q < ns; ++q) {
+        if (!live(q))
+            continue;
         ++deg[inv[s->h_ends[2 * q]]];
         ++deg[inv[s->h_ends[2 * q + 1]]];
     }
@@ -165,6 +168,8 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     {
         std::vector<int64_t> fill(rp.begin(), rp.end() - 1);
         for (int64_t q = 0; q < ns; ++q) {
+            if (!live(q))
+                continue;
             const int64_t a = s->h_ends[2 * q], b = s->h_ends[2 * q + 1];
             inc[fill[inv[a]]++] = {(int32_t)b, (int32_t)q};
             inc[fill[inv[b]]++] = {(int32_t)a, (int32_t)q};
@@ -199,12 +204,18 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     const bool tiled = allow_tiled && max_local * 3 * (int64_t)sizeof(float4) <= 65536;
 
     // Per-spring constants (FP64 -> FP32).
+    // (over the springs present; q0: the first of them)
+    int64_t q0 = -1;
     bool act = false, rest = false, damp_uniform = true, k_uniform = true;
     for (int64_t q = 0; q < ns; ++q) {
+        if (!live(q))
+            continue;
+        if (q0 < 0)
+            q0 = q;
         act |= s->h_amp[q] != 0.f;
         rest |= s->h_rest[q] > 0.f;
-        damp_uniform &= s->h_damp[q] == s->h_damp[0];
-        k_uniform &= s->h_k[q] == s->h_k[0];
+        damp_uniform &= s->h_damp[q] == s->h_damp[q0];
+        k_uniform &= s->h_k[q] == s->h_k[q0];
     }
     const bool wave = act && s->params.actuation == TITAN_ACT_WAVE;
     std::vector<float> sC, sS, sD0, sL0;
@@ -254,6 +265,7 @@ static int build_gather(titan_sim *s, bool allow_tiled)
         int32_t w = 0;
         for (int64_t i = sl * kSlice; i < std::min(n, (sl + 1) * kSlice); ++i)
             w = std::max(w, deg[i]);
+        w += s->slack;  // spare slots for springs added later (after an edit)
         off[sl + 1] = off[sl] + (int64_t)w * kSlice;
     }
     const int64_t slots = off[nsl];
@@ -331,8 +343,8 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     g.n_slices = nsl;
     g.n_tiles = nt;
     g.max_local = max_local;
-    g.c_uniform = (ns > 0 && damp_uniform) ? s->h_damp[0] : 0.f;
-    g.k_uniform = (ns > 0 && k_uniform) ? s->h_k[0] : 0.f;
+    g.c_uniform = (q0 >= 0 && damp_uniform) ? s->h_damp[q0] : 0.f;
+    g.k_uniform = (q0 >= 0 && k_uniform) ? s->h_k[q0] : 0.f;
     if (int rc = put(s, off, &g.slice_off))
         return rc;
     if (int rc = put(s, deg, &g.deg))
@@ -380,8 +392,18 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     return TITAN_OK;
 }
 
+// Allocations made while an engine's layout is built or updated belong to the
+// engine (freed when the layout is rebuilt).
+struct EngineAllocs {
+    titan_sim *s;
+    bool was;
+    explicit EngineAllocs(titan_sim *sim) : s(sim), was(sim->engine_allocs) { s->engine_allocs = true; }
+    ~EngineAllocs() { s->engine_allocs = was; }
+};
+
 int build_engines(titan_sim *s)
 {
+    EngineAllocs mark(s);
     const int want = s->params.engine;
     if (int rc = dev_alloc(s, sizeof(float2) * (kTrigChunk + 1), (void **)&s->trig))
         return rc;
@@ -403,20 +425,25 @@ int build_engines(titan_sim *s)
     return TITAN_OK;
 }
 
-// Spring constants changed after the device layout exists: both incidence
-// slots of every changed spring are rewritten on the device, in stream order.
-// A uniform stiffness/damping that stops being uniform, or actuation that
-// appears, gets its per-slot array first.
-int update_springs(titan_sim *s, int64_t first, int64_t count, const float *k, const float *damping,
-                   const float *amp, const float *phase)
+// Spring constants changed after the device layout exists (the new values
+// are in the host table): both incidence slots of every listed spring that is
+// in the layout are rewritten on the device, in stream order.  A uniform
+// stiffness/damping that stops being uniform, or actuation that appears, gets
+// its per-slot array first.
+int update_spring_list(titan_sim *s, const std::vector<int64_t> &springs, bool k, bool damping, bool amp,
+                       bool force)
 {
+    EngineAllocs mark(s);
     GatherGraph &g = s->gg;
-    const int64_t m = 2 * count;
-    std::vector<int64_t> slot(m);
-    for (int64_t q = 0; q < count; ++q) {
-        slot[2 * q] = s->h_owner_slot[first + q];
-        slot[2 * q + 1] = s->h_other_slot[first + q];
-    }
+    std::vector<int64_t> slot, of;
+    for (int64_t q : springs)
+        if (s->h_owner_slot[q] >= 0) {
+            slot.push_back(s->h_owner_slot[q]);
+            slot.push_back(s->h_other_slot[q]);
+            of.push_back(q);
+            of.push_back(q);
+        }
+    const int64_t m = (int64_t)slot.size();
     std::vector<void *> tmp;
     auto cleanup = [&]() {
         for (void *p : tmp)
@@ -432,62 +459,90 @@ int update_springs(titan_sim *s, int64_t first, int64_t count, const float *k, c
         return rc;
     }
     tmp.push_back(dval);
-    if (m)
-        HIP_TRY(s, hipMemcpyAsync(dslot, slot.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, s->stream));
     std::vector<float> val(m);
     // one per-slot array: allocate it (filled with `fill`) if absent, then scatter
-    auto apply = [&](const float **arr, float fill, auto value_of) -> int {
+    auto apply = [&](const float **arr, float fill, auto value_of) -> hipError_t {
         if (!*arr) {
             float *p = nullptr;
-            if (int rc = dev_alloc(s, sizeof(float) * std::max<int64_t>(s->n_slots, 1), (void **)&p))
-                return rc;
-            HIP_TRY(s, launch_fill(p, fill, s->n_slots, s->stream));
+            if (dev_alloc(s, sizeof(float) * std::max<int64_t>(s->n_slots, 1), (void **)&p))
+                return hipErrorOutOfMemory;
+            if (hipError_t e = launch_fill(p, fill, s->n_slots, s->stream))
+                return e;
             *arr = p;
         }
-        for (int64_t q = 0; q < count; ++q)
-            val[2 * q] = val[2 * q + 1] = value_of(first + q);
-        if (m)
-            HIP_TRY(s, hipMemcpyAsync(dval, val.data(), sizeof(float) * m, hipMemcpyHostToDevice, s->stream));
-        HIP_TRY(s, launch_scatter(const_cast<float *>(*arr), dslot, dval, m, s->stream));
+        if (m == 0)
+            return hipSuccess;
+        for (int64_t e = 0; e < m; ++e)
+            val[e] = value_of(of[e]);
+        if (hipError_t e = hipMemcpyAsync(dval, val.data(), sizeof(float) * m, hipMemcpyHostToDevice, s->stream))
+            return e;
+        if (hipError_t e = launch_scatter(const_cast<float *>(*arr), dslot, dval, m, s->stream))
+            return e;
         // the staging values are reused by the next array: wait for this one
-        HIP_TRY(s, hipStreamSynchronize(s->stream));
-        return TITAN_OK;
+        return hipStreamSynchronize(s->stream);
     };
+    // uniform over the springs present?
+    auto uniform_of = [&](const std::vector<float> &v, float &u) {
+        bool seen = false;
+        for (int64_t q = 0; q < s->ns; ++q) {
+            if (!s->h_removed.empty() && s->h_removed[q])
+                continue;
+            if (!seen) {
+                u = v[q];
+                seen = true;
+            } else if (v[q] != u) {
+                return false;
+            }
+        }
+        return seen;
+    };
+    hipError_t e = hipSuccess;
     int rc = TITAN_OK;
-    if (k) {
-        bool uniform = count == s->ns;
-        for (int64_t q = 0; q < s->ns && uniform; ++q)
-            uniform = s->h_k[q] == s->h_k[0];
-        if (!g.k && uniform && s->ns > 0)
-            g.k_uniform = s->h_k[0];
+    if (m)
+        e = hipMemcpyAsync(dslot, slot.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, s->stream);
+    if (!e && k) {
+        float u = 0.f;
+        if (!g.k && !force && uniform_of(s->h_k, u))
+            g.k_uniform = u;
         else
-            rc = apply(&g.k, g.k_uniform, [&](int64_t q) { return s->h_k[q]; });
+            e = apply(&g.k, g.k_uniform, [&](int64_t q) { return s->h_k[q]; });
     }
-    if (!rc && damping) {
-        bool uniform = true;
-        for (int64_t q = 0; q < s->ns && uniform; ++q)
-            uniform = s->h_damp[q] == s->h_damp[0];
-        if (!g.c && uniform && s->ns > 0)
-            g.c_uniform = s->h_damp[0];
+    if (!e && damping) {
+        float u = 0.f;
+        if (!g.c && !force && uniform_of(s->h_damp, u))
+            g.c_uniform = u;
         else
-            rc = apply(&g.c, g.c_uniform, [&](int64_t q) { return s->h_damp[q]; });
+            e = apply(&g.c, g.c_uniform, [&](int64_t q) { return s->h_damp[q]; });
     }
-    if (!rc && amp && g.t_off) {
+    if (!e && amp && g.t_off) {
         // wave law: the amplitude is the factor; the offsets stay those of Eq. 5
-        rc = apply(&g.act_c, 0.f, [&](int64_t q) { return s->h_amp[q]; });
-    } else if (!rc && amp && s->params.actuation == TITAN_ACT_WAVE) {
+        e = apply(&g.act_c, 0.f, [&](int64_t q) { return s->h_amp[q]; });
+    } else if (!e && amp && s->params.actuation == TITAN_ACT_WAVE) {
         rc = fail(TITAN_ESTATE, "wave actuation must be present when the system is finalized");
-    } else if (!rc && amp) {
-        rc = apply(&g.act_c, 0.f, [&](int64_t q) {
+    } else if (!e && amp) {
+        e = apply(&g.act_c, 0.f, [&](int64_t q) {
             return (float)((double)s->h_amp[q] * std::cos((double)s->h_phase[q]));
         });
-        if (!rc)
-            rc = apply(&g.act_s, 0.f, [&](int64_t q) {
+        if (!e)
+            e = apply(&g.act_s, 0.f, [&](int64_t q) {
                 return (float)((double)s->h_amp[q] * std::sin((double)s->h_phase[q]));
             });
     }
+    if (e != hipSuccess)
+        rc = e == hipErrorOutOfMemory ? fail(TITAN_ENOMEM, "out of device memory updating spring constants")
+                                      : hip_fail(s, e, "updating spring constants");
     cleanup();
     return rc;
+}
+
+int update_springs(titan_sim *s, int64_t first, int64_t count, const float *k, const float *damping,
+                   const float *amp, const float *phase)
+{
+    (void)phase;
+    std::vector<int64_t> list(count);
+    for (int64_t q = 0; q < count; ++q)
+        list[q] = first + q;
+    return update_spring_list(s, list, k != nullptr, damping != nullptr, amp != nullptr, false);
 }
 
 StepConsts consts_for(const titan_sim *s, int64_t step, const float2 *trig)
@@ -549,5 +604,21 @@ int compute_forces(titan_sim *s)
 }
 
 void destroy_engines(titan_sim *s) { destroy_batch_engine(s); }
+
+int rebuild_engines(titan_sim *s)
+{
+    destroy_batch_engine(s);
+    dev_free_engine(s);
+    s->gg = GatherGraph{};
+    s->tiled = false;
+    s->trig = nullptr;
+    s->n_slots = 0;
+    s->h_slot_nbr.clear();
+    if (int rc = build_engines(s))
+        return rc;
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    s->layout_dirty = false;
+    return TITAN_OK;
+}
 
 }  // namespace titan

@@ -75,7 +75,7 @@ int titan::dev_alloc(titan_sim *s, size_t bytes, void **out)
                         "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
         }
     }
-    s->allocations.push_back({p, bytes});
+    s->allocations.push_back({p, bytes, s->engine_allocs});
     s->device_bytes += (int64_t)bytes;
     *out = p;
     return TITAN_OK;
@@ -92,19 +92,35 @@ static void release(titan_sim *s, void *p)
 void titan::dev_free(titan_sim *s, void *p)
 {
     for (size_t q = 0; q < s->allocations.size(); ++q)
-        if (s->allocations[q].first == p) {
+        if (s->allocations[q].p == p) {
             (void)hipStreamSynchronize(s->stream);
             release(s, p);
-            s->device_bytes -= (int64_t)s->allocations[q].second;
+            s->device_bytes -= (int64_t)s->allocations[q].bytes;
             s->allocations.erase(s->allocations.begin() + q);
             return;
         }
 }
 
+// Free every allocation of the engines' layouts (after the queued work).
+void titan::dev_free_engine(titan_sim *s)
+{
+    (void)hipStreamSynchronize(s->stream);
+    std::vector<titan_sim::Allocation> keep;
+    for (auto &a : s->allocations) {
+        if (a.engine) {
+            release(s, a.p);
+            s->device_bytes -= (int64_t)a.bytes;
+        } else {
+            keep.push_back(a);
+        }
+    }
+    s->allocations.swap(keep);
+}
+
 static void dev_free_all(titan_sim *s)
 {
     for (auto &a : s->allocations)
-        release(s, a.first);
+        release(s, a.p);
     s->allocations.clear();
     s->device_bytes = 0;
 }
@@ -208,14 +224,15 @@ extern "C" int titan_destroy(titan_sim *s)
 // ABI: building the system
 // ---------------------------------------------------------------------------
 
+static int add_masses_live(titan_sim *s, int64_t n, const float *pos, const float *vel, const float *mass,
+                           const int32_t *body, int64_t *first_out);
+
 extern "C" int titan_add_masses(titan_sim *s, int64_t n, const float *pos, const float *vel, const float *mass,
                                 const int32_t *body, int64_t *first_out)
 {
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->finalized)
-        return fail(TITAN_ESTATE, "masses can only be added before the first step");
     if (n < 0)
         return fail(TITAN_EINVAL, "negative count");
     if (n > 0 && (!pos || !mass))
@@ -232,6 +249,8 @@ extern "C" int titan_add_masses(titan_sim *s, int64_t n, const float *pos, const
         if (body && body[i] < 0)
             return fail(TITAN_EINVAL, "mass %lld: negative body id", (long long)i);
     }
+    if (s->finalized)
+        return add_masses_live(s, n, pos, vel, mass, body, first_out);
     if (first_out)
         *first_out = (int64_t)s->h_mass.size();
     s->h_pos.insert(s->h_pos.end(), pos, pos + 3 * n);
@@ -253,8 +272,8 @@ extern "C" int titan_add_springs(titan_sim *s, int64_t n, const int64_t *ends, c
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->finalized)
-        return fail(TITAN_ESTATE, "springs can only be added before the first step");
+    if (s->finalized && s->dev_error)
+        return fail(TITAN_EDEVICE, "sim is in a failed device state");
     if (n < 0)
         return fail(TITAN_EINVAL, "negative count");
     if (n > 0 && (!ends || !k))
@@ -272,10 +291,12 @@ extern "C" int titan_add_springs(titan_sim *s, int64_t n, const int64_t *ends, c
             return fail(TITAN_EINVAL, "spring %lld: both ends are mass %lld", (long long)q, (long long)i);
         if (s->h_body[i] != s->h_body[j])
             return fail(TITAN_EINVAL, "spring %lld joins bodies %d and %d", (long long)q, s->h_body[i], s->h_body[j]);
-        const float *a = &s->h_pos[3 * i], *b = &s->h_pos[3 * j];
-        const double dx = (double)b[0] - a[0], dy = (double)b[1] - a[1], dz = (double)b[2] - a[2];
-        if (!(dx * dx + dy * dy + dz * dz > 0))
-            return fail(TITAN_EINVAL, "spring %lld: zero initial length", (long long)q);
+        if (!s->finalized) {
+            const float *a = &s->h_pos[3 * i], *b = &s->h_pos[3 * j];
+            const double dx = (double)b[0] - a[0], dy = (double)b[1] - a[1], dz = (double)b[2] - a[2];
+            if (!(dx * dx + dy * dy + dz * dz > 0))
+                return fail(TITAN_EINVAL, "spring %lld: zero initial length", (long long)q);
+        }
         if (!(std::isfinite(k[q]) && k[q] >= 0.f))
             return fail(TITAN_EINVAL, "spring %lld: k must be finite and >= 0", (long long)q);
         if (damping && !(std::isfinite(damping[q]) && damping[q] >= 0.f))
@@ -284,6 +305,26 @@ extern "C" int titan_add_springs(titan_sim *s, int64_t n, const int64_t *ends, c
             return fail(TITAN_EINVAL, "spring %lld: rest length must be finite and > 0", (long long)q);
         if (amp && !(std::isfinite(amp[q]) && std::isfinite(phase[q])))
             return fail(TITAN_EINVAL, "spring %lld: non-finite actuation", (long long)q);
+    }
+    // After the first step a spring without a rest length is at rest at the
+    // current positions (the state after the queued steps).
+    std::vector<float> live_rest;
+    if (s->finalized && n > 0) {
+        std::vector<float4> hU(s->n);
+        HIP_TRY(s, hipMemcpyAsync(hU.data(), s->U[s->cur], sizeof(float4) * s->n, hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(s, hipStreamSynchronize(s->stream));
+        live_rest.resize(n);
+        for (int64_t q = 0; q < n; ++q) {
+            const int64_t a = s->inv_perm_of(ends[2 * q]), b = s->inv_perm_of(ends[2 * q + 1]);
+            const double dx = ((double)s->hX0[b].x + hU[b].x) - ((double)s->hX0[a].x + hU[a].x);
+            const double dy = ((double)s->hX0[b].y + hU[b].y) - ((double)s->hX0[a].y + hU[a].y);
+            const double dz = ((double)s->hX0[b].z + hU[b].z) - ((double)s->hX0[a].z + hU[a].z);
+            const double len = std::sqrt(dx * dx + dy * dy + dz * dz);
+            if (!(len > 0))
+                return fail(TITAN_EINVAL, "spring %lld: zero current length", (long long)q);
+            live_rest[q] = rest ? rest[q] : (float)len;
+        }
+        rest = live_rest.data();
     }
     if (first_out)
         *first_out = (int64_t)s->h_k.size();
@@ -304,6 +345,181 @@ extern "C" int titan_add_springs(titan_sim *s, int64_t n, const int64_t *ends, c
         s->h_amp.insert(s->h_amp.end(), (size_t)n, 0.f);
         s->h_phase.insert(s->h_phase.end(), (size_t)n, 0.f);
     }
+    if (!s->h_removed.empty())
+        s->h_removed.resize(s->h_k.size(), 0);
+    if (s->finalized && n > 0) {
+        s->ns = (int64_t)s->h_k.size();
+        s->h_owner_slot.resize(s->ns, -1);
+        s->h_other_slot.resize(s->ns, -1);
+        s->layout_dirty = true;
+        s->slack = std::max(s->slack, 2);
+    }
+    return TITAN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// topology edits after the first step
+// ---------------------------------------------------------------------------
+
+// A device float4 array of n_old entries grown to n_old + tail.size(), the new
+// entries taken from tail (stream order).
+static int grow_state(titan_sim *s, float4 **buf, int64_t n_old, const std::vector<float4> &tail)
+{
+    const int64_t n_new = n_old + (int64_t)tail.size();
+    float4 *p = nullptr;
+    if (int rc = dev_alloc(s, sizeof(float4) * n_new, (void **)&p))
+        return rc;
+    if (n_old)
+        HIP_TRY(s, hipMemcpyAsync(p, *buf, sizeof(float4) * n_old, hipMemcpyDeviceToDevice, s->stream));
+    if (!tail.empty())
+        HIP_TRY(s, hipMemcpyAsync(p + n_old, tail.data(), sizeof(float4) * tail.size(), hipMemcpyHostToDevice,
+                                  s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    dev_free(s, *buf);
+    *buf = p;
+    return TITAN_OK;
+}
+
+// Masses added after the first step go after every existing mass in the
+// internal order (existing indices, state and snapshots keep their meaning).
+// They must start new bodies, or join the only body of a single-body system,
+// so that every body stays one contiguous run.
+static int add_masses_live(titan_sim *s, int64_t n, const float *pos, const float *vel, const float *mass,
+                           const int32_t *body, int64_t *first_out)
+{
+    if (s->dev_error)
+        return fail(TITAN_EDEVICE, "sim is in a failed device state");
+    int32_t maxb = -1;
+    for (int32_t b : s->h_body)
+        maxb = std::max(maxb, b);
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t b = body ? body[i] : 0;
+        if (!(b > maxb || (maxb == 0 && b == 0)))
+            return fail(TITAN_EINVAL, "mass %lld: masses added after the first step must start a new body "
+                                      "(or join the only body)", (long long)i);
+    }
+    const int64_t n_old = s->n;
+    if (first_out)
+        *first_out = n_old;
+    std::vector<float4> x0(n), u(n), v(n);
+    for (int64_t i = 0; i < n; ++i) {
+        x0[i] = make_float4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], 0.f);
+        u[i] = make_float4(0.f, 0.f, 0.f, mass[i] > 0.f ? (float)(1.0 / (double)mass[i]) : 0.f);
+        v[i] = vel ? make_float4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 0.f) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    if (int rc = grow_state(s, &s->X0, n_old, x0))
+        return rc;
+    for (int b = 0; b < 2; ++b) {
+        if (int rc = grow_state(s, &s->U[b], n_old, u))
+            return rc;
+        if (int rc = grow_state(s, &s->V[b], n_old, v))
+            return rc;
+    }
+    for (auto &kv : s->bps) {  // a snapshot before the masses existed holds their initial state
+        if (int rc = grow_state(s, &kv.second.snapU, n_old, u))
+            return rc;
+        if (int rc = grow_state(s, &kv.second.snapV, n_old, v))
+            return rc;
+    }
+    if (s->F) {
+        dev_free(s, s->F);
+        s->F = nullptr;
+    }
+    HIP_TRY(s, hipHostFree(s->host_stage));
+    s->host_stage = nullptr;
+    HIP_TRY(s, hipHostMalloc(&s->host_stage, sizeof(float4) * 2 * (n_old + n), hipHostMallocDefault));
+    s->hX0.insert(s->hX0.end(), x0.begin(), x0.end());
+    s->h_pos.insert(s->h_pos.end(), pos, pos + 3 * n);
+    if (vel)
+        s->h_vel.insert(s->h_vel.end(), vel, vel + 3 * n);
+    else
+        s->h_vel.insert(s->h_vel.end(), (size_t)(3 * n), 0.f);
+    s->h_mass.insert(s->h_mass.end(), mass, mass + n);
+    for (int64_t i = 0; i < n; ++i) {
+        s->h_body.push_back(body ? body[i] : 0);
+        s->perm.push_back(n_old + i);  // caller index n_old + i is internal index n_old + i
+        if (!s->inv_perm.empty())
+            s->inv_perm.push_back(n_old + i);
+    }
+    s->n = n_old + n;
+    s->layout_dirty = true;
+    return TITAN_OK;
+}
+
+// Springs removed: kept in the spring table, dropped from the layouts.  On a
+// current layout the removal is a tombstone -- k = 0 and damping 0 in the
+// spring's two slots -- so each end adds an exact zero in the spring's place
+// and every other bit of the step is unchanged.
+static int remove_springs_locked(titan_sim *s, const std::vector<int64_t> &list)
+{
+    if (s->h_removed.empty())
+        s->h_removed.assign(s->h_k.size(), 0);
+    std::vector<int64_t> now;
+    for (int64_t q : list)
+        if (!s->h_removed[q]) {
+            s->h_removed[q] = 1;
+            s->h_k[q] = 0.f;
+            s->h_damp[q] = 0.f;
+            now.push_back(q);
+        }
+    if (!s->finalized || s->layout_dirty || now.empty())
+        return TITAN_OK;
+    const bool damped = s->gg.c != nullptr || s->gg.c_uniform != 0.f;
+    return update_spring_list(s, now, true, damped, false, true);
+}
+
+extern "C" int titan_remove_springs(titan_sim *s, int64_t n, const int64_t *springs)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (n < 0 || (n > 0 && !springs))
+        return fail(TITAN_EINVAL, "bad spring list");
+    if (s->dev_error)
+        return fail(TITAN_EDEVICE, "sim is in a failed device state");
+    const int64_t ns = (int64_t)s->h_k.size();
+    std::vector<int64_t> list(springs, springs + n);
+    for (int64_t q : list)
+        if (q < 0 || q >= ns)
+            return fail(TITAN_EINVAL, "spring %lld out of range [0, %lld)", (long long)q, (long long)ns);
+    return remove_springs_locked(s, list);
+}
+
+extern "C" int titan_remove_masses(titan_sim *s, int64_t n, const int64_t *masses)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (n < 0 || (n > 0 && !masses))
+        return fail(TITAN_EINVAL, "bad mass list");
+    if (s->dev_error)
+        return fail(TITAN_EDEVICE, "sim is in a failed device state");
+    const int64_t nm = (int64_t)s->h_mass.size();
+    std::vector<uint8_t> gone(nm, 0);
+    for (int64_t k = 0; k < n; ++k) {
+        if (masses[k] < 0 || masses[k] >= nm)
+            return fail(TITAN_EINVAL, "mass %lld out of range [0, %lld)", (long long)masses[k], (long long)nm);
+        gone[masses[k]] = 1;
+    }
+    std::vector<int64_t> springs;
+    for (int64_t q = 0; q < (int64_t)s->h_k.size(); ++q)
+        if (gone[s->h_ends[2 * q]] || gone[s->h_ends[2 * q + 1]])
+            springs.push_back(q);
+    if (int rc = remove_springs_locked(s, springs))
+        return rc;
+    // a removed mass stays where it is, pinned and at rest
+    const float zero4[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t k = 0; k < n; ++k) {
+        s->h_mass[masses[k]] = 0.f;
+        if (s->finalized) {
+            const int64_t i = s->inv_perm_of(masses[k]);
+            HIP_TRY(s, hipMemcpyAsync(&s->U[s->cur][i].w, zero4, sizeof(float), hipMemcpyHostToDevice, s->stream));
+            HIP_TRY(s, hipMemcpyAsync(&s->V[s->cur][i], zero4, sizeof(float4), hipMemcpyHostToDevice, s->stream));
+        }
+    }
+    if (s->finalized)
+        HIP_TRY(s, hipStreamSynchronize(s->stream));
     return TITAN_OK;
 }
 
@@ -423,8 +639,18 @@ static int fire_breakpoints(titan_sim *s)
     return TITAN_OK;
 }
 
+// Layouts invalidated by topology edits are rebuilt before they are used.
+static int ensure_layout(titan_sim *s)
+{
+    if (!s->finalized || !s->layout_dirty)
+        return TITAN_OK;
+    return rebuild_engines(s);
+}
+
 static int pump(titan_sim *s)
 {
+    if (int rc = ensure_layout(s))
+        return rc;
     if (int rc = fire_breakpoints(s))
         return rc;
     while (!s->paused && s->step_enq < s->steps_req) {
@@ -707,6 +933,8 @@ extern "C" int titan_get_forces(titan_sim *s, int64_t first, int64_t count, floa
         return rc;
     if (!s->n)
         return TITAN_OK;
+    if (int rc = ensure_layout(s))
+        return rc;
     if (int rc = compute_forces(s))
         return rc;
     float4 *hF = s->host_stage;
@@ -837,6 +1065,8 @@ extern "C" int titan_rollout_grad(titan_sim *s, int64_t nsteps, int32_t checkpoi
     if (s->params.actuation != TITAN_ACT_PHASOR)
         return fail(TITAN_ESTATE, "the rollout adjoint covers phasor actuation only");
     if (int rc = ready(s))
+        return rc;
+    if (int rc = ensure_layout(s))
         return rc;
     return rollout_grad(s, nsteps, checkpoint_every, body_weights, loss_out, grad_k, grad_act_c, grad_act_s);
 }

@@ -44,8 +44,14 @@ struct titan_sim {
     bool dev_error = false;
     int device = 0;
     int engine = TITAN_ENGINE_GATHER;
-    std::vector<std::pair<void *, size_t>> allocations;
+    struct Allocation {
+        void *p;
+        size_t bytes;
+        bool engine;  // part of an engine's layout (freed when the layout is rebuilt)
+    };
+    std::vector<Allocation> allocations;
     int64_t device_bytes = 0;
+    bool engine_allocs = false;  // dev_alloc marks new allocations as the engine's
     int64_t n = 0, ns = 0;
     std::vector<int64_t> perm;      // perm[internal] = caller index
     std::vector<int64_t> inv_perm;  // inv_perm[caller] = internal index (empty: identity)
@@ -66,6 +72,12 @@ struct titan_sim {
     std::vector<int64_t> h_owner_slot;  // per spring (caller order): its slot at the lower-index end
     std::vector<int64_t> h_other_slot;  // per spring: its slot at the other end
     float2 *trig = nullptr;           // clock table: kTrigChunk entries + 1 for force queries
+
+    // topology edits after finalize: the engines' layouts are rebuilt before
+    // the next step when dirty; removed springs stay in the spring table
+    bool layout_dirty = false;
+    std::vector<uint8_t> h_removed;  // per spring (empty: none removed)
+    int32_t slack = 0;               // spare slots per row after an edit-triggered rebuild
 
     // batched engine (null unless selected) and the tuner's measurements
     titan::BatchEngine *batch = nullptr;
@@ -90,9 +102,14 @@ int fail(int code, const char *fmt, ...);
 int hip_fail(titan_sim *sim, hipError_t e, const char *what);
 int dev_alloc(titan_sim *s, size_t bytes, void **out);
 void dev_free(titan_sim *s, void *p);
+void dev_free_engine(titan_sim *s);
 int batch_threads(const titan_sim *s);
 int update_springs(titan_sim *s, int64_t first, int64_t count, const float *k, const float *damping,
                    const float *amp, const float *phase);
+// Same for a list of springs; the flags say which constants changed.  force:
+// write per-slot arrays even where the values stay uniform (removal).
+int update_spring_list(titan_sim *s, const std::vector<int64_t> &springs, bool k, bool damping, bool amp,
+                       bool force);
 int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weights, float *loss, float *gk,
                  float *gC, float *gS);
 
@@ -105,5 +122,8 @@ int enqueue_steps(titan_sim *s, int64_t first_step, int64_t count);
 int compute_forces(titan_sim *s);
 StepConsts consts_for(const titan_sim *s, int64_t step, const float2 *trig);
 void destroy_engines(titan_sim *s);
+// Rebuild the engines' layouts for the current topology, keeping the state,
+// the internal order and every device buffer that is not an engine's.
+int rebuild_engines(titan_sim *s);
 
 }  // namespace titan

@@ -121,6 +121,8 @@ def _load():
         "titan_set_step": ([_vp, ctypes.c_int64], ctypes.c_int),
         "titan_get_body_displacement": ([_vp, _fp], ctypes.c_int),
         "titan_set_springs": ([_vp, ctypes.c_int64, ctypes.c_int64, _fp, _fp, _fp, _fp], ctypes.c_int),
+        "titan_remove_springs": ([_vp, ctypes.c_int64, _i64p], ctypes.c_int),
+        "titan_remove_masses": ([_vp, ctypes.c_int64, _i64p], ctypes.c_int),
         "titan_rollout_grad": ([_vp, ctypes.c_int64, ctypes.c_int32, _fp, _fp, _fp, _fp, _fp], ctypes.c_int),
         "titan_get_info": ([_vp, ctypes.POINTER(_Info)], ctypes.c_int),
         "titan_mlp_create": ([ctypes.c_int32, _i32p, _vp, ctypes.POINTER(_Allocator), ctypes.POINTER(_vp)],
@@ -286,6 +288,16 @@ class Sim:
         first = ctypes.c_int64()
         _check(lib.titan_add_springs(self._h, n, e.ctypes.data_as(_i64p), kp, cp, rp, ap, php, ctypes.byref(first)))
         return first.value
+
+    def remove_springs(self, springs):
+        """Remove springs (titan_remove_springs)."""
+        q = np.ascontiguousarray(springs, dtype=np.int64).reshape(-1)
+        _check(lib.titan_remove_springs(self._h, q.size, q.ctypes.data_as(_i64p)))
+
+    def remove_masses(self, masses):
+        """Remove masses and their springs (titan_remove_masses)."""
+        q = np.ascontiguousarray(masses, dtype=np.int64).reshape(-1)
+        _check(lib.titan_remove_masses(self._h, q.size, q.ctypes.data_as(_i64p)))
 
     def set_params(self, params: Params):
         _check(lib.titan_set_params(self._h, ctypes.byref(params._c())))

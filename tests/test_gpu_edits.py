@@ -1,0 +1,208 @@
+"""Topology edits while a simulation runs (Sec. III-C: insertion and
+deletion of springs and masses), through the C ABI.
+
+Removal is checked bitwise against a fresh system built without the removed
+springs and started from the same state; insertion against the FP64 oracle
+from the GPU's state at the edit, per step, at the usual 1e-5 bar."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1911_10274_amd import scenes
+from tests.parity import TOL, compare_series, gpu_series
+
+pytestmark = pytest.mark.gpu
+
+DT = 5e-5
+OMEGA = 2 * math.pi * 2
+
+
+def _T():
+    from paper_1911_10274_amd import titan as T
+
+    return T
+
+
+def _params(engine=None):
+    T = _T()
+    return T.Params(dt=DT, gravity=(0.0, 0.0, -9.81), ground=True, ground_k=1e5, friction_mu=0.5, omega=OMEGA,
+                    engine=T.ENGINE_TILED if engine is None else engine)
+
+
+def _oparams():
+    return O.Params(dt=DT, gravity=(0.0, 0.0, -9.81), ground=True, ground_k=1e5, mu=0.5, omega=OMEGA)
+
+
+def _without(sc, drop):
+    keep = np.ones(sc["ends"].shape[0], bool)
+    keep[drop] = False
+    out = dict(sc)
+    for key in ("ends", "k", "damping", "amp", "phase"):
+        if sc.get(key) is not None:
+            out[key] = sc[key][keep]
+    return out
+
+
+@pytest.mark.parametrize("engine", ["gather", "tiled", "batched"])
+def test_removed_springs_bitwise_equal_a_system_without_them(engine):
+    T = _T()
+    eng = {"gather": T.ENGINE_GATHER, "tiled": T.ENGINE_TILED, "batched": T.ENGINE_BATCHED}[engine]
+    sc = scenes.jittered_actuated_lattice(n=12, seed=4)
+    rng = np.random.Generator(np.random.PCG64(9))
+    drop = rng.choice(sc["ends"].shape[0], 300, replace=False)
+    a = T.sim_from_scene(sc, _params(eng))
+    a.step(50)
+    p50, v50, _ = a.get_state(displacement=True)
+    a.remove_springs(drop)
+    a.step(100)
+    pa, va, sa = a.get_state(displacement=True)
+    fa = a.get_forces()
+    assert a.info()["engine"] == eng
+    a.close()
+    b = T.sim_from_scene(_without(sc, drop), _params(eng))
+    b.set_state(p50, v50, displacement=True)
+    b.set_step(50)
+    b.step(100)
+    pb, vb, sb = b.get_state(displacement=True)
+    fb = b.get_forces()
+    b.close()
+    assert sa == sb == 150
+    assert np.array_equal(pa, pb) and np.array_equal(va, vb) and np.array_equal(fa, fb)
+
+
+def test_added_springs_match_the_oracle():
+    """Braces between masses two spacings apart, added after 30 steps with
+    their rest length taken at the current positions."""
+    T = _T()
+    n = 9
+    sc = scenes.jittered_actuated_lattice(n=n, seed=6)
+    sim = T.sim_from_scene(sc, _params())
+    sim.step(30)
+    p, v, _ = sim.get_state(displacement=True)
+    ids = np.arange(n ** 3).reshape(n, n, n)  # [z, y, x]
+    new = np.stack([ids[:, :, :-2].ravel(), ids[:, :, 2:].ravel()], axis=1)[::3]
+    kn = np.full(new.shape[0], 7.0e3, np.float32)
+    first = sim.add_springs(new, kn, damping=np.full(new.shape[0], 1.0, np.float32))
+    assert first == sc["ends"].shape[0]
+    gpu = gpu_series(sim, 10)
+    sim.close()
+    # the oracle: the same springs, the new ones at rest at the step-30 positions
+    x30 = O._d(sc["pos"]) + O._d(p)
+    d = x30[new[:, 1]] - x30[new[:, 0]]
+    rest_new = np.sqrt((d * d).sum(1)).astype(np.float32).astype(np.float64)
+    both = dict(sc, ends=np.vstack([sc["ends"], new]), k=np.concatenate([sc["k"], kn]),
+                damping=np.concatenate([sc["damping"], np.full(new.shape[0], 1.0, np.float32)]),
+                amp=np.concatenate([sc["amp"], np.zeros(new.shape[0], np.float32)]),
+                phase=np.concatenate([sc["phase"], np.zeros(new.shape[0], np.float32)]))
+    base = O.System(sc).rest
+    sysm = O.System(both, rest=np.concatenate([base, rest_new]))
+    rdX, rV, rF = sysm.trajectory(_oparams(), 10, x=x30, v=O._d(v), step0=30)
+    rdX = rdX + O._d(p)[None]  # displacement from the reference positions
+    err = compare_series(gpu, (rdX, rV, rF), sysm.mass)
+    print("added springs", err)
+    assert max(err.values()) <= TOL
+
+
+@pytest.mark.parametrize("engine", ["tiled", "batched"])
+def test_added_body_matches_the_oracle(engine):
+    """A second cube added as a new body after 20 steps falls on its own."""
+    T = _T()
+    eng = T.ENGINE_TILED if engine == "tiled" else T.ENGINE_BATCHED
+    c1 = scenes.cube_drop(6)
+    c2 = scenes.lattice(4, origin=(2.0, 0.0, 0.3))
+    sim = T.sim_from_scene(dict(c1, body=np.zeros(c1["pos"].shape[0], np.int32)), _params(eng))
+    sim.step(20)
+    p, v, _ = sim.get_state(displacement=True)
+    m0 = sim.add_masses(c2["pos"], c2["mass"], body=np.ones(c2["pos"].shape[0], np.int32))
+    assert m0 == c1["pos"].shape[0]
+    sim.add_springs(c2["ends"] + m0, c2["k"], damping=c2["damping"], rest=O.System(c2).rest.astype(np.float32))
+    gpu = gpu_series(sim, 10)
+    assert sim.info()["engine"] == eng
+    sim.close()
+    both = scenes.concat([c1, c2])
+    # the added springs' rest lengths as the library received them (FP32)
+    rest2 = O.System(c2).rest.astype(np.float32).astype(np.float64)
+    sysm = O.System(both, rest=np.concatenate([O.System(c1).rest, rest2]))
+    x = np.vstack([O._d(c1["pos"]) + O._d(p), O._d(c2["pos"])])
+    vv = np.vstack([O._d(v), np.zeros((c2["pos"].shape[0], 3))])
+    rdX, rV, rF = sysm.trajectory(_oparams(), 10, x=x, v=vv, step0=20)
+    rdX = rdX + (x - sysm.x0)[None]
+    err = compare_series(gpu, (rdX, rV, rF), sysm.mass)
+    print("added body", engine, err)
+    assert max(err.values()) <= TOL
+
+
+def test_removed_masses_are_pinned_and_detached():
+    T = _T()
+    sc = scenes.jittered_actuated_lattice(n=10, seed=5)
+    gone = np.array([0, 55, 555, 999])
+    a = T.sim_from_scene(sc, _params())
+    a.step(40)
+    p40, v40, _ = a.get_state(displacement=True)
+    a.remove_masses(gone)
+    a.step(60)
+    pa, va, _ = a.get_state(displacement=True)
+    a.close()
+    assert np.array_equal(pa[gone], p40[gone]) and np.all(va[gone] == 0.0)
+    # the same as pinning them in a system built without their springs
+    touching = np.isin(sc["ends"], gone).any(axis=1)
+    b_sc = _without(sc, np.nonzero(touching)[0])
+    b_sc["mass"] = sc["mass"].copy()
+    b_sc["mass"][gone] = 0.0
+    v40b = v40.copy()
+    v40b[gone] = 0.0
+    b = T.sim_from_scene(b_sc, _params())
+    b.set_state(p40, v40b, displacement=True)
+    b.set_step(40)
+    b.step(60)
+    pb, vb, _ = b.get_state(displacement=True)
+    b.close()
+    assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+
+
+def test_edit_at_a_pause_breakpoint():
+    """Pause at step 40 with 100 steps requested, remove springs, resume: the
+    same bits as stepping to 40, removing, and stepping 60 more."""
+    T = _T()
+    sc = scenes.jittered_actuated_lattice(n=10, seed=7)
+    drop = np.arange(0, sc["ends"].shape[0], 17)
+    a = T.sim_from_scene(sc, _params())
+    bp = a.set_breakpoint(40, T.BP_PAUSE)
+    a.step(100)
+    a.wait(bp)
+    a.remove_springs(drop)
+    a.resume()
+    pa, va, sa = a.get_state(displacement=True)
+    a.close()
+    b = T.sim_from_scene(sc, _params())
+    b.step(40)
+    b.remove_springs(drop)
+    b.step(60)
+    pb, vb, sb = b.get_state(displacement=True)
+    b.close()
+    assert sa == sb == 100
+    assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+
+
+def test_edit_errors():
+    T = _T()
+    a = scenes.lattice(3, origin=(0.0, 0.0, 1.0))
+    b = scenes.lattice(3, origin=(1.0, 0.0, 1.0))
+    two = scenes.concat([a, b])
+    sim = T.sim_from_scene(two, _params())
+    sim.step(1)
+    with pytest.raises(T.TitanError) as ei:
+        sim.remove_springs([two["ends"].shape[0]])
+    assert ei.value.code == T.EINVAL
+    with pytest.raises(T.TitanError) as ei:  # rest lengths must be > 0
+        sim.add_springs([[3, 4]], [1.0], rest=[-1.0])
+    assert ei.value.code == T.EINVAL
+    with pytest.raises(T.TitanError) as ei:  # a new mass may not join an existing body of several
+        sim.add_masses([[5.0, 0.0, 1.0]], [0.1], body=[0])
+    assert ei.value.code == T.EINVAL
+    with pytest.raises(T.TitanError) as ei:  # springs may not join bodies
+        sim.add_springs([[0, 30]], [1.0])
+    assert ei.value.code == T.EINVAL
+    sim.close()
