@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TITAN_ABI_VERSION 2
+#define TITAN_ABI_VERSION 3
 
 /* Status codes. */
 #define TITAN_OK 0
@@ -133,6 +133,11 @@ typedef struct titan_info {
     float tune_batch_ms;     /* tuner's time per step of the batched engine */
     float tune_gather_ms;    /* tuner's time per step of the gather engine
                                 (measured only under TITAN_ENGINE_AUTO) */
+    int32_t slack;           /* spare slots per row of the current layouts */
+    int64_t layout_builds;   /* times the layouts were built (the first step,
+                                then each rebuild after a topology edit) */
+    int64_t springs_in_place; /* springs added after the first step that went
+                                 into spare slots without a rebuild */
 } titan_info;
 
 /* ABI version this library implements (TITAN_ABI_VERSION). */

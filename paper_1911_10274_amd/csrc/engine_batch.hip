@@ -142,6 +142,7 @@ int build_batch_engine(titan_sim *s, bool may_step)
     if (!be)
         return fail(TITAN_ENOMEM, "out of host memory");
     be->lay.n_groups = ng;
+    s->h_group_off = goff;
     be->lay.max_group = (int32_t)max_group;
     {
         int64_t *d = nullptr;
@@ -241,6 +242,11 @@ int enqueue_batch_steps(titan_sim *s, int64_t first_step, int64_t count)
         s->cur = 1 - s->cur;
     }
     return TITAN_OK;
+}
+
+uint16_t *batch_nbr_group(titan_sim *s)
+{
+    return s->batch ? const_cast<uint16_t *>(s->batch->lay.nbr_group) : nullptr;
 }
 
 void destroy_batch_engine(titan_sim *s)

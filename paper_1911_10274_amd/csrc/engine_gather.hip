@@ -9,6 +9,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <unordered_map>
 #include <vector>
 
 #include "titan_sim.h"
@@ -138,6 +140,44 @@ void plan_order(titan_sim *s)
     }
 }
 
+// Per-spring constants in the layouts' form (FP64 -> FP32).
+// Phasor actuation: C = amp cos(phase), S = amp sin(phase).
+static void phasor_consts(const titan_sim *s, int64_t q, float &C, float &S)
+{
+    C = (float)((double)s->h_amp[q] * std::cos((double)s->h_phase[q]));
+    S = (float)((double)s->h_amp[q] * std::sin((double)s->h_phase[q]));
+}
+
+// Explicit rest length L (else the reference length |R|): d0 = |R| - L, L0 = L.
+static void rest_consts(const titan_sim *s, int64_t q, float &d0, float &L0)
+{
+    const float *a = &s->h_pos[3 * s->h_ends[2 * q]], *b = &s->h_pos[3 * s->h_ends[2 * q + 1]];
+    const double dx = (double)b[0] - a[0], dy = (double)b[1] - a[1], dz = (double)b[2] - a[2];
+    const double R = std::sqrt(dx * dx + dy * dy + dz * dz);
+    const double L = s->h_rest[q] > 0.f ? (double)s->h_rest[q] : R;
+    d0 = (float)(R - L);
+    L0 = (float)L;
+}
+
+// Sec. IV-B, Eq. 5: the wave offset t_o of a spring is the smaller reference
+// x of its two ends minus the smallest reference x of its body.
+static std::vector<double> body_xmin(const titan_sim *s)
+{
+    int32_t nb = 0;
+    for (int32_t b : s->h_body)
+        nb = std::max(nb, b + 1);
+    std::vector<double> xmin(nb, INFINITY);
+    for (size_t i = 0; i < s->h_body.size(); ++i)
+        xmin[s->h_body[i]] = std::min(xmin[s->h_body[i]], (double)s->h_pos[3 * i]);
+    return xmin;
+}
+
+static double wave_offset(const titan_sim *s, const std::vector<double> &xmin, int64_t q)
+{
+    const int64_t a = s->h_ends[2 * q], b = s->h_ends[2 * q + 1];
+    return std::min((double)s->h_pos[3 * a], (double)s->h_pos[3 * b]) - xmin[s->h_body[a]];
+}
+
 static int build_gather(titan_sim *s, bool allow_tiled)
 {
     const int64_t n = s->n, ns = s->ns;
@@ -223,39 +263,23 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     if (act && !wave) {
         sC.resize(ns);
         sS.resize(ns);
-        for (int64_t q = 0; q < ns; ++q) {
-            sC[q] = (float)((double)s->h_amp[q] * std::cos((double)s->h_phase[q]));
-            sS[q] = (float)((double)s->h_amp[q] * std::sin((double)s->h_phase[q]));
-        }
+        for (int64_t q = 0; q < ns; ++q)
+            phasor_consts(s, q, sC[q], sS[q]);
     }
     if (wave) {
-        // Sec. IV-B, Eq. 5: offset t_o = smaller reference x of the two ends
-        // minus the smallest reference x of the body
-        int32_t nb = 0;
-        for (int32_t b : s->h_body)
-            nb = std::max(nb, b + 1);
-        std::vector<double> xmin(nb, INFINITY);
-        for (int64_t i = 0; i < n; ++i)
-            xmin[s->h_body[i]] = std::min(xmin[s->h_body[i]], (double)s->h_pos[3 * i]);
+        const std::vector<double> xmin = body_xmin(s);
         sC.resize(ns);
         sT.resize(ns);
         for (int64_t q = 0; q < ns; ++q) {
-            const int64_t a = s->h_ends[2 * q], b = s->h_ends[2 * q + 1];
             sC[q] = s->h_amp[q];
-            sT[q] = std::min((double)s->h_pos[3 * a], (double)s->h_pos[3 * b]) - xmin[s->h_body[a]];
+            sT[q] = wave_offset(s, xmin, q);
         }
     }
     if (rest) {
         sD0.resize(ns);
         sL0.resize(ns);
-        for (int64_t q = 0; q < ns; ++q) {
-            const float *a = &s->h_pos[3 * s->h_ends[2 * q]], *b = &s->h_pos[3 * s->h_ends[2 * q + 1]];
-            const double dx = (double)b[0] - a[0], dy = (double)b[1] - a[1], dz = (double)b[2] - a[2];
-            const double R = std::sqrt(dx * dx + dy * dy + dz * dz);
-            const double L = s->h_rest[q] > 0.f ? (double)s->h_rest[q] : R;
-            sD0[q] = (float)(R - L);
-            sL0[q] = (float)L;
-        }
+        for (int64_t q = 0; q < ns; ++q)
+            rest_consts(s, q, sD0[q], sL0[q]);
     }
 
     // Sliced ELL (slices of 64 masses; a tile is 4 slices).
@@ -389,6 +413,17 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     // keep the staging alive until the copies have run
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     s->h_slot_nbr.swap(nbr);  // for the batched engine's layout
+    // what insertion in place needs of the layout
+    s->h_deg.swap(deg);
+    s->h_slice_off.swap(off);
+    if (tiled) {
+        s->h_halo_off.swap(halo_off);
+        s->h_halo_idx.swap(halo_idx);
+    } else {
+        std::vector<int64_t>().swap(s->h_halo_off);
+        std::vector<int32_t>().swap(s->h_halo_idx);
+    }
+    ++s->layout_builds;
     return TITAN_OK;
 }
 
@@ -605,6 +640,174 @@ int compute_forces(titan_sim *s)
 
 void destroy_engines(titan_sim *s) { destroy_batch_engine(s); }
 
+// Springs added to a running system go into spare slots of the current
+// layouts (Sec. III-C: arrays made larger than needed give O(1) insertion).
+// A spring fits when both of its rows have a slot past their degree, the
+// other end is reachable from each row (tiled layout: in the row's tile or
+// its halo; batched layout: in the row's group), and its constants are
+// representable by the arrays the layout has (a uniform stiffness or damping
+// that it matches, actuation only where per-slot actuation exists, per-slot
+// rest lengths).  The inserted spring is summed after the row's earlier
+// springs; a later rebuild sorts it into place.
+int insert_springs(titan_sim *s, int64_t first, int64_t count)
+{
+    GatherGraph &g = s->gg;
+    const int64_t n = s->n;
+    if (count <= 0)
+        return TITAN_OK;
+    if ((int64_t)s->h_deg.size() != n || (int64_t)s->h_slice_off.size() != g.n_slices + 1 || !g.d0)
+        return 2;
+    const bool act = g.act_c != nullptr, wave = g.t_off != nullptr;
+    uint16_t *ngroup = batch_nbr_group(s);
+    const bool grouped = ngroup != nullptr;
+    if (grouped && s->h_group_off.size() < 2)
+        return 2;
+    auto group_of = [&](int64_t i) {
+        return (int64_t)(std::upper_bound(s->h_group_off.begin(), s->h_group_off.end(), i) -
+                         s->h_group_off.begin()) - 1;
+    };
+    // one new incidence: slot e of row r, whose other end is o
+    struct Put {
+        int64_t e, r, o, q;
+        uint16_t local, group;
+    };
+    std::vector<Put> puts;
+    std::unordered_map<int64_t, int32_t> extra;  // slots taken in this call, per row
+    for (int64_t q = first; q < first + count; ++q) {
+        if ((!g.k && s->h_k[q] != g.k_uniform) || (!g.c && s->h_damp[q] != g.c_uniform) ||
+            (!act && s->h_amp[q] != 0.f))
+            return 2;
+        const int64_t i = s->inv_perm_of(s->h_ends[2 * q]), j = s->inv_perm_of(s->h_ends[2 * q + 1]);
+        for (int side = 0; side < 2; ++side) {
+            const int64_t r = side ? j : i, o = side ? i : j;
+            const int64_t sl = r / kSlice;
+            const int64_t width = (s->h_slice_off[sl + 1] - s->h_slice_off[sl]) / kSlice;
+            const int64_t w = s->h_deg[r] + extra[r];
+            if (w >= width)
+                return 1;
+            Put p{s->h_slice_off[sl] + (r % kSlice) + w * kSlice, r, o, q, 0, 0};
+            if (s->tiled) {
+                const int64_t t = r / kTile, a = t * kTile;
+                if (o >= a && o < a + kTile) {
+                    p.local = (uint16_t)(o - a);
+                } else {
+                    const int32_t *hb = s->h_halo_idx.data() + s->h_halo_off[t];
+                    const int32_t *he = s->h_halo_idx.data() + s->h_halo_off[t + 1];
+                    const int32_t *f = std::lower_bound(hb, he, (int32_t)o);
+                    if (f == he || *f != (int32_t)o)
+                        return 2;
+                    p.local = (uint16_t)(kTile + (f - hb));
+                }
+            }
+            if (grouped) {
+                const int64_t gr = group_of(r);
+                if (gr != group_of(o))
+                    return 2;
+                p.group = (uint16_t)(o - s->h_group_off[gr]);
+            }
+            ++extra[r];
+            puts.push_back(p);
+        }
+    }
+
+    // All fit: write the slots, one scatter per array, in stream order.
+    const int64_t m = (int64_t)puts.size();
+    for (const Put &p : puts)
+        if (p.e < 0 || p.e >= s->n_slots || p.r < 0 || p.r >= n || p.o < 0 || p.o >= n)
+            return fail(TITAN_EINVAL, "internal: inserted slot out of range");
+    std::vector<int64_t> slot(m);
+    for (int64_t e = 0; e < m; ++e)
+        slot[e] = puts[e].e;
+    int64_t *dslot = nullptr;
+    void *dval = nullptr;
+    if (int rc = dev_alloc(s, sizeof(int64_t) * m, (void **)&dslot))
+        return rc;
+    if (int rc = dev_alloc(s, sizeof(double) * m, &dval)) {
+        dev_free(s, dslot);
+        return rc;
+    }
+    std::vector<uint8_t> val(sizeof(double) * m);
+    auto scatter = [&](const void *dst, int bytes, auto value_of) -> hipError_t {
+        using V = decltype(value_of(puts[0]));
+        static_assert(sizeof(V) == 2 || sizeof(V) == 4 || sizeof(V) == 8, "element size");
+        (void)bytes;
+        for (int64_t e = 0; e < m; ++e) {
+            const V v = value_of(puts[e]);
+            memcpy(val.data() + e * sizeof(V), &v, sizeof(V));
+        }
+        if (hipError_t err = hipMemcpyAsync(dval, val.data(), sizeof(V) * m, hipMemcpyHostToDevice, s->stream))
+            return err;
+        if (hipError_t err = launch_scatter_bits(const_cast<void *>(dst), sizeof(V), dslot, dval, m, s->stream))
+            return err;
+        return hipStreamSynchronize(s->stream);  // the staging is reused by the next array
+    };
+    std::vector<double> xmin;
+    if (wave)
+        xmin = body_xmin(s);
+    hipError_t err = hipMemcpyAsync(dslot, slot.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, s->stream);
+    if (!err && g.nbr)
+        err = scatter(g.nbr, 4, [](const Put &p) { return (int32_t)p.o; });
+    if (!err && g.nbr_local)
+        err = scatter(g.nbr_local, 2, [](const Put &p) { return p.local; });
+    if (!err && grouped)
+        err = scatter(ngroup, 2, [](const Put &p) { return p.group; });
+    if (!err && g.k)
+        err = scatter(g.k, 4, [&](const Put &p) { return s->h_k[p.q]; });
+    if (!err && g.c)
+        err = scatter(g.c, 4, [&](const Put &p) { return s->h_damp[p.q]; });
+    if (!err && act && wave) {
+        err = scatter(g.act_c, 4, [&](const Put &p) { return s->h_amp[p.q]; });
+        if (!err)
+            err = scatter(g.t_off, 8, [&](const Put &p) { return wave_offset(s, xmin, p.q); });
+    } else if (!err && act) {
+        err = scatter(g.act_c, 4, [&](const Put &p) {
+            float C, S;
+            phasor_consts(s, p.q, C, S);
+            return C;
+        });
+        if (!err)
+            err = scatter(g.act_s, 4, [&](const Put &p) {
+                float C, S;
+                phasor_consts(s, p.q, C, S);
+                return S;
+            });
+    }
+    if (!err)
+        err = scatter(g.d0, 4, [&](const Put &p) {
+            float d0, L0;
+            rest_consts(s, p.q, d0, L0);
+            return d0;
+        });
+    if (!err)
+        err = scatter(g.rest, 4, [&](const Put &p) {
+            float d0, L0;
+            rest_consts(s, p.q, d0, L0);
+            return L0;
+        });
+    if (!err) {
+        for (const Put &p : puts) {
+            ++s->h_deg[p.r];
+            if (p.o > p.r)
+                s->h_owner_slot[p.q] = p.e;
+            else
+                s->h_other_slot[p.q] = p.e;
+        }
+        // the device copy of the row degrees: indexed by row, not by slot
+        // (slot holds m >= the number of rows)
+        for (int64_t e = 0; e < m; ++e)
+            slot[e] = puts[e].r;
+        err = hipMemcpyAsync(dslot, slot.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, s->stream);
+        if (!err)
+            err = scatter(g.deg, 4, [&](const Put &p) { return s->h_deg[p.r]; });
+    }
+    dev_free(s, dslot);
+    dev_free(s, dval);
+    if (err != hipSuccess)
+        return hip_fail(s, err, "inserting springs");
+    s->springs_in_place += count;
+    return TITAN_OK;
+}
+
 int rebuild_engines(titan_sim *s)
 {
     destroy_batch_engine(s);
@@ -614,6 +817,7 @@ int rebuild_engines(titan_sim *s)
     s->trig = nullptr;
     s->n_slots = 0;
     s->h_slot_nbr.clear();
+    s->h_group_off.clear();
     if (int rc = build_engines(s))
         return rc;
     HIP_TRY(s, hipStreamSynchronize(s->stream));

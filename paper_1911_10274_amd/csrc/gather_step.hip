@@ -148,6 +148,14 @@ __global__ void scatter_kernel(float *dst, const int64_t *slot, const float *val
         dst[slot[q]] = val[q];
 }
 
+template <class T>
+__global__ void scatter_bits_kernel(T *dst, const int64_t *slot, const T *val, int64_t m)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < m)
+        dst[slot[q]] = val[q];
+}
+
 // disp[b] = sum_i w_i u_i over body b's internal masses [off[b], off[b+1]),
 // w_i = m_i / M_b: the body's centre-of-mass displacement (one thread per
 // body, masses in index order).
@@ -182,6 +190,26 @@ hipError_t launch_scatter(float *dst, const int64_t *slot, const float *val, int
     if (m <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, dst, slot, val, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_bits(void *dst, int bytes, const int64_t *slot, const void *val, int64_t m,
+                               hipStream_t stream)
+{
+    if (m <= 0)
+        return hipSuccess;
+    const dim3 grid((unsigned)((m + 255) / 256)), block(256);
+    if (bytes == 2)
+        hipLaunchKernelGGL(scatter_bits_kernel<uint16_t>, grid, block, 0, stream, (uint16_t *)dst, slot,
+                           (const uint16_t *)val, m);
+    else if (bytes == 4)
+        hipLaunchKernelGGL(scatter_bits_kernel<uint32_t>, grid, block, 0, stream, (uint32_t *)dst, slot,
+                           (const uint32_t *)val, m);
+    else if (bytes == 8)
+        hipLaunchKernelGGL(scatter_bits_kernel<uint64_t>, grid, block, 0, stream, (uint64_t *)dst, slot,
+                           (const uint64_t *)val, m);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

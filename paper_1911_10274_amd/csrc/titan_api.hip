@@ -348,11 +348,22 @@ extern "C" int titan_add_springs(titan_sim *s, int64_t n, const int64_t *ends, c
     if (!s->h_removed.empty())
         s->h_removed.resize(s->h_k.size(), 0);
     if (s->finalized && n > 0) {
+        const int64_t first = s->ns;
         s->ns = (int64_t)s->h_k.size();
         s->h_owner_slot.resize(s->ns, -1);
         s->h_other_slot.resize(s->ns, -1);
-        s->layout_dirty = true;
-        s->slack = std::max(s->slack, 2);
+        // into spare slots of the current layouts if they all fit (O(1) per
+        // spring), else the layouts are rebuilt before the next step, with
+        // more spare slots
+        int rc = s->layout_dirty ? 2 : insert_springs(s, first, n);
+        if (rc > 0) {
+            s->layout_dirty = true;
+            s->slack = rc == 1 ? std::min(std::max(2 * s->slack, 2), kMaxSlack) : std::max(s->slack, 2);
+            rc = TITAN_OK;
+        } else if (rc != TITAN_OK) {
+            s->layout_dirty = true;
+        }
+        return rc;
     }
     return TITAN_OK;
 }
@@ -1094,5 +1105,8 @@ extern "C" int titan_get_info(titan_sim *s, titan_info *info)
     info->batch_threads = batch_threads(s);
     info->tune_batch_ms = s->tune_batch_ms;
     info->tune_gather_ms = s->tune_gather_ms;
+    info->slack = s->slack;
+    info->layout_builds = s->layout_builds;
+    info->springs_in_place = s->springs_in_place;
     return TITAN_OK;
 }

@@ -89,6 +89,9 @@ struct StateIO {
 
 // dst[slot[q]] = val[q] for q < m; dst[q] = v for q < m.
 hipError_t launch_scatter(float *dst, const int64_t *slot, const float *val, int64_t m, hipStream_t stream);
+// The same for 16-, 32- and 64-bit elements (bit patterns).
+hipError_t launch_scatter_bits(void *dst, int bytes, const int64_t *slot, const void *val, int64_t m,
+                               hipStream_t stream);
 hipError_t launch_fill(float *dst, float v, int64_t m, hipStream_t stream);
 // disp[3b..3b+2] = sum over internal masses [off[b], off[b+1]) of w_i * u_i.xyz
 hipError_t launch_body_disp(const float4 *U, const float *w, const int64_t *off, int64_t nb, float *disp,

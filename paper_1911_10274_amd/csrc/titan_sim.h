@@ -12,6 +12,10 @@
 
 namespace titan {
 
+// Most spare slots per row that insertions after the first step grow the
+// layouts to (each slot of slack costs a row slot of traffic per step).
+constexpr int32_t kMaxSlack = 8;
+
 struct BP {
     uint64_t id = 0;
     int64_t step = 0;
@@ -77,7 +81,15 @@ struct titan_sim {
     // the next step when dirty; removed springs stay in the spring table
     bool layout_dirty = false;
     std::vector<uint8_t> h_removed;  // per spring (empty: none removed)
-    int32_t slack = 0;               // spare slots per row after an edit-triggered rebuild
+    int32_t slack = 0;               // spare slots per row (grown by edits, up to kMaxSlack)
+    // host copies of the current layout, for insertions in place
+    std::vector<int32_t> h_deg;        // incidences per mass (internal order)
+    std::vector<int64_t> h_slice_off;  // sliced-ELL offsets
+    std::vector<int64_t> h_halo_off;   // tiled layout: halo lists
+    std::vector<int32_t> h_halo_idx;
+    std::vector<int64_t> h_group_off;  // batched layout: group ranges (empty: none)
+    int64_t layout_builds = 0;     // times the layouts were built
+    int64_t springs_in_place = 0;  // springs inserted into spare slots
 
     // batched engine (null unless selected) and the tuner's measurements
     titan::BatchEngine *batch = nullptr;
@@ -122,6 +134,15 @@ int enqueue_steps(titan_sim *s, int64_t first_step, int64_t count);
 int compute_forces(titan_sim *s);
 StepConsts consts_for(const titan_sim *s, int64_t step, const float2 *trig);
 void destroy_engines(titan_sim *s);
+// Place springs [first, first + count) (already in the host tables) into spare
+// slots of the current layouts, O(1) per spring.  Returns 0 when all were
+// placed; 1 if some row has no spare slot left, 2 if some spring does not fit
+// the layout otherwise (in both cases nothing is written and the layouts must
+// be rebuilt); or an error code (< 0).
+int insert_springs(titan_sim *s, int64_t first, int64_t count);
+// Device array of the batched layout's group-relative neighbour indices
+// (null without a batched layout).
+uint16_t *batch_nbr_group(titan_sim *s);
 // Rebuild the engines' layouts for the current topology, keeping the state,
 // the internal order and every device buffer that is not an engine's.
 int rebuild_engines(titan_sim *s);

@@ -80,6 +80,9 @@ class _Info(ctypes.Structure):
         ("batch_threads", ctypes.c_int32),
         ("tune_batch_ms", ctypes.c_float),
         ("tune_gather_ms", ctypes.c_float),
+        ("slack", ctypes.c_int32),
+        ("layout_builds", ctypes.c_int64),
+        ("springs_in_place", ctypes.c_int64),
     ]
 
 

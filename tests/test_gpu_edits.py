@@ -206,3 +206,171 @@ def test_edit_errors():
         sim.add_springs([[0, 30]], [1.0])
     assert ei.value.code == T.EINVAL
     sim.close()
+
+
+def _matching(ends, count, skip=()):
+    """Up to `count` existing springs, no two sharing a mass (nor touching
+    `skip`): parallel springs on them fit one spare slot per row, and their
+    ends are in each other's tile or halo."""
+    used = set(int(m) for m in skip)
+    out = []
+    for a, b in ends:
+        if a in used or b in used:
+            continue
+        used.update((int(a), int(b)))
+        out.append((int(a), int(b)))
+        if len(out) == count:
+            break
+    return np.array(out, np.int64)
+
+
+def _rest_now(sc, p, ends):
+    x = O._d(sc["pos"]) + O._d(p)
+    d = x[ends[:, 1]] - x[ends[:, 0]]
+    return np.sqrt((d * d).sum(1)).astype(np.float32).astype(np.float64)
+
+
+def test_springs_inserted_in_place_match_the_oracle():
+    """A first insertion rebuilds the layouts with spare slots; a second one
+    goes into those slots without a rebuild (Sec. III-C), then 10 steps
+    against the oracle.  The in-place springs carry their own stiffness,
+    damping, phasor actuation and rest length."""
+    T = _T()
+    n = 9
+    sc = scenes.jittered_actuated_lattice(n=n, seed=6)
+    sim = T.sim_from_scene(sc, _params())
+    sim.step(30)
+    p30, _, _ = sim.get_state(displacement=True)
+    ids = np.arange(n ** 3).reshape(n, n, n)
+    A = np.stack([ids[:, :, :-2].ravel(), ids[:, :, 2:].ravel()], axis=1)[::5]
+    kA = np.full(A.shape[0], 7.0e3, np.float32)
+    cA = np.full(A.shape[0], 1.5, np.float32)  # damping no longer uniform: per-slot damping
+    sim.add_springs(A, kA, damping=cA)
+    sim.step(10)
+    i1 = sim.info()
+    assert i1["slack"] == 2 and i1["springs_in_place"] == 0
+    p40, v40, s40 = sim.get_state(displacement=True)
+    assert s40 == 40
+    B = _matching(sc["ends"][::3], 60)
+    rng = np.random.Generator(np.random.PCG64(3))
+    kB = rng.uniform(2e3, 9e3, B.shape[0]).astype(np.float32)
+    cB = rng.uniform(0.5, 2.0, B.shape[0]).astype(np.float32)
+    aB = rng.uniform(0.0, 0.1, B.shape[0]).astype(np.float32)
+    phB = rng.uniform(0.0, 2 * np.pi, B.shape[0]).astype(np.float32)
+    sim.add_springs(B, kB, damping=cB, amp=aB, phase=phB)
+    i2 = sim.info()
+    assert i2["springs_in_place"] == B.shape[0] and i2["layout_builds"] == i1["layout_builds"]
+    gpu = gpu_series(sim, 10)
+    assert sim.info()["layout_builds"] == i1["layout_builds"]
+    sim.close()
+    z = lambda m: np.zeros(m, np.float32)  # noqa: E731
+    both = dict(sc, ends=np.vstack([sc["ends"], A, B]), k=np.concatenate([sc["k"], kA, kB]),
+                damping=np.concatenate([sc["damping"], cA, cB]),
+                amp=np.concatenate([sc["amp"], z(A.shape[0]), aB]),
+                phase=np.concatenate([sc["phase"], z(A.shape[0]), phB]))
+    rest = np.concatenate([O.System(sc).rest, _rest_now(sc, p30, A), _rest_now(sc, p40, B)])
+    sysm = O.System(both, rest=rest)
+    x40 = O._d(sc["pos"]) + O._d(p40)
+    rdX, rV, rF = sysm.trajectory(_oparams(), 10, x=x40, v=O._d(v40), step0=40)
+    rdX = rdX + O._d(p40)[None]
+    err = compare_series(gpu, (rdX, rV, rF), sysm.mass)
+    print("springs in place", err)
+    assert max(err.values()) <= TOL
+
+
+@pytest.mark.parametrize("law", ["phasor", "wave"])
+def test_engines_agree_bitwise_after_insertion_in_place(law):
+    T = _T()
+    sc = scenes.worm_batch(2, nx=12) if law == "wave" else scenes.jittered_actuated_lattice(n=10, seed=8)
+    outs = []
+    for eng in (T.ENGINE_GATHER, T.ENGINE_TILED, T.ENGINE_BATCHED):
+        if law == "wave":
+            prm = T.Params(dt=1e-4, gravity=(0.0, 0.0, -9.81), ground=True, ground_k=1e5, friction_mu=0.5,
+                           omega=20.0, engine=eng, actuation=T.ACT_WAVE, wave_period=1.0)
+        else:
+            prm = _params(eng)
+        sim = T.sim_from_scene(sc, prm)
+        sim.step(20)
+        A = _matching(sc["ends"][1::4], 40)
+        sim.add_springs(A, np.full(A.shape[0], 3e3, np.float32), damping=np.full(A.shape[0], 0.7, np.float32),
+                        amp=np.full(A.shape[0], 0.05, np.float32), phase=np.full(A.shape[0], 0.3, np.float32))
+        sim.step(5)
+        builds = sim.info()["layout_builds"]
+        B = _matching(sc["ends"][2::4], 40)
+        sim.add_springs(B, np.full(B.shape[0], 5e3, np.float32), damping=np.full(B.shape[0], 0.9, np.float32),
+                        amp=np.full(B.shape[0], 0.08, np.float32), phase=np.full(B.shape[0], 1.1, np.float32))
+        info = sim.info()
+        assert info["springs_in_place"] == B.shape[0] and info["layout_builds"] == builds
+        sim.step(300)
+        assert sim.info()["engine"] == eng
+        outs.append(sim.get_state(displacement=True)[:2] + (sim.get_forces(),))
+        sim.close()
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert np.array_equal(a, b)
+
+
+def test_removing_springs_inserted_in_place_restores_the_bits():
+    T = _T()
+    sc = scenes.jittered_actuated_lattice(n=10, seed=9)
+    A = _matching(sc["ends"][1::4], 50)
+    B = _matching(sc["ends"][2::4], 50)
+    runs = []
+    for with_b in (True, False):
+        sim = T.sim_from_scene(sc, _params())
+        sim.step(20)
+        sim.add_springs(A, np.full(A.shape[0], 3e3, np.float32))
+        sim.step(5)
+        if with_b:
+            first = sim.add_springs(B, np.full(B.shape[0], 5e3, np.float32), damping=np.ones(B.shape[0], np.float32))
+            assert sim.info()["springs_in_place"] == B.shape[0]
+            sim.step(3)
+            sim.remove_springs(np.arange(first, first + B.shape[0]))
+            sim.step(97)
+        else:
+            sim.step(100)
+        runs.append(sim.get_state(displacement=True))
+        sim.close()
+    # B acted for 3 steps: compare a run that removes B at once instead
+    sim = T.sim_from_scene(sc, _params())
+    sim.step(20)
+    sim.add_springs(A, np.full(A.shape[0], 3e3, np.float32))
+    sim.step(5)
+    first = sim.add_springs(B, np.full(B.shape[0], 5e3, np.float32), damping=np.ones(B.shape[0], np.float32))
+    sim.remove_springs(np.arange(first, first + B.shape[0]))
+    sim.step(100)
+    pc, vc, sc_ = sim.get_state(displacement=True)
+    sim.close()
+    pn, vn, sn = runs[1]
+    assert sc_ == sn == 125
+    assert np.array_equal(pc, pn) and np.array_equal(vc, vn)
+    assert not np.array_equal(runs[0][0], pn)  # B's three steps did move the system
+
+
+def test_exhausted_spare_slots_rebuild_with_more():
+    T = _T()
+    sc = scenes.jittered_actuated_lattice(n=8, seed=2)
+    sim = T.sim_from_scene(sc, _params())
+    sim.step(5)
+    assert sim.info()["layout_builds"] == 1
+    sim.add_springs([[0, 1]], [1e3])  # no spare slots yet: rebuilt before the next step
+    sim.step(1)
+    i = sim.info()
+    assert i["layout_builds"] == 2 and i["slack"] == 2
+    # three springs at a mass of the largest degree: its row has exactly the
+    # two spare slots
+    ends = np.vstack([sc["ends"], [[0, 1]]])
+    top = int(np.argmax(np.bincount(ends.ravel(), minlength=sc["pos"].shape[0])))
+    row = sc["ends"][(sc["ends"] == top).any(axis=1)][:3]
+    sim.add_springs(row, [1e3] * 3)
+    assert sim.info()["springs_in_place"] == 0
+    sim.step(1)
+    i = sim.info()
+    assert i["layout_builds"] == 3 and i["slack"] == 4
+    sim.add_springs(row[:2], [1e3] * 2)  # now they fit
+    i = sim.info()
+    assert i["springs_in_place"] == 2 and i["layout_builds"] == 3
+    sim.step(20)
+    p, v, _ = sim.get_state()
+    assert np.isfinite(p).all() and np.isfinite(v).all()
+    sim.close()
