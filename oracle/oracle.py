@@ -58,12 +58,13 @@ def _load():
     if _lib is None:
         lib = ctypes.CDLL(build())
         lib.orc_rest_lengths.argtypes = [ctypes.c_int64, _lp, _dp, _dp]
+        _u8p = ctypes.POINTER(ctypes.c_uint8)
         lib.orc_spring_forces.argtypes = [ctypes.c_int64, ctypes.c_int64, _lp, _dp, _dp, _dp, _dp, _dp,
-                                          ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
-                                          _dp, _dp, _dp]
+                                          ctypes.c_double, ctypes.c_int32, ctypes.c_double, _dp, _u8p,
+                                          ctypes.c_double, _dp, _dp, _dp]
         lib.orc_integrate.argtypes = [ctypes.c_int64, _dp, ctypes.POINTER(_Params), _dp, _dp, _dp]
         lib.orc_run.argtypes = [ctypes.c_int64, _dp, ctypes.c_int64, _lp, _dp, _dp, _dp, _dp, _dp,
-                                ctypes.POINTER(_Params), ctypes.c_int64, ctypes.c_int64, _dp, _dp, _dp]
+                                ctypes.POINTER(_Params), _dp, _u8p, ctypes.c_int64, ctypes.c_int64, _dp, _dp, _dp]
         lib.orc_run.restype = ctypes.c_int
         _i32p = ctypes.POINTER(ctypes.c_int32)
         _u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -131,7 +132,13 @@ def wave_offsets(pos, ends, body=None) -> np.ndarray:
 
 class System:
     """A scene promoted to FP64.  ``rest`` defaults to the initial lengths,
-    computed in FP64 from the (FP32) initial positions."""
+    computed in FP64 from the (FP32) initial positions.
+
+    A scene with a ``yield`` array (per spring; inf = never breaks) has
+    breakable springs (Sec. III-B): ``broken`` holds one flag per spring,
+    starts all clear and is updated by ``run``, ``trajectory`` and
+    ``spring_forces`` unless they are given a flag array of their own (then
+    that array is updated in place)."""
 
     def __init__(self, scene: dict, rest=None):
         self.x0 = _d(scene["pos"]).reshape(-1, 3).copy()
@@ -151,17 +158,29 @@ class System:
             rest = np.empty(self.ns, np.float64)
             _load().orc_rest_lengths(self.ns, _ptr(self.ends, _lp), _ptr(self.x0), _ptr(rest))
         self.rest = _d(rest)
+        self.yield_ = _d(scene.get("yield"))
+        self.broken = np.zeros(self.ns, np.uint8) if self.yield_ is not None else None
 
-    def spring_forces(self, x, v, t, omega, wave=False, period=1.0):
+    def _flags(self, broken):
+        if self.yield_ is None:
+            return None
+        b = self.broken if broken is None else broken
+        if b.dtype != np.uint8 or b.shape != (self.ns,) or not b.flags.c_contiguous:
+            raise ValueError("broken must be a contiguous uint8 array with one flag per spring")
+        return b
+
+    def spring_forces(self, x, v, t, omega, wave=False, period=1.0, broken=None):
         x = _d(x).reshape(-1, 3)
         v = _d(v).reshape(-1, 3)
         f = np.empty((self.n, 3), np.float64)
+        b = self._flags(broken)
         _load().orc_spring_forces(self.n, self.ns, _ptr(self.ends, _lp), _ptr(self.k), _ptr(self.c),
                                   _ptr(self.rest), _ptr(self.amp), _ptr(self.phase), omega, 1 if wave else 0,
-                                  period, t, _ptr(x), _ptr(v), _ptr(f))
+                                  period, _ptr(self.yield_), _ptr(b, ctypes.POINTER(ctypes.c_uint8)), t, _ptr(x),
+                                  _ptr(v), _ptr(f))
         return f
 
-    def run(self, params: Params, x, v, step0: int, nsteps: int, want_forces: bool = False):
+    def run(self, params: Params, x, v, step0: int, nsteps: int, want_forces: bool = False, broken=None):
         """Advance copies of (x, v) by ``nsteps`` steps from step index
         ``step0``.  Returns (x, v, f) with f the spring forces of the last
         step's starting state (or None)."""
@@ -169,14 +188,16 @@ class System:
         v = _d(v).reshape(-1, 3).copy()
         f = np.empty((self.n, 3), np.float64) if want_forces else None
         p = params._c()
+        b = self._flags(broken)
         rc = _load().orc_run(self.n, _ptr(self.mass), self.ns, _ptr(self.ends, _lp), _ptr(self.k),
                              _ptr(self.c), _ptr(self.rest), _ptr(self.amp), _ptr(self.phase),
-                             ctypes.byref(p), step0, nsteps, _ptr(x), _ptr(v), _ptr(f))
+                             ctypes.byref(p), _ptr(self.yield_), _ptr(b, ctypes.POINTER(ctypes.c_uint8)), step0,
+                             nsteps, _ptr(x), _ptr(v), _ptr(f))
         if rc != 0:
             raise MemoryError("oracle run failed")
         return x, v, f
 
-    def trajectory(self, params: Params, nsteps: int, x=None, v=None, step0: int = 0):
+    def trajectory(self, params: Params, nsteps: int, x=None, v=None, step0: int = 0, broken=None):
         """Per-step series for n = 1..nsteps: displacement X(n) - X(0),
         velocity V(n) and spring force F of step n's starting state (F(n-1)).
         Returns three arrays of shape (nsteps, n, 3)."""
@@ -187,7 +208,7 @@ class System:
         V = np.empty((nsteps, self.n, 3))
         F = np.empty((nsteps, self.n, 3))
         for s in range(nsteps):
-            x, v, f = self.run(params, x, v, step0 + s, 1, want_forces=True)
+            x, v, f = self.run(params, x, v, step0 + s, 1, want_forces=True, broken=broken)
             dX[s] = x - xs0
             V[s] = v
             F[s] = f
@@ -202,6 +223,8 @@ class System:
     def rollout_loss(self, params: Params, nsteps: int, body=None):
         """Per-body J_b = -(CoM_x after nsteps - CoM_x at start), and a hash of
         every contact / friction-stick decision of the run."""
+        if self.yield_ is not None:
+            raise ValueError("the rollout covers unbreakable springs only")
         b, nb = self._body(body)
         loss = np.empty(nb, np.float64)
         sig = ctypes.c_uint64()
@@ -219,6 +242,8 @@ class System:
         gk, gC, gS and the decision hash."""
         if params.wave:
             raise ValueError("the rollout adjoint covers phasor actuation only")
+        if self.yield_ is not None:
+            raise ValueError("the rollout adjoint covers unbreakable springs only")
         b, nb = self._body(body)
         w = np.ones(nb) if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
         loss = np.empty(nb, np.float64)

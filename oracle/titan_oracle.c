@@ -26,6 +26,13 @@
  *     taken non-negative (tau in [0, period)); the per-spring offset t_o is
  *     passed in the phase array.  Eq. 5 defines t_o from the reference
  *     positions: the smaller x of the two ends minus the body's smallest x.
+ *   - Sec. III-B (material properties): a spring may carry a yield value that
+ *     is compared against in the force calculation to find broken springs.
+ *     Reading taken here: the value compared is the magnitude of the spring's
+ *     elastic force |k (l - L(t))| (the damper's force is not a material
+ *     load); a spring whose elastic force exceeds its yield value breaks in
+ *     that force evaluation, exerts no force in it, and stays broken.
+ *     Springs with coincident ends (no direction, no force) are not tested.
  *
  * Accumulation is a serial scatter loop over springs in index order
  * (Sec. III-B's "apply to each corresponding mass"), all in double precision.
@@ -71,11 +78,13 @@ void orc_rest_lengths(int64_t ns, const int64_t *ends, const double *x, double *
 
 /* Spring forces of the state (x, v) at time t, summed per mass into f (n*3,
  * overwritten).  amp/phase may be NULL (no actuation); c may be NULL (no
- * damping). */
+ * damping).  yield may be NULL (no spring breaks); otherwise broken (ns
+ * flags, in and out) marks the broken springs and gains those that break in
+ * this evaluation. */
 void orc_spring_forces(int64_t n, int64_t ns, const int64_t *ends,
                        const double *k, const double *c, const double *rest,
                        const double *amp, const double *phase, double omega,
-                       int32_t wave, double period,
+                       int32_t wave, double period, const double *yield, uint8_t *broken,
                        double t, const double *x, const double *v, double *f)
 {
     memset(f, 0, sizeof(double) * 3 * (size_t)n);
@@ -94,6 +103,14 @@ void orc_spring_forces(int64_t n, int64_t ns, const int64_t *ends,
         if (amp)
             L = rest[s] * (1.0 + act_factor(amp[s], phase[s], omega, t, wave, period));
         double mag = k[s] * (len - L);
+        if (yield) {
+            if (broken[s])
+                continue;
+            if (!(fabs(mag) <= yield[s])) {
+                broken[s] = 1; /* breaks now: no force from here on */
+                continue;
+            }
+        }
         if (c)
             mag += c[s] * (dv[0] * u[0] + dv[1] * u[1] + dv[2] * u[2]);
         for (int q = 0; q < 3; ++q) {
@@ -150,6 +167,7 @@ void orc_integrate(int64_t n, const double *mass, const orc_params *p,
 int orc_run(int64_t n, const double *mass, int64_t ns, const int64_t *ends,
             const double *k, const double *c, const double *rest,
             const double *amp, const double *phase, const orc_params *p,
+            const double *yield, uint8_t *broken,
             int64_t step0, int64_t nsteps, double *x, double *v, double *f_last)
 {
     double *f = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
@@ -157,7 +175,8 @@ int orc_run(int64_t n, const double *mass, int64_t ns, const int64_t *ends,
         return -2;
     for (int64_t s = 0; s < nsteps; ++s) {
         double t = (double)(step0 + s) * p->dt;
-        orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, p->wave, p->period, t, x, v, f);
+        orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, p->wave, p->period, yield, broken, t, x,
+                          v, f);
         if (f_last && s == nsteps - 1)
             memcpy(f_last, f, sizeof(double) * 3 * (size_t)n);
         orc_integrate(n, mass, p, f, x, v);
@@ -199,8 +218,8 @@ static void step_sig(int64_t n, const double *mass, int64_t ns, const int64_t *e
                      const orc_params *p, int64_t step, double *f, double *x, double *v, uint64_t *sig)
 {
     const double dt = p->dt;
-    orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, p->wave, p->period, (double)step * dt, x, v,
-                      f);
+    orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, p->wave, p->period, NULL, NULL,
+                      (double)step * dt, x, v, f);
     for (int64_t i = 0; i < n; ++i) {
         double m = mass[i];
         if (m == 0.0)
@@ -342,7 +361,8 @@ int orc_rollout_grad(int64_t n, const double *mass, int64_t ns, const int64_t *e
     for (int64_t st = nsteps - 1; st >= 0; --st) {
         const double *x = X + S * st, *v = V + S * st;
         const double t = (double)st * dt;
-        orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, p->wave, p->period, t, x, v, f);
+        orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, p->wave, p->period, NULL, NULL, t, x, v,
+                          f);
         /* masses: position update, friction, velocity update */
         for (int64_t i = 0; i < n; ++i) {
             double m = mass[i];
