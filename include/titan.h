@@ -179,8 +179,16 @@ int titan_add_masses(titan_sim *sim, int64_t n, const float *pos_n3, const float
  * gets the first new spring's index.  After the first step (a topology edit,
  * Sec. III-C, applied from the next enqueued step on): a NULL rest length
  * means the distance between the ends after the steps already enqueued (the
- * call waits for them), which must be > 0; the device layout is rebuilt
- * before the next step, with spare slots per row for later additions. */
+ * call waits for them), which must be > 0.  The springs go into spare
+ * slots of the current device layout, O(1) each, when all of them fit: both
+ * rows have a free slot, the layout reaches the other end from each row, and
+ * the spring's constants are representable there (a uniform stiffness or
+ * damping it matches, actuation only where per-slot actuation exists,
+ * per-slot rest lengths).  Otherwise the layout is rebuilt before the next
+ * step, with more spare slots per row (2, doubled when a row ran out, at
+ * most 8).  A spring inserted in place is summed after its rows' earlier
+ * springs until a rebuild sorts it in.  A sim with breakable springs gives
+ * the new springs an infinite yield value (titan_set_yield changes it). */
 int titan_add_springs(titan_sim *sim, int64_t n, const int64_t *ends_n2, const float *k_n,
                       const float *damping_n, const float *rest_n, const float *amp_n,
                       const float *phase_n, int64_t *first_out);
@@ -193,6 +201,26 @@ int titan_add_springs(titan_sim *sim, int64_t n, const int64_t *ends_n2, const f
  * ends add an exact zero where its force was and every other result is
  * bitwise unchanged.  Layouts rebuilt later leave it out. */
 int titan_remove_springs(titan_sim *sim, int64_t n, const int64_t *springs_n);
+
+/* Yield values of springs [first, first + count) (Sec. III-B: material yield
+ * values compared against in the force calculation to find broken springs).
+ * yield_count: > 0, or +inf for a spring that never breaks; springs never
+ * given one have +inf.  A spring whose elastic force |k (l - L(t))| (damping
+ * excluded) exceeds its yield value in a step's force evaluation breaks: it
+ * exerts no force in that step and after, on every engine (both of its ends
+ * take the same decision).  Breaks are permanent: a broken spring keeps its
+ * state through later yield changes and is left out of rebuilt layouts, and
+ * restoring positions (titan_set_state) does not restore it.  A system with
+ * breakable springs keeps damping and rest lengths per incidence slot (more
+ * traffic per step).  After the first step the new values apply from the
+ * next enqueued step on (the call waits for the steps already enqueued).
+ * The rollout adjoint refuses breakable springs (TITAN_ESTATE). */
+int titan_set_yield(titan_sim *sim, int64_t first, int64_t count, const float *yield_count);
+
+/* Broken flags (1 broken, 0 intact) of springs [first, first + count) after
+ * the steps enqueued so far (waits for them).  Springs of a sim without
+ * yield values are never broken. */
+int titan_get_broken(titan_sim *sim, int64_t first, int64_t count, uint8_t *broken_count);
 
 /* Remove n masses: every spring touching them is removed (as above) and the
  * masses stay where they are, pinned (mass 0) and at rest.  Indices are kept.

@@ -11,7 +11,7 @@ namespace titan {
 
 namespace {
 
-template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, int T, int MAXM>
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool YIELD, int T, int MAXM>
 __global__ __launch_bounds__(T) void batch_step_kernel(GatherGraph g, BatchLayout b, StateIO io, StepConsts sc,
                                                        int nsteps)
 {
@@ -42,7 +42,9 @@ __global__ __launch_bounds__(T) void batch_step_kernel(GatherGraph g, BatchLayou
                 const float4 xi = sX[q], ui = sU[q], vi = sV[q];
                 const int64_t base = g.slice_off[i >> 6] + (i & 63);
                 float fx = 0.f, fy = 0.f, fz = 0.f;
-                sum_forces<ACT, DAMP, DAMPV, REST, false, WAVE>(
+                // a slot's break is recorded and read back by this same thread
+                // (a mass's row belongs to one thread for the whole launch)
+                sum_forces<ACT, DAMP, DAMPV, REST, false, WAVE, YIELD ? 2 : 0>(
                     g, base, slice_width(g, i), xi, ui, vi, ck, sc, [&](int64_t e) { return (int)b.nbr_group[e]; },
                     [&](int r, float4 &xj, float4 &uj, float4 &vj) {
                         uj = sU[r];
@@ -73,11 +75,11 @@ __global__ __launch_bounds__(T) void batch_step_kernel(GatherGraph g, BatchLayou
     }
 }
 
-template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, int T, int MAXM>
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool YIELD, int T, int MAXM>
 hipError_t launch_tm(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc,
                      int nsteps, hipStream_t st)
 {
-    auto kern = batch_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, T, MAXM>;
+    auto kern = batch_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, YIELD, T, MAXM>;
     const size_t lds = (size_t)b.max_group * 3 * sizeof(float4);
     if (lds > 65536) {
         const hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -89,30 +91,30 @@ hipError_t launch_tm(const GatherGraph &g, const BatchLayout &b, const StateIO &
     return hipGetLastError();
 }
 
-template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, int T>
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool YIELD, int T>
 hipError_t launch_t(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc, int nsteps,
                     hipStream_t st)
 {
     const int per = (b.max_group + T - 1) / T;
     if (per <= 1)
-        return launch_tm<ACT, WAVE, DAMP, DAMPV, REST, T, 1>(g, b, io, sc, nsteps, st);
+        return launch_tm<ACT, WAVE, DAMP, DAMPV, REST, YIELD, T, 1>(g, b, io, sc, nsteps, st);
     if (per <= 2)
-        return launch_tm<ACT, WAVE, DAMP, DAMPV, REST, T, 2>(g, b, io, sc, nsteps, st);
+        return launch_tm<ACT, WAVE, DAMP, DAMPV, REST, YIELD, T, 2>(g, b, io, sc, nsteps, st);
     if (per <= 4)
-        return launch_tm<ACT, WAVE, DAMP, DAMPV, REST, T, 4>(g, b, io, sc, nsteps, st);
+        return launch_tm<ACT, WAVE, DAMP, DAMPV, REST, YIELD, T, 4>(g, b, io, sc, nsteps, st);
     if (per <= 8)
-        return launch_tm<ACT, WAVE, DAMP, DAMPV, REST, T, 8>(g, b, io, sc, nsteps, st);
+        return launch_tm<ACT, WAVE, DAMP, DAMPV, REST, YIELD, T, 8>(g, b, io, sc, nsteps, st);
     return hipErrorInvalidValue;
 }
 
-template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST>
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool YIELD = false>
 hipError_t launch4(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc, int nsteps,
                    int threads, hipStream_t st)
 {
     switch (threads) {
-    case 256: return launch_t<ACT, WAVE, DAMP, DAMPV, REST, 256>(g, b, io, sc, nsteps, st);
-    case 512: return launch_t<ACT, WAVE, DAMP, DAMPV, REST, 512>(g, b, io, sc, nsteps, st);
-    case 1024: return launch_t<ACT, WAVE, DAMP, DAMPV, REST, 1024>(g, b, io, sc, nsteps, st);
+    case 256: return launch_t<ACT, WAVE, DAMP, DAMPV, REST, YIELD, 256>(g, b, io, sc, nsteps, st);
+    case 512: return launch_t<ACT, WAVE, DAMP, DAMPV, REST, YIELD, 512>(g, b, io, sc, nsteps, st);
+    case 1024: return launch_t<ACT, WAVE, DAMP, DAMPV, REST, YIELD, 1024>(g, b, io, sc, nsteps, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -127,7 +129,12 @@ hipError_t launch_batch(const GatherGraph &g, const BatchLayout &b, const StateI
     const bool act = g.act_c != nullptr, wave = act && g.t_off != nullptr, dampv = g.c != nullptr,
                rest = g.d0 != nullptr;
     const bool damp = dampv || g.c_uniform != 0.f;
-    const int key = (act ? 8 : 0) | (damp ? 4 : 0) | (dampv ? 2 : 0) | (rest ? 1 : 0) | (wave ? 16 : 0);
+    // breakable springs come with per-slot damping and rest lengths
+    const bool yield = g.yield != nullptr;
+    if (yield && !(dampv && rest))
+        return hipErrorInvalidValue;
+    const int key = (act ? 8 : 0) | (damp ? 4 : 0) | (dampv ? 2 : 0) | (rest ? 1 : 0) | (wave ? 16 : 0) |
+                    (yield ? 32 : 0);
     switch (key) {
     case 0: return launch4<false, false, false, false, false>(g, b, io, sc, nsteps, threads, stream);
     case 1: return launch4<false, false, false, false, true>(g, b, io, sc, nsteps, threads, stream);
@@ -147,6 +154,9 @@ hipError_t launch_batch(const GatherGraph &g, const BatchLayout &b, const StateI
     case 29: return launch4<true, true, true, false, true>(g, b, io, sc, nsteps, threads, stream);
     case 30: return launch4<true, true, true, true, false>(g, b, io, sc, nsteps, threads, stream);
     case 31: return launch4<true, true, true, true, true>(g, b, io, sc, nsteps, threads, stream);
+    case 39: return launch4<false, false, true, true, true, true>(g, b, io, sc, nsteps, threads, stream);
+    case 47: return launch4<true, false, true, true, true, true>(g, b, io, sc, nsteps, threads, stream);
+    case 63: return launch4<true, true, true, true, true, true>(g, b, io, sc, nsteps, threads, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -170,7 +170,30 @@ int build_batch_engine(titan_sim *s, bool may_step)
 
     // Autotune: workgroup size of the batched kernel, and (AUTO) batched vs
     // the per-step gather engine, by timing kTuneSteps steps of each into
-    // scratch buffers (the simulation state is not touched).
+    // scratch buffers (the simulation state is not touched; breaks of
+    // breakable springs are recorded in a copy of their yield values).
+    struct YieldCopy {
+        titan_sim *s;
+        float *keep = nullptr, *tmp = nullptr;
+        ~YieldCopy()
+        {
+            if (tmp) {
+                (void)hipStreamSynchronize(s->stream);
+                s->gg.yield = keep;
+                dev_free(s, tmp);
+            }
+        }
+    } ycopy{s};
+    if (s->gg.yield && s->n_slots > 0) {
+        if (int rc = dev_alloc(s, sizeof(float) * s->n_slots, (void **)&ycopy.tmp)) {
+            delete be;
+            return rc;
+        }
+        ycopy.keep = s->gg.yield;
+        HIP_TRY(s, hipMemcpyAsync(ycopy.tmp, ycopy.keep, sizeof(float) * s->n_slots, hipMemcpyDeviceToDevice,
+                                  s->stream));
+        s->gg.yield = ycopy.tmp;
+    }
     float4 *su = nullptr, *sv = nullptr;
     if (int rc = dev_alloc(s, sizeof(float4) * n, (void **)&su)) {
         delete be;

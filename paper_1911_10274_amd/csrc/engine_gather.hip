@@ -245,8 +245,11 @@ static int build_gather(titan_sim *s, bool allow_tiled)
 
     // Per-spring constants (FP64 -> FP32).
     // (over the springs present; q0: the first of them)
+    // Breakable springs keep damping and rest lengths per slot (one kernel
+    // variant per actuation law).
+    const bool yield = !s->h_yield.empty();
     int64_t q0 = -1;
-    bool act = false, rest = false, damp_uniform = true, k_uniform = true;
+    bool act = false, rest = yield, damp_uniform = !yield, k_uniform = true;
     for (int64_t q = 0; q < ns; ++q) {
         if (!live(q))
             continue;
@@ -297,8 +300,10 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     std::vector<uint16_t> nbr_local;
     if (tiled)
         nbr_local.assign(slots, 0);
-    std::vector<float> kk, cc, ac, as, d0, L0;
+    std::vector<float> kk, cc, ac, as, d0, L0, yy;
     std::vector<double> to;
+    if (yield)
+        yy.assign(slots, INFINITY);  // padding never breaks
     if (!k_uniform)
         kk.assign(slots, 0.f);
     if (!damp_uniform)
@@ -358,6 +363,8 @@ static int build_gather(titan_sim *s, bool allow_tiled)
                 d0[e] = sD0[x.spring];
                 L0[e] = sL0[x.spring];
             }
+            if (yield)
+                yy[e] = s->h_yield[x.spring];
         }
     }
 
@@ -406,6 +413,12 @@ static int build_gather(titan_sim *s, bool allow_tiled)
             return rc;
         if (int rc = put(s, L0, &g.rest))
             return rc;
+    }
+    if (yield) {
+        const float *p = nullptr;
+        if (int rc = put(s, yy, &p))
+            return rc;
+        g.yield = const_cast<float *>(p);  // the step records breaks here
     }
     g.X0 = s->X0;
     s->tiled = tiled;
@@ -784,6 +797,8 @@ int insert_springs(titan_sim *s, int64_t first, int64_t count)
             rest_consts(s, p.q, d0, L0);
             return L0;
         });
+    if (!err && g.yield)
+        err = scatter(g.yield, 4, [&](const Put &p) { return s->h_yield[p.q]; });
     if (!err) {
         for (const Put &p : puts) {
             ++s->h_deg[p.r];
@@ -808,8 +823,72 @@ int insert_springs(titan_sim *s, int64_t first, int64_t count)
     return TITAN_OK;
 }
 
+// Breaks recorded by the steps so far (in stream order) are copied into the
+// host tables: a broken spring is marked broken and removed, so that a
+// rebuilt layout leaves it out.
+int sync_broken(titan_sim *s)
+{
+    if (!s->gg.yield || s->n_slots == 0)
+        return TITAN_OK;
+    std::vector<float> y(s->n_slots);
+    HIP_TRY(s, hipMemcpyAsync(y.data(), s->gg.yield, sizeof(float) * s->n_slots, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    const int64_t ns = (int64_t)s->h_k.size();
+    if (s->h_removed.empty())
+        s->h_removed.assign(ns, 0);
+    if (s->h_broken.empty())
+        s->h_broken.assign(ns, 0);
+    for (int64_t q = 0; q < ns && q < (int64_t)s->h_owner_slot.size(); ++q) {
+        const int64_t e = s->h_owner_slot[q];
+        if (e >= 0 && y[e] < 0.f && !s->h_broken[q]) {
+            s->h_broken[q] = 1;
+            s->h_removed[q] = 1;
+        }
+    }
+    return TITAN_OK;
+}
+
+// New yield values of the listed springs (host table) written to both of
+// their slots; springs that are removed or broken keep theirs.
+int update_yield(titan_sim *s, const std::vector<int64_t> &springs)
+{
+    std::vector<int64_t> slot;
+    std::vector<float> val;
+    for (int64_t q : springs) {
+        if (s->h_owner_slot[q] < 0 || (!s->h_removed.empty() && s->h_removed[q]))
+            continue;
+        slot.push_back(s->h_owner_slot[q]);
+        slot.push_back(s->h_other_slot[q]);
+        val.push_back(s->h_yield[q]);
+        val.push_back(s->h_yield[q]);
+    }
+    const int64_t m = (int64_t)slot.size();
+    if (m == 0)
+        return TITAN_OK;
+    int64_t *dslot = nullptr;
+    float *dval = nullptr;
+    if (int rc = dev_alloc(s, sizeof(int64_t) * m, (void **)&dslot))
+        return rc;
+    if (int rc = dev_alloc(s, sizeof(float) * m, (void **)&dval)) {
+        dev_free(s, dslot);
+        return rc;
+    }
+    hipError_t e = hipMemcpyAsync(dslot, slot.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, s->stream);
+    if (!e)
+        e = hipMemcpyAsync(dval, val.data(), sizeof(float) * m, hipMemcpyHostToDevice, s->stream);
+    if (!e)
+        e = launch_scatter(s->gg.yield, dslot, dval, m, s->stream);
+    if (!e)
+        e = hipStreamSynchronize(s->stream);
+    dev_free(s, dslot);
+    dev_free(s, dval);
+    return e == hipSuccess ? TITAN_OK : hip_fail(s, e, "updating yield values");
+}
+
 int rebuild_engines(titan_sim *s)
 {
+    if (int rc = sync_broken(s))
+        return rc;
     destroy_batch_engine(s);
     dev_free_engine(s);
     s->gg = GatherGraph{};

@@ -20,7 +20,12 @@ namespace titan {
 
 namespace {
 
-template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool FORCES>
+// Sum-of-forces mode of a kernel: breakable springs are tested, and their
+// breaks recorded unless the launch only queries the forces.
+template <bool YIELD, bool FORCES>
+constexpr int yield_mode = YIELD ? (FORCES ? 1 : 2) : 0;
+
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool FORCES, bool YIELD>
 __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateIO io, StepConsts sc)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -32,7 +37,7 @@ __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateI
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
     float fx = 0.f, fy = 0.f, fz = 0.f;
     const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), (double)sc.step * sc.dt64};
-    sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE>(
+    sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE, yield_mode<YIELD, FORCES>>(
         g, base, slice_width(g, i), xi, ui, vi, ck, sc, [&](int64_t e) { return stream_load(g.nbr + e); },
         [&](int j, float4 &xj, float4 &uj, float4 &vj) {
             uj = io.U_in[j];
@@ -52,7 +57,7 @@ __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateI
         atomicMin(io.first_bad, (unsigned long long)sc.step);
 }
 
-template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool FORCES>
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool FORCES, bool YIELD>
 __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateIO io, StepConsts sc)
 {
     extern __shared__ float4 smem[];
@@ -91,7 +96,7 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
     float fx = 0.f, fy = 0.f, fz = 0.f;
     const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), (double)sc.step * sc.dt64};
-    sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE>(
+    sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE, yield_mode<YIELD, FORCES>>(
         g, base, slice_width(g, i), xi, ui, vi, ck, sc, [&](int64_t e) { return (int)stream_load(g.nbr_local + e); },
         [&](int q, float4 &xj, float4 &uj, float4 &vj) {
             uj = sU[q];
@@ -111,7 +116,7 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
         atomicMin(io.first_bad, (unsigned long long)sc.step);
 }
 
-template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST>
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool YIELD = false>
 hipError_t launch4(const GatherGraph &g, const StateIO &io, const StepConsts &sc, bool forces, bool tiled,
                    hipStream_t st)
 {
@@ -119,15 +124,19 @@ hipError_t launch4(const GatherGraph &g, const StateIO &io, const StepConsts &sc
         const dim3 grid((unsigned)g.n_tiles), block(kTile);
         const size_t lds = (size_t)g.max_local * sizeof(float4) * (DAMP ? 3 : 2);
         if (forces)
-            hipLaunchKernelGGL((tiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, true>), grid, block, lds, st, g, io, sc);
+            hipLaunchKernelGGL((tiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, true, YIELD>), grid, block, lds, st, g,
+                               io, sc);
         else
-            hipLaunchKernelGGL((tiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, false>), grid, block, lds, st, g, io, sc);
+            hipLaunchKernelGGL((tiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, false, YIELD>), grid, block, lds, st, g,
+                               io, sc);
     } else {
         const dim3 grid((unsigned)((g.n + 255) / 256)), block(256);
         if (forces)
-            hipLaunchKernelGGL((untiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, true>), grid, block, 0, st, g, io, sc);
+            hipLaunchKernelGGL((untiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, true, YIELD>), grid, block, 0, st, g,
+                               io, sc);
         else
-            hipLaunchKernelGGL((untiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, false>), grid, block, 0, st, g, io, sc);
+            hipLaunchKernelGGL((untiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, false, YIELD>), grid, block, 0, st, g,
+                               io, sc);
     }
     return hipGetLastError();
 }
@@ -250,7 +259,12 @@ hipError_t launch_gather_step(const GatherGraph &g, const StateIO &io, const Ste
     const bool damp = dampv || g.c_uniform != 0.f;
     tiled = tiled && g.nbr_local != nullptr;
     // (ACT, WAVE, DAMP, DAMPV, REST); WAVE implies ACT, DAMPV implies DAMP.
-    const int key = (act ? 8 : 0) | (damp ? 4 : 0) | (dampv ? 2 : 0) | (rest ? 1 : 0) | (wave ? 16 : 0);
+    // breakable springs come with per-slot damping and rest lengths
+    const bool yield = g.yield != nullptr;
+    if (yield && !(dampv && rest))
+        return hipErrorInvalidValue;
+    const int key = (act ? 8 : 0) | (damp ? 4 : 0) | (dampv ? 2 : 0) | (rest ? 1 : 0) | (wave ? 16 : 0) |
+                    (yield ? 32 : 0);
     switch (key) {
     case 0: return launch4<false, false, false, false, false>(g, io, sc, forces_only, tiled, stream);
     case 1: return launch4<false, false, false, false, true>(g, io, sc, forces_only, tiled, stream);
@@ -270,6 +284,9 @@ hipError_t launch_gather_step(const GatherGraph &g, const StateIO &io, const Ste
     case 29: return launch4<true, true, true, false, true>(g, io, sc, forces_only, tiled, stream);
     case 30: return launch4<true, true, true, true, false>(g, io, sc, forces_only, tiled, stream);
     case 31: return launch4<true, true, true, true, true>(g, io, sc, forces_only, tiled, stream);
+    case 39: return launch4<false, false, true, true, true, true>(g, io, sc, forces_only, tiled, stream);
+    case 47: return launch4<true, false, true, true, true, true>(g, io, sc, forces_only, tiled, stream);
+    case 63: return launch4<true, true, true, true, true, true>(g, io, sc, forces_only, tiled, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -12,6 +12,13 @@
 //     l - L(t) = (l - |R|) + d0 - L0 (C sin + S cos),   d0 = |R| - L0.
 // When every rest length is the initial length, d0 = 0 and L0 = |R|.
 //
+// Breakable springs (Sec. III-B, material yield values): a spring whose
+// elastic force |k (l - L(t))| exceeds its yield value Y breaks in that force
+// evaluation and exerts no force from then on (its damper included).  Per
+// slot, Y = +inf never breaks and Y < 0 marks a broken spring; both ends of a
+// spring compute the same |k (l - L(t))| (exactly negated operands), so they
+// take the same decision and each records it in its own slot.
+//
 // Mass update (Sec. III-B, Eq. 1: dx = xdot dt + xddot dt^2, semi-implicit
 // Euler): a = F/m + g (+ ground normal force -k_g z / m while z < 0),
 // v* = v + a dt; in contact, Coulomb friction scales the tangential part of
@@ -32,6 +39,7 @@ struct SpringConst {
     float d0;     // |R| - L0 (only with explicit rest lengths)
     float L0;     // rest length (only with explicit rest lengths)
     double t_off; // wave-law offset t_o (only with the wave law)
+    float yield;  // yield value Y; < 0: broken (only with breakable springs)
 };
 
 // Actuation clock of one step: (sin, cos)(omega t_n) for the phasor law, and
@@ -75,8 +83,9 @@ __device__ __forceinline__ float act_factor(const SpringConst &p, const Clock &c
 // Force on mass i from one incident spring (xi, ui, vi: mass i; xj, uj, vj:
 // the other end).  Evaluating the same spring from its other end gives the
 // exact negative: every operand is negated, so every rounding is the same.
-template <bool ACT, bool DAMP, bool REST>
-__device__ __forceinline__ void spring_force(const float4 &xi, const float4 &ui, const float4 &vi,
+// With YIELD, returns true when the spring breaks in this evaluation.
+template <bool ACT, bool DAMP, bool REST, bool YIELD = false>
+__device__ __forceinline__ bool spring_force(const float4 &xi, const float4 &ui, const float4 &vi,
                                              const float4 &xj, const float4 &uj, const float4 &vj,
                                              const SpringConst &p, float act, float &fx, float &fy, float &fz)
 {
@@ -106,13 +115,18 @@ __device__ __forceinline__ void spring_force(const float4 &xi, const float4 &ui,
     }
     const float ux = dx * il, uy = dy * il, uz = dz * il;
     float mag = p.k * stretch;
+    // coincident ends (no direction) are not tested; NaN fails the test
+    const bool holds = !YIELD || !ok || fabsf(mag) <= p.yield;
     if (DAMP) {
         const float vr = fmaf(vj.x - vi.x, ux, fmaf(vj.y - vi.y, uy, (vj.z - vi.z) * uz));
         mag = fmaf(p.c, vr, mag);
     }
+    if (YIELD)
+        mag = holds ? mag : 0.f;
     fx = fmaf(mag, ux, fx);
     fy = fmaf(mag, uy, fy);
     fz = fmaf(mag, uz, fz);
+    return YIELD && !holds && p.yield >= 0.f;
 }
 
 // Mass update.  Returns false if the new state is not finite.
@@ -174,7 +188,7 @@ __device__ __forceinline__ T const_load(const T *p)
 
 // NT: the constants are streamed once per launch (gather engines); the
 // batched engine reads them every step of a launch and keeps them cached.
-template <bool ACT, bool DAMPV, bool REST, bool NT, bool WAVE = false>
+template <bool ACT, bool DAMPV, bool REST, bool NT, bool WAVE = false, bool YIELD = false>
 __device__ __forceinline__ SpringConst load_const(const GatherGraph &g, int64_t e)
 {
     SpringConst p;
@@ -185,6 +199,7 @@ __device__ __forceinline__ SpringConst load_const(const GatherGraph &g, int64_t 
     p.d0 = REST ? const_load<NT>(g.d0 + e) : 0.f;
     p.L0 = REST ? const_load<NT>(g.rest + e) : 0.f;
     p.t_off = WAVE ? const_load<NT>(g.t_off + e) : 0.0;
+    p.yield = YIELD ? const_load<NT>(g.yield + e) : 0.f;
     return p;
 }
 
@@ -194,10 +209,11 @@ __device__ __forceinline__ SpringConst load_const(const GatherGraph &g, int64_t 
 // slots (neighbour index and spring constants) are issued together before
 // any of them is used, so each wave keeps several requests in flight.
 // Nbr(e) loads the neighbour reference of slot e; State(ref, xj, uj, vj)
-// fetches that neighbour's state.
+// fetches that neighbour's state.  YIELD: 0 unbreakable springs; 1 apply the
+// yield test (a force query); 2 apply it and record breaks in the slot.
 constexpr int kUnroll = TITAN_UNROLL;
 
-template <bool ACT, bool DAMP, bool DAMPV, bool REST, bool NT, bool WAVE, class Nbr, class State>
+template <bool ACT, bool DAMP, bool DAMPV, bool REST, bool NT, bool WAVE, int YIELD = 0, class Nbr, class State>
 __device__ __forceinline__ void sum_forces(const GatherGraph &g, int64_t base, int width, const float4 &xi,
                                            const float4 &ui, const float4 &vi, const Clock &ck,
                                            const StepConsts &sc, Nbr nbr, State state, float &fx, float &fy,
@@ -211,23 +227,28 @@ __device__ __forceinline__ void sum_forces(const GatherGraph &g, int64_t base, i
         for (int u = 0; u < kUnroll; ++u) {
             const int64_t e = base + (int64_t)(w + u) * kSlice;
             ref[u] = nbr(e);
-            p[u] = load_const<ACT, DAMPV, REST, NT, WAVE>(g, e);
+            p[u] = load_const<ACT, DAMPV, REST, NT, WAVE, YIELD != 0>(g, e);
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             float4 xj, uj, vj;
             state(ref[u], xj, uj, vj);
-            spring_force<ACT, DAMP, REST>(xi, ui, vi, xj, uj, vj, p[u], act_factor<ACT, WAVE>(p[u], ck, sc), fx, fy,
-                                          fz);
+            const bool broke = spring_force<ACT, DAMP, REST, YIELD != 0>(
+                xi, ui, vi, xj, uj, vj, p[u], act_factor<ACT, WAVE>(p[u], ck, sc), fx, fy, fz);
+            if (YIELD == 2 && broke)
+                g.yield[base + (int64_t)(w + u) * kSlice] = -1.f;
         }
     }
     for (; w < width; ++w) {
         const int64_t e = base + (int64_t)w * kSlice;
         const int ref = nbr(e);
-        const SpringConst p = load_const<ACT, DAMPV, REST, NT, WAVE>(g, e);
+        const SpringConst p = load_const<ACT, DAMPV, REST, NT, WAVE, YIELD != 0>(g, e);
         float4 xj, uj, vj;
         state(ref, xj, uj, vj);
-        spring_force<ACT, DAMP, REST>(xi, ui, vi, xj, uj, vj, p, act_factor<ACT, WAVE>(p, ck, sc), fx, fy, fz);
+        const bool broke = spring_force<ACT, DAMP, REST, YIELD != 0>(xi, ui, vi, xj, uj, vj, p,
+                                                                     act_factor<ACT, WAVE>(p, ck, sc), fx, fy, fz);
+        if (YIELD == 2 && broke)
+            g.yield[e] = -1.f;
     }
 }
 

@@ -347,6 +347,10 @@ extern "C" int titan_add_springs(titan_sim *s, int64_t n, const int64_t *ends, c
     }
     if (!s->h_removed.empty())
         s->h_removed.resize(s->h_k.size(), 0);
+    if (!s->h_yield.empty())
+        s->h_yield.resize(s->h_k.size(), INFINITY);
+    if (!s->h_broken.empty())
+        s->h_broken.resize(s->h_k.size(), 0);
     if (s->finalized && n > 0) {
         const int64_t first = s->ns;
         s->ns = (int64_t)s->h_k.size();
@@ -495,6 +499,57 @@ extern "C" int titan_remove_springs(titan_sim *s, int64_t n, const int64_t *spri
         if (q < 0 || q >= ns)
             return fail(TITAN_EINVAL, "spring %lld out of range [0, %lld)", (long long)q, (long long)ns);
     return remove_springs_locked(s, list);
+}
+
+extern "C" int titan_set_yield(titan_sim *s, int64_t first, int64_t count, const float *yield)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    const int64_t ns = (int64_t)s->h_k.size();
+    if (first < 0 || count < 0 || first > ns || count > ns - first || (count > 0 && !yield))
+        return fail(TITAN_EINVAL, "bad spring range [%lld, +%lld) of %lld", (long long)first, (long long)count,
+                    (long long)ns);
+    for (int64_t q = 0; q < count; ++q)
+        if (!(yield[q] > 0.f))  // NaN fails too
+            return fail(TITAN_EINVAL, "spring %lld: yield value must be > 0 (or +inf)", (long long)(first + q));
+    if (s->finalized && s->dev_error)
+        return fail(TITAN_EDEVICE, "sim is in a failed device state");
+    if (s->finalized && !s->layout_dirty)
+        if (int rc = sync_broken(s))  // keep the breaks already recorded
+            return rc;
+    if (s->h_yield.empty())
+        s->h_yield.assign(ns, INFINITY);
+    std::copy(yield, yield + count, s->h_yield.begin() + first);
+    if (!s->finalized || s->layout_dirty || count == 0)
+        return TITAN_OK;
+    if (!s->gg.yield) {  // the layout has no yield values yet: rebuilt before the next step
+        s->layout_dirty = true;
+        return TITAN_OK;
+    }
+    std::vector<int64_t> list(count);
+    for (int64_t q = 0; q < count; ++q)
+        list[q] = first + q;
+    return update_yield(s, list);
+}
+
+extern "C" int titan_get_broken(titan_sim *s, int64_t first, int64_t count, uint8_t *broken)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    const int64_t ns = (int64_t)s->h_k.size();
+    if (first < 0 || count < 0 || first > ns || count > ns - first || (count > 0 && !broken))
+        return fail(TITAN_EINVAL, "bad spring range [%lld, +%lld) of %lld", (long long)first, (long long)count,
+                    (long long)ns);
+    if (s->finalized && s->dev_error)
+        return fail(TITAN_EDEVICE, "sim is in a failed device state");
+    if (s->finalized && !s->layout_dirty)
+        if (int rc = sync_broken(s))
+            return rc;
+    for (int64_t q = 0; q < count; ++q)
+        broken[q] = s->h_broken.empty() ? 0 : s->h_broken[first + q];
+    return TITAN_OK;
 }
 
 extern "C" int titan_remove_masses(titan_sim *s, int64_t n, const int64_t *masses)
@@ -1075,6 +1130,8 @@ extern "C" int titan_rollout_grad(titan_sim *s, int64_t nsteps, int32_t checkpoi
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->params.actuation != TITAN_ACT_PHASOR)
         return fail(TITAN_ESTATE, "the rollout adjoint covers phasor actuation only");
+    if (!s->h_yield.empty())
+        return fail(TITAN_ESTATE, "the rollout adjoint covers unbreakable springs only");
     if (int rc = ready(s))
         return rc;
     if (int rc = ensure_layout(s))

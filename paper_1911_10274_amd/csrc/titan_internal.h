@@ -70,6 +70,7 @@ struct GatherGraph {
     const float *act_c;        // [slots] amp*cos(phase), or null: no actuation
     const float *act_s;        // [slots] amp*sin(phase)
     const double *t_off;       // [slots] wave-law offsets t_o, or null: phasor law (act_s used)
+    float *yield;              // [slots] yield values (< 0: broken; written by the step), or null
     const float *d0;           // [slots] |R| - rest (FP64-rounded), or null: rest = |R|
     const float *rest;         // [slots] rest length (with d0)
     const float4 *X0;          // [n] reference positions (w unused)

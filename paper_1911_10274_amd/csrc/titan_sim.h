@@ -88,6 +88,8 @@ struct titan_sim {
     std::vector<int64_t> h_halo_off;   // tiled layout: halo lists
     std::vector<int32_t> h_halo_idx;
     std::vector<int64_t> h_group_off;  // batched layout: group ranges (empty: none)
+    std::vector<float> h_yield;    // per spring: yield value (+inf: never breaks); empty: none
+    std::vector<uint8_t> h_broken; // per spring: broken (as of the last sync_broken)
     int64_t layout_builds = 0;     // times the layouts were built
     int64_t springs_in_place = 0;  // springs inserted into spare slots
 
@@ -140,6 +142,11 @@ void destroy_engines(titan_sim *s);
 // the layout otherwise (in both cases nothing is written and the layouts must
 // be rebuilt); or an error code (< 0).
 int insert_springs(titan_sim *s, int64_t first, int64_t count);
+// Copy the breaks the steps have recorded into h_broken (and h_removed);
+// waits for the stream.
+int sync_broken(titan_sim *s);
+// Write h_yield of the listed springs into the current layout.
+int update_yield(titan_sim *s, const std::vector<int64_t> &springs);
 // Device array of the batched layout's group-relative neighbour indices
 // (null without a batched layout).
 uint16_t *batch_nbr_group(titan_sim *s);

@@ -126,6 +126,8 @@ def _load():
         "titan_set_springs": ([_vp, ctypes.c_int64, ctypes.c_int64, _fp, _fp, _fp, _fp], ctypes.c_int),
         "titan_remove_springs": ([_vp, ctypes.c_int64, _i64p], ctypes.c_int),
         "titan_remove_masses": ([_vp, ctypes.c_int64, _i64p], ctypes.c_int),
+        "titan_set_yield": ([_vp, ctypes.c_int64, ctypes.c_int64, _fp], ctypes.c_int),
+        "titan_get_broken": ([_vp, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint8)], ctypes.c_int),
         "titan_rollout_grad": ([_vp, ctypes.c_int64, ctypes.c_int32, _fp, _fp, _fp, _fp, _fp], ctypes.c_int),
         "titan_get_info": ([_vp, ctypes.POINTER(_Info)], ctypes.c_int),
         "titan_mlp_create": ([ctypes.c_int32, _i32p, _vp, ctypes.POINTER(_Allocator), ctypes.POINTER(_vp)],
@@ -302,6 +304,18 @@ class Sim:
         q = np.ascontiguousarray(masses, dtype=np.int64).reshape(-1)
         _check(lib.titan_remove_masses(self._h, q.size, q.ctypes.data_as(_i64p)))
 
+    def set_yield(self, yield_values, first: int = 0):
+        """Yield values of springs first.. (titan_set_yield; inf: never breaks)."""
+        y = np.ascontiguousarray(yield_values, dtype=np.float32).reshape(-1)
+        _check(lib.titan_set_yield(self._h, first, y.size, y.ctypes.data_as(_fp)))
+
+    def get_broken(self, first: int = 0, count: int | None = None) -> np.ndarray:
+        """Broken flags of springs first.. (titan_get_broken), as bools."""
+        count = self.info()["n_springs"] - first if count is None else count
+        out = np.zeros(count, np.uint8)
+        _check(lib.titan_get_broken(self._h, first, count, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+        return out.astype(bool)
+
     def set_params(self, params: Params):
         _check(lib.titan_set_params(self._h, ctypes.byref(params._c())))
         self.params = params
@@ -412,6 +426,8 @@ def sim_from_scene(scene: dict, params: Params, rest=None, **kw) -> Sim:
     if scene["ends"].shape[0]:
         sim.add_springs(scene["ends"], scene["k"], damping=scene.get("damping"), rest=rest,
                         amp=scene.get("amp"), phase=scene.get("phase"))
+        if scene.get("yield") is not None:
+            sim.set_yield(scene["yield"])
     return sim
 
 
