@@ -35,6 +35,7 @@ class _Params(ctypes.Structure):
         ("omega", ctypes.c_double),
         ("wave", ctypes.c_int32),
         ("period", ctypes.c_double),
+        ("integrator", ctypes.c_int32),
     ]
 
 
@@ -64,7 +65,8 @@ def _load():
                                           ctypes.c_double, _dp, _dp, _dp]
         lib.orc_integrate.argtypes = [ctypes.c_int64, _dp, ctypes.POINTER(_Params), _dp, _dp, _dp]
         lib.orc_run.argtypes = [ctypes.c_int64, _dp, ctypes.c_int64, _lp, _dp, _dp, _dp, _dp, _dp,
-                                ctypes.POINTER(_Params), _dp, _u8p, ctypes.c_int64, ctypes.c_int64, _dp, _dp, _dp]
+                                ctypes.POINTER(_Params), _dp, _u8p, _dp, ctypes.POINTER(ctypes.c_int32),
+                                ctypes.c_int64, ctypes.c_int64, _dp, _dp, _dp]
         lib.orc_run.restype = ctypes.c_int
         _i32p = ctypes.POINTER(ctypes.c_int32)
         _u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -88,6 +90,9 @@ def _ptr(a, t=_dp):
     return None if a is None else a.ctypes.data_as(t)
 
 
+INTEGRATORS = {"euler": 0, "verlet": 1, "rk4": 2}
+
+
 @dataclass
 class Params:
     dt: float = 1.0e-4
@@ -98,12 +103,13 @@ class Params:
     omega: float = 0.0
     wave: bool = False    # wave actuation (Eqs. 3-5): a scene's phase holds the offsets t_o
     period: float = 1.0   # wave period t_p, s
+    integrator: str = "euler"  # "euler" (semi-implicit), "verlet" (velocity Verlet) or "rk4"
 
     @classmethod
     def from_dict(cls, d: dict) -> "Params":
         return cls(dt=d["dt"], gravity=tuple(d["gravity"]), ground=bool(d["ground"]),
                    ground_k=d["ground_k"], mu=d["mu"], omega=d["omega"], wave=bool(d.get("wave", False)),
-                   period=d.get("period", 1.0))
+                   period=d.get("period", 1.0), integrator=d.get("integrator", "euler"))
 
     def _c(self) -> _Params:
         p = _Params()
@@ -115,6 +121,7 @@ class Params:
         p.omega = self.omega
         p.wave = 1 if self.wave else 0
         p.period = self.period
+        p.integrator = INTEGRATORS[self.integrator]
         return p
 
 
@@ -138,7 +145,12 @@ class System:
     breakable springs (Sec. III-B): ``broken`` holds one flag per spring,
     starts all clear and is updated by ``run``, ``trajectory`` and
     ``spring_forces`` unless they are given a flag array of their own (then
-    that array is updated in place)."""
+    that array is updated in place).
+
+    Velocity Verlet carries the acceleration of each step's end into the
+    next step: ``run`` and ``trajectory`` keep it in ``acc`` (None: none
+    carried, recomputed from the starting state), so that consecutive calls
+    continue one run; set ``acc = None`` to start afresh."""
 
     def __init__(self, scene: dict, rest=None):
         self.x0 = _d(scene["pos"]).reshape(-1, 3).copy()
@@ -160,6 +172,7 @@ class System:
         self.rest = _d(rest)
         self.yield_ = _d(scene.get("yield"))
         self.broken = np.zeros(self.ns, np.uint8) if self.yield_ is not None else None
+        self.acc = None
 
     def _flags(self, broken):
         if self.yield_ is None:
@@ -189,10 +202,17 @@ class System:
         f = np.empty((self.n, 3), np.float64) if want_forces else None
         p = params._c()
         b = self._flags(broken)
+        acc, have = None, ctypes.c_int32(0)
+        if params.integrator == "verlet":
+            acc = np.zeros((self.n, 3), np.float64) if self.acc is None else self.acc
+            have.value = 0 if self.acc is None else 1
         rc = _load().orc_run(self.n, _ptr(self.mass), self.ns, _ptr(self.ends, _lp), _ptr(self.k),
                              _ptr(self.c), _ptr(self.rest), _ptr(self.amp), _ptr(self.phase),
-                             ctypes.byref(p), _ptr(self.yield_), _ptr(b, ctypes.POINTER(ctypes.c_uint8)), step0,
+                             ctypes.byref(p), _ptr(self.yield_), _ptr(b, ctypes.POINTER(ctypes.c_uint8)),
+                             _ptr(acc), ctypes.byref(have) if acc is not None else None, step0,
                              nsteps, _ptr(x), _ptr(v), _ptr(f))
+        if acc is not None and have.value:
+            self.acc = acc
         if rc != 0:
             raise MemoryError("oracle run failed")
         return x, v, f
@@ -225,6 +245,8 @@ class System:
         every contact / friction-stick decision of the run."""
         if self.yield_ is not None:
             raise ValueError("the rollout covers unbreakable springs only")
+        if params.integrator != "euler":
+            raise ValueError("the rollout covers the Euler step only")
         b, nb = self._body(body)
         loss = np.empty(nb, np.float64)
         sig = ctypes.c_uint64()
@@ -244,6 +266,8 @@ class System:
             raise ValueError("the rollout adjoint covers phasor actuation only")
         if self.yield_ is not None:
             raise ValueError("the rollout adjoint covers unbreakable springs only")
+        if params.integrator != "euler":
+            raise ValueError("the rollout adjoint covers the Euler step only")
         b, nb = self._body(body)
         w = np.ones(nb) if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
         loss = np.empty(nb, np.float64)

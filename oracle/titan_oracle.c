@@ -33,6 +33,19 @@
  *     load); a spring whose elastic force exceeds its yield value breaks in
  *     that force evaluation, exerts no force in it, and stays broken.
  *     Springs with coincident ends (no direction, no force) are not tested.
+ *   - Sec. III-B names Verlet and RK4 as alternatives to Euler.  Readings
+ *     taken here (integrator 1 and 2; 0 is the semi-implicit Euler above):
+ *     both integrate the smooth forces (springs with their dampers, gravity,
+ *     the ground's normal force at the evaluated position); Coulomb friction
+ *     is then applied once per step as in the Euler step -- normal force from
+ *     the step's starting height, tangential velocity scaled by
+ *     max(0, 1 - mu F_n dt / (m |v_t|)) -- and the position takes the same
+ *     velocity change times dt.  Pinned masses keep position and velocity.
+ *     Velocity Verlet: v' = v + a dt/2, x' = x + v' dt, a' = a(x', v', t+dt),
+ *     v'' = v' + a' dt/2; the dampers at the end of the step see the
+ *     half-step velocity v', and a' is carried to the next step (recomputed
+ *     from (x, v, t) when none is carried).  RK4: the classical four stages
+ *     on (x, v) at t, t + dt/2, t + dt/2, t + dt, weights 1/6, 2/6, 2/6, 1/6.
  *
  * Accumulation is a serial scatter loop over springs in index order
  * (Sec. III-B's "apply to each corresponding mass"), all in double precision.
@@ -51,6 +64,7 @@ typedef struct {
     double omega;     /* actuation angular frequency, rad/s */
     int32_t wave;     /* nonzero: wave actuation (Eqs. 3-5), phase = offset t_o */
     double period;    /* wave actuation period t_p, s */
+    int32_t integrator; /* 0 semi-implicit Euler, 1 velocity Verlet, 2 RK4 */
 } orc_params;
 
 /* Factor by which spring s's rest length exceeds its base length at time t:
@@ -160,19 +174,206 @@ void orc_integrate(int64_t n, const double *mass, const orc_params *p,
     }
 }
 
-/* nsteps steps starting at step index step0 (t_n = n * dt).  If f_last is
+/* Acceleration of the smooth forces: a = f / m + g, plus the ground's normal
+ * force -k_g z / m while z < 0 (z of the given positions).  Pinned masses: 0. */
+static void accel(int64_t n, const double *mass, const orc_params *p, const double *f, const double *x, double *a)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double m = mass[i];
+        for (int q = 0; q < 3; ++q)
+            a[3 * i + q] = 0.0;
+        if (m == 0.0)
+            continue;
+        for (int q = 0; q < 3; ++q)
+            a[3 * i + q] = f[3 * i + q] / m + p->g[q];
+        double z = x[3 * i + 2];
+        if (p->ground && z < 0.0)
+            a[3 * i + 2] += -p->ground_k * z / m;
+    }
+}
+
+/* Coulomb friction after a smooth update (integrators 1 and 2): for a mass
+ * whose starting height z0 is below the ground, the tangential velocity is
+ * scaled by max(0, 1 - mu F_n dt / (m |v_t|)), F_n = -k_g z0, and the
+ * position moves by the velocity change times dt. */
+static void friction_after(int64_t n, const double *mass, const orc_params *p, const double *x0, double *x,
+                           double *v)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double m = mass[i];
+        double z = x0[3 * i + 2];
+        if (m == 0.0 || !(p->ground && z < 0.0))
+            continue;
+        double Fn = -p->ground_k * z;
+        double vt = sqrt(v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1]);
+        if (!(vt > 0.0))
+            continue;
+        double scale = 1.0 - p->mu * Fn * p->dt / (m * vt);
+        if (scale < 0.0)
+            scale = 0.0;
+        for (int q = 0; q < 2; ++q) {
+            double w = v[3 * i + q] * scale;
+            x[3 * i + q] += (w - v[3 * i + q]) * p->dt;
+            v[3 * i + q] = w;
+        }
+    }
+}
+
+/* One velocity-Verlet step from (x, v) at step index `step`.  acc (n*3) holds
+ * the carried acceleration when *have_acc, and receives the new one; f
+ * receives the spring forces of (x, v, t) (the step's starting state; with a
+ * carried acceleration they are evaluated for the caller only: yield tests
+ * applied to a copy of the flags, broken in the step proper); w is scratch of
+ * 2 * n*3 doubles, bw of ns flags (or NULL without yields).  Returns 0. */
+static void verlet_step(int64_t n, const double *mass, int64_t ns, const int64_t *ends, const double *k,
+                        const double *c, const double *rest, const double *amp, const double *phase,
+                        const orc_params *p, const double *yield, uint8_t *broken, int64_t step, double *x,
+                        double *v, double *acc, int32_t *have_acc, double *f, double *w, uint8_t *bw)
+{
+    const size_t S = 3 * (size_t)n;
+    const double dt = p->dt, t = (double)step * dt, t1 = (double)(step + 1) * dt;
+    double *x0 = w, *f1 = w + S;
+    memcpy(x0, x, sizeof(double) * S);
+    if (!*have_acc) {
+        orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, p->wave, p->period, yield, broken, t, x, v,
+                          f);
+        accel(n, mass, p, f, x, acc);
+        *have_acc = 1;
+    } else {
+        if (yield)
+            memcpy(bw, broken, (size_t)ns);
+        orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, p->wave, p->period, yield,
+                          yield ? bw : NULL, t, x, v, f);
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (mass[i] == 0.0)
+            continue;
+        for (int q = 0; q < 3; ++q) {
+            v[3 * i + q] += 0.5 * dt * acc[3 * i + q];
+            x[3 * i + q] += dt * v[3 * i + q];
+        }
+    }
+    orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, p->wave, p->period, yield, broken, t1, x, v, f1);
+    accel(n, mass, p, f1, x, acc);
+    for (int64_t i = 0; i < n; ++i) {
+        if (mass[i] == 0.0)
+            continue;
+        for (int q = 0; q < 3; ++q)
+            v[3 * i + q] += 0.5 * dt * acc[3 * i + q];
+    }
+    friction_after(n, mass, p, x0, x, v);
+}
+
+/* One classical RK4 step on (x, v) from step index `step`; f receives the
+ * spring forces of the first stage (the step's starting state); w is scratch
+ * of 8 * n*3 doubles. */
+static void rk4_step(int64_t n, const double *mass, int64_t ns, const int64_t *ends, const double *k,
+                     const double *c, const double *rest, const double *amp, const double *phase,
+                     const orc_params *p, const double *yield, uint8_t *broken, int64_t step, double *x, double *v,
+                     double *f, double *w)
+{
+    const size_t S = 3 * (size_t)n;
+    const double dt = p->dt, t = (double)step * dt;
+    double *x0 = w, *v0 = w + S, *xs = w + 2 * S, *vs = w + 3 * S, *sx = w + 4 * S, *sv = w + 5 * S,
+           *a = w + 6 * S, *fs = w + 7 * S;
+    memcpy(x0, x, sizeof(double) * S);
+    memcpy(v0, v, sizeof(double) * S);
+    memcpy(xs, x, sizeof(double) * S);
+    memcpy(vs, v, sizeof(double) * S);
+    memset(sx, 0, sizeof(double) * S);
+    memset(sv, 0, sizeof(double) * S);
+    static const double c_time[4] = {0.0, 0.5, 0.5, 1.0};   /* stage times, in dt */
+    static const double c_next[3] = {0.5, 0.5, 1.0};        /* next stage offset, in dt */
+    static const double weight[4] = {1.0, 2.0, 2.0, 1.0};   /* times 1/6 */
+    for (int st = 0; st < 4; ++st) {
+        const double ts = t + c_time[st] * dt;
+        orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, p->wave, p->period, yield, broken, ts, xs,
+                          vs, fs);
+        if (st == 0)
+            memcpy(f, fs, sizeof(double) * S);
+        accel(n, mass, p, fs, xs, a);
+        for (int64_t i = 0; i < n; ++i) {
+            if (mass[i] == 0.0)
+                continue;
+            for (int q = 0; q < 3; ++q) {
+                const size_t e = 3 * (size_t)i + q;
+                sx[e] += weight[st] * vs[e];
+                sv[e] += weight[st] * a[e];
+            }
+        }
+        if (st < 3)
+            for (int64_t i = 0; i < n; ++i) {
+                if (mass[i] == 0.0)
+                    continue;
+                for (int q = 0; q < 3; ++q) {
+                    const size_t e = 3 * (size_t)i + q;
+                    const double xn = x0[e] + c_next[st] * dt * vs[e];
+                    const double vn = v0[e] + c_next[st] * dt * a[e];
+                    xs[e] = xn;
+                    vs[e] = vn;
+                }
+            }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (mass[i] == 0.0)
+            continue;
+        for (int q = 0; q < 3; ++q) {
+            const size_t e = 3 * (size_t)i + q;
+            x[e] = x0[e] + dt / 6.0 * sx[e];
+            v[e] = v0[e] + dt / 6.0 * sv[e];
+        }
+    }
+    friction_after(n, mass, p, x0, x, v);
+}
+
+/* nsteps steps of p->integrator starting at step index step0 (t_n = n * dt).
+ * Velocity Verlet carries its acceleration in acc (n*3) while *have_acc is
+ * set (NULL: none carried in or out).  If f_last is
  * non-NULL it receives the spring forces of the last step's starting state.
  * Scratch of n*3 doubles is allocated here.  Returns 0, or -2 on allocation
  * failure. */
 int orc_run(int64_t n, const double *mass, int64_t ns, const int64_t *ends,
             const double *k, const double *c, const double *rest,
             const double *amp, const double *phase, const orc_params *p,
-            const double *yield, uint8_t *broken,
+            const double *yield, uint8_t *broken, double *acc, int32_t *have_acc,
             int64_t step0, int64_t nsteps, double *x, double *v, double *f_last)
 {
-    double *f = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    const size_t S = 3 * (size_t)(n > 0 ? n : 1);
+    double *f = (double *)malloc(sizeof(double) * S);
     if (!f)
         return -2;
+    if (p->integrator == 1 || p->integrator == 2) {
+        double *w = (double *)malloc(sizeof(double) * 8 * S);
+        double *own_acc = NULL;
+        int32_t own_have = 0;
+        uint8_t *bw = yield ? (uint8_t *)malloc((size_t)(ns > 0 ? ns : 1)) : NULL;
+        if (p->integrator == 1 && !acc) {
+            own_acc = (double *)malloc(sizeof(double) * S);
+            acc = own_acc;
+            have_acc = &own_have;
+        }
+        if (!w || (p->integrator == 1 && !acc) || (yield && !bw)) {
+            free(w);
+            free(own_acc);
+            free(bw);
+            free(f);
+            return -2;
+        }
+        for (int64_t s = 0; s < nsteps; ++s) {
+            if (p->integrator == 1)
+                verlet_step(n, mass, ns, ends, k, c, rest, amp, phase, p, yield, broken, step0 + s, x, v, acc,
+                            have_acc, f, w, bw);
+            else
+                rk4_step(n, mass, ns, ends, k, c, rest, amp, phase, p, yield, broken, step0 + s, x, v, f, w);
+            if (f_last && s == nsteps - 1)
+                memcpy(f_last, f, sizeof(double) * 3 * (size_t)n);
+        }
+        free(w);
+        free(own_acc);
+        free(bw);
+        free(f);
+        return 0;
+    }
     for (int64_t s = 0; s < nsteps; ++s) {
         double t = (double)(step0 + s) * p->dt;
         orc_spring_forces(n, ns, ends, k, c, rest, amp, phase, p->omega, p->wave, p->period, yield, broken, t, x,
@@ -280,6 +481,8 @@ int orc_rollout_loss(int64_t n, const double *mass, int64_t ns, const int64_t *e
                      const orc_params *p, const int32_t *body, int32_t nbody, int64_t nsteps,
                      const double *x0, const double *v0, double *loss, uint64_t *sig)
 {
+    if (p->integrator != 0)
+        return -1; /* the rollout covers the Euler step only */
     double *x = (double *)malloc(sizeof(double) * 3 * (size_t)(n + 1));
     double *v = (double *)malloc(sizeof(double) * 3 * (size_t)(n + 1));
     double *f = (double *)malloc(sizeof(double) * 3 * (size_t)(n + 1));
@@ -309,8 +512,8 @@ int orc_rollout_grad(int64_t n, const double *mass, int64_t ns, const int64_t *e
                      int64_t nsteps, const double *x0, const double *v0, double *loss, double *gk,
                      double *gC, double *gS, uint64_t *sig)
 {
-    if (p->wave)
-        return -1; /* the adjoint covers phasor actuation only */
+    if (p->wave || p->integrator != 0)
+        return -1; /* the adjoint covers phasor actuation and the Euler step only */
     const double dt = p->dt;
     const size_t S = 3 * (size_t)(n > 0 ? n : 1);
     double *X = (double *)malloc(sizeof(double) * S * (size_t)(nsteps + 1));
