@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TITAN_ABI_VERSION 3
+#define TITAN_ABI_VERSION 4
 
 /* Status codes. */
 #define TITAN_OK 0
@@ -92,6 +92,24 @@ typedef struct titan_sim titan_sim;
 
 /* Simulation parameters (SI units).  Taken by value at each call that
  * passes them. */
+/* Time integrators (Sec. III-B).  EULER: semi-implicit Euler, one force
+ * evaluation per step (the default; every engine).  VERLET: velocity Verlet,
+ * v' = v + a dt/2, x' = x + v' dt, a' = a(x', v', t + dt), v'' = v' + a' dt/2,
+ * one force evaluation per step: the acceleration is carried from step to
+ * step and recomputed from the current state after anything changes the
+ * system or its state (edits, titan_set_state / _step / _params / _springs /
+ * _yield); the end-of-step dampers see the half-step velocity v'.  RK4: the
+ * classical four stages on (x, v) at t, t + dt/2, t + dt/2, t + dt, four
+ * force evaluations per step.  Verlet and RK4 integrate springs, dampers,
+ * gravity and the ground's normal force; Coulomb friction is applied after
+ * the step as in the Euler step (normal force from the starting height), the
+ * position moving by the velocity change times dt.  They run on the gather
+ * and tiled engines; the batched engine and the rollout adjoint take EULER
+ * only. */
+#define TITAN_INTEG_EULER 0
+#define TITAN_INTEG_VERLET 1
+#define TITAN_INTEG_RK4 2
+
 typedef struct titan_params {
     double dt;          /* time step, s (> 0) */
     double gravity[3];  /* m/s^2, e.g. {0, 0, -9.81} */
@@ -103,6 +121,8 @@ typedef struct titan_params {
     double omega;       /* actuation angular frequency, rad/s */
     int32_t actuation;  /* TITAN_ACT_*; fixed once the system is finalized */
     double wave_period; /* TITAN_ACT_WAVE: period t_p, s (> 0) */
+    int32_t integrator; /* TITAN_INTEG_*: the time integrator (Sec. III-B
+                           names Euler, Verlet and RK4) */
 } titan_params;
 
 /* Optional device-memory provider.  alloc returns a device pointer aligned

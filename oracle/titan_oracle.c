@@ -231,7 +231,7 @@ static void verlet_step(int64_t n, const double *mass, int64_t ns, const int64_t
                         double *v, double *acc, int32_t *have_acc, double *f, double *w, uint8_t *bw)
 {
     const size_t S = 3 * (size_t)n;
-    const double dt = p->dt, t = (double)step * dt, t1 = (double)(step + 1) * dt;
+    const double dt = p->dt, t = (double)step * dt, t1 = t + dt; /* as RK4's last stage: t + 1 dt */
     double *x0 = w, *f1 = w + S;
     memcpy(x0, x, sizeof(double) * S);
     if (!*have_acc) {

@@ -463,7 +463,9 @@ int build_engines(titan_sim *s)
     // The batched layout is built whenever the bodies fit it (the adjoint
     // uses it); it steps the system when asked for, or when AUTO times it
     // faster.
-    if (int rc = build_batch_engine(s, want == TITAN_ENGINE_BATCHED || want == TITAN_ENGINE_AUTO))
+    // (the batched engine steps with the Euler integrator only)
+    if (int rc = build_batch_engine(s, (want == TITAN_ENGINE_BATCHED || want == TITAN_ENGINE_AUTO) &&
+                                           s->params.integrator == TITAN_INTEG_EULER))
         return rc;
     if (s->batch && s->batch_step)
         s->engine = TITAN_ENGINE_BATCHED;
@@ -612,8 +614,116 @@ StepConsts consts_for(const titan_sim *s, int64_t step, const float2 *trig)
     return sc;
 }
 
+// Buffers of the staged integrators, for the current number of masses.
+static int ensure_stage_buffers(titan_sim *s, bool rk4)
+{
+    if (s->stage_n != s->n) {
+        for (float4 *&b : s->stage_buf) {
+            if (b)
+                dev_free(s, b);
+            b = nullptr;
+        }
+        if (s->verlet_acc)
+            dev_free(s, s->verlet_acc);
+        s->verlet_acc = nullptr;
+        s->acc_valid = false;
+        s->stage_n = s->n;
+    }
+    const size_t bytes = sizeof(float4) * std::max<int64_t>(s->n, 1);
+    if (rk4) {
+        for (float4 *&b : s->stage_buf)
+            if (!b)
+                if (int rc = dev_alloc(s, bytes, (void **)&b))
+                    return rc;
+    } else if (!s->verlet_acc) {
+        if (int rc = dev_alloc(s, bytes, (void **)&s->verlet_acc))
+            return rc;
+        s->acc_valid = false;
+    }
+    return TITAN_OK;
+}
+
+// Velocity Verlet and RK4 (Sec. III-B): one gather launch per force
+// evaluation, on the plain engines.
+static int enqueue_staged(titan_sim *s, int64_t first_step, int64_t count)
+{
+    const bool rk4 = s->params.integrator == TITAN_INTEG_RK4;
+    if (int rc = ensure_stage_buffers(s, rk4))
+        return rc;
+    const double dt = s->params.dt;
+    // RK4's clock table holds half steps: entry 2q + j is t_(n0+q) + j dt/2
+    const int chunk = rk4 ? kTrigChunk / 2 : kTrigChunk;
+    for (int64_t c0 = 0; c0 < count; c0 += chunk) {
+        const int nc = (int)std::min<int64_t>(chunk, count - c0);
+        const int64_t n0 = first_step + c0;
+        if (rk4)
+            HIP_TRY(s, launch_trig_table(s->trig, 2 * n0, 2 * nc + 1, s->params.omega, 0.5 * dt, s->stream));
+        else
+            HIP_TRY(s, launch_trig_table(s->trig, n0, nc + 1, s->params.omega, dt, s->stream));
+        for (int q = 0; q < nc; ++q) {
+            const int64_t n = n0 + q;
+            float4 *const U0 = s->U[s->cur], *const V0 = s->V[s->cur];
+            float4 *const U1 = s->U[1 - s->cur], *const V1 = s->V[1 - s->cur];
+            StateIO io{};
+            io.first_bad = s->first_bad;
+            if (rk4) {
+                // stage s reads the previous stage's state; stages 1-3 write the
+                // next one (into alternating buffers), stage 4 the new state
+                io.U_base = U0;
+                io.V_base = V0;
+                io.sum_u = s->stage_buf[4];
+                io.sum_v = s->stage_buf[5];
+                const float4 *inU = U0, *inV = V0;
+                for (int st = kStageRk1; st <= kStageRk4; ++st) {
+                    float4 *oU = st == kStageRk4 ? U1 : s->stage_buf[(st & 1) ? 0 : 2];
+                    float4 *oV = st == kStageRk4 ? V1 : s->stage_buf[(st & 1) ? 1 : 3];
+                    io.U_in = inU;
+                    io.V_in = inV;
+                    io.U_out = oU;
+                    io.V_out = oV;
+                    const double c = st == kStageRk1 ? 0.0 : (st == kStageRk4 ? 1.0 : 0.5);
+                    StepConsts sc = consts_for(s, n, s->trig + 2 * q + (int)(2 * c));
+                    sc.t_add = c * dt;
+                    sc.stage = st;
+                    HIP_TRY(s, launch_gather_stage(s->gg, io, sc, s->tiled, s->stream));
+                    inU = oU;
+                    inV = oV;
+                }
+                s->cur = 1 - s->cur;
+                continue;
+            }
+            // velocity Verlet
+            io.A = s->verlet_acc;
+            if (!s->acc_valid) {
+                io.U_in = U0;
+                io.V_in = V0;
+                StepConsts sc = consts_for(s, n, s->trig + q);
+                sc.stage = kStageVerletInit;
+                HIP_TRY(s, launch_gather_stage(s->gg, io, sc, s->tiled, s->stream));
+                s->acc_valid = true;
+            }
+            HIP_TRY(s, launch_verlet_drift(U0, V0, s->verlet_acc, U1, V1, s->n, (float)dt, s->stream));
+            // the kick reads the drifted state and writes the step's result
+            // back over the starting state (each mass reads its own starting
+            // height first)
+            io.U_in = U1;
+            io.V_in = V1;
+            io.U_base = U0;
+            io.U_out = U0;
+            io.V_out = V0;
+            StepConsts sc = consts_for(s, n, s->trig + q + 1);
+            sc.t_add = dt;
+            sc.stage = kStageVerletKick;
+            HIP_TRY(s, launch_gather_stage(s->gg, io, sc, s->tiled, s->stream));
+        }
+    }
+    return TITAN_OK;
+}
+
 int enqueue_steps(titan_sim *s, int64_t first_step, int64_t count)
 {
+    if (s->params.integrator != TITAN_INTEG_EULER)
+        return enqueue_staged(s, first_step, count);
     if (s->engine == TITAN_ENGINE_BATCHED && s->batch && s->batch_step)
         return enqueue_batch_steps(s, first_step, count);
     for (int64_t c0 = 0; c0 < count; c0 += kTrigChunk) {

@@ -20,12 +20,16 @@ namespace titan {
 
 namespace {
 
+// What a launch does after the force sum: an Euler step, a force query, or
+// one stage of another integrator (StepConsts::stage).
+constexpr int kModeStep = 0, kModeForces = 1, kModeStage = 2;
+
 // Sum-of-forces mode of a kernel: breakable springs are tested, and their
 // breaks recorded unless the launch only queries the forces.
-template <bool YIELD, bool FORCES>
-constexpr int yield_mode = YIELD ? (FORCES ? 1 : 2) : 0;
+template <bool YIELD, int MODE>
+constexpr int yield_mode = YIELD ? (MODE == kModeForces ? 1 : 2) : 0;
 
-template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool FORCES, bool YIELD>
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, int MODE, bool YIELD>
 __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateIO io, StepConsts sc)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -36,8 +40,8 @@ __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateI
     const float4 xi = g.X0[i];
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
     float fx = 0.f, fy = 0.f, fz = 0.f;
-    const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), (double)sc.step * sc.dt64};
-    sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE, yield_mode<YIELD, FORCES>>(
+    const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), (double)sc.step * sc.dt64 + sc.t_add};
+    sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE, yield_mode<YIELD, MODE>>(
         g, base, slice_width(g, i), xi, ui, vi, ck, sc, [&](int64_t e) { return stream_load(g.nbr + e); },
         [&](int j, float4 &xj, float4 &uj, float4 &vj) {
             uj = io.U_in[j];
@@ -45,8 +49,13 @@ __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateI
             vj = DAMP ? io.V_in[j] : make_float4(0.f, 0.f, 0.f, 0.f);
         },
         fx, fy, fz);
-    if (FORCES) {
+    if (MODE == kModeForces) {
         io.F_out[i] = make_float4(fx, fy, fz, 0.f);
+        return;
+    }
+    if (MODE == kModeStage) {
+        if (!stage_update(i, xi, ui, vi, fx, fy, fz, io, sc))
+            atomicMin(io.first_bad, (unsigned long long)sc.step);
         return;
     }
     float4 uo, vo;
@@ -57,7 +66,7 @@ __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateI
         atomicMin(io.first_bad, (unsigned long long)sc.step);
 }
 
-template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool FORCES, bool YIELD>
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, int MODE, bool YIELD>
 __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateIO io, StepConsts sc)
 {
     extern __shared__ float4 smem[];
@@ -95,8 +104,8 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
 
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
     float fx = 0.f, fy = 0.f, fz = 0.f;
-    const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), (double)sc.step * sc.dt64};
-    sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE, yield_mode<YIELD, FORCES>>(
+    const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), (double)sc.step * sc.dt64 + sc.t_add};
+    sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE, yield_mode<YIELD, MODE>>(
         g, base, slice_width(g, i), xi, ui, vi, ck, sc, [&](int64_t e) { return (int)stream_load(g.nbr_local + e); },
         [&](int q, float4 &xj, float4 &uj, float4 &vj) {
             uj = sU[q];
@@ -104,8 +113,13 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
             vj = DAMP ? sV[q] : make_float4(0.f, 0.f, 0.f, 0.f);
         },
         fx, fy, fz);
-    if (FORCES) {
+    if (MODE == kModeForces) {
         io.F_out[i] = make_float4(fx, fy, fz, 0.f);
+        return;
+    }
+    if (MODE == kModeStage) {
+        if (!stage_update(i, xi, ui, vi, fx, fy, fz, io, sc))
+            atomicMin(io.first_bad, (unsigned long long)sc.step);
         return;
     }
     float4 uo, vo;
@@ -116,29 +130,51 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
         atomicMin(io.first_bad, (unsigned long long)sc.step);
 }
 
-template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool YIELD = false>
-hipError_t launch4(const GatherGraph &g, const StateIO &io, const StepConsts &sc, bool forces, bool tiled,
-                   hipStream_t st)
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool YIELD, int MODE>
+void launch_mode(const GatherGraph &g, const StateIO &io, const StepConsts &sc, bool tiled, hipStream_t st)
 {
     if (tiled) {
         const dim3 grid((unsigned)g.n_tiles), block(kTile);
         const size_t lds = (size_t)g.max_local * sizeof(float4) * (DAMP ? 3 : 2);
-        if (forces)
-            hipLaunchKernelGGL((tiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, true, YIELD>), grid, block, lds, st, g,
-                               io, sc);
-        else
-            hipLaunchKernelGGL((tiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, false, YIELD>), grid, block, lds, st, g,
-                               io, sc);
+        hipLaunchKernelGGL((tiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, MODE, YIELD>), grid, block, lds, st, g,
+                           io, sc);
     } else {
         const dim3 grid((unsigned)((g.n + 255) / 256)), block(256);
-        if (forces)
-            hipLaunchKernelGGL((untiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, true, YIELD>), grid, block, 0, st, g,
-                               io, sc);
-        else
-            hipLaunchKernelGGL((untiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, false, YIELD>), grid, block, 0, st, g,
-                               io, sc);
+        hipLaunchKernelGGL((untiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, MODE, YIELD>), grid, block, 0, st, g,
+                           io, sc);
     }
+}
+
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool YIELD = false>
+hipError_t launch4(const GatherGraph &g, const StateIO &io, const StepConsts &sc, int mode, bool tiled,
+                   hipStream_t st)
+{
+    if (mode == kModeForces)
+        launch_mode<ACT, WAVE, DAMP, DAMPV, REST, YIELD, kModeForces>(g, io, sc, tiled, st);
+    else if (mode == kModeStage)
+        launch_mode<ACT, WAVE, DAMP, DAMPV, REST, YIELD, kModeStage>(g, io, sc, tiled, st);
+    else
+        launch_mode<ACT, WAVE, DAMP, DAMPV, REST, YIELD, kModeStep>(g, io, sc, tiled, st);
     return hipGetLastError();
+}
+
+__global__ void verlet_drift_kernel(const float4 *U, const float4 *V, const float4 *A, float4 *Uo, float4 *Vo,
+                                    int64_t n, float dt)
+{
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const float4 u = U[i], v = V[i], a = A[i];
+    if (u.w == 0.f) {  // pinned
+        Uo[i] = u;
+        Vo[i] = v;
+        return;
+    }
+    const float half = 0.5f * dt;
+    const float4 vh = make_float4(fmaf(half, a.x, v.x), fmaf(half, a.y, v.y), fmaf(half, a.z, v.z), 0.f);
+    Uo[i] = make_float4(fmaf(dt, vh.x, u.x), fmaf(dt, vh.y, u.y), fmaf(dt, vh.z, u.z), u.w);
+    Vo[i] = vh;
 }
 
 __global__ void trig_table_kernel(float2 *trig, int64_t first, int count, double omega, double dt)
@@ -249,8 +285,8 @@ hipError_t launch_trig_table(float2 *trig, int64_t first, int count, double omeg
     return hipGetLastError();
 }
 
-hipError_t launch_gather_step(const GatherGraph &g, const StateIO &io, const StepConsts &sc, bool forces_only,
-                              bool tiled, hipStream_t stream)
+static hipError_t dispatch_mode(const GatherGraph &g, const StateIO &io, const StepConsts &sc, int mode, bool tiled,
+                                hipStream_t stream)
 {
     if (g.n == 0)
         return hipSuccess;
@@ -266,29 +302,51 @@ hipError_t launch_gather_step(const GatherGraph &g, const StateIO &io, const Ste
     const int key = (act ? 8 : 0) | (damp ? 4 : 0) | (dampv ? 2 : 0) | (rest ? 1 : 0) | (wave ? 16 : 0) |
                     (yield ? 32 : 0);
     switch (key) {
-    case 0: return launch4<false, false, false, false, false>(g, io, sc, forces_only, tiled, stream);
-    case 1: return launch4<false, false, false, false, true>(g, io, sc, forces_only, tiled, stream);
-    case 4: return launch4<false, false, true, false, false>(g, io, sc, forces_only, tiled, stream);
-    case 5: return launch4<false, false, true, false, true>(g, io, sc, forces_only, tiled, stream);
-    case 6: return launch4<false, false, true, true, false>(g, io, sc, forces_only, tiled, stream);
-    case 7: return launch4<false, false, true, true, true>(g, io, sc, forces_only, tiled, stream);
-    case 8: return launch4<true, false, false, false, false>(g, io, sc, forces_only, tiled, stream);
-    case 9: return launch4<true, false, false, false, true>(g, io, sc, forces_only, tiled, stream);
-    case 12: return launch4<true, false, true, false, false>(g, io, sc, forces_only, tiled, stream);
-    case 13: return launch4<true, false, true, false, true>(g, io, sc, forces_only, tiled, stream);
-    case 14: return launch4<true, false, true, true, false>(g, io, sc, forces_only, tiled, stream);
-    case 15: return launch4<true, false, true, true, true>(g, io, sc, forces_only, tiled, stream);
-    case 24: return launch4<true, true, false, false, false>(g, io, sc, forces_only, tiled, stream);
-    case 25: return launch4<true, true, false, false, true>(g, io, sc, forces_only, tiled, stream);
-    case 28: return launch4<true, true, true, false, false>(g, io, sc, forces_only, tiled, stream);
-    case 29: return launch4<true, true, true, false, true>(g, io, sc, forces_only, tiled, stream);
-    case 30: return launch4<true, true, true, true, false>(g, io, sc, forces_only, tiled, stream);
-    case 31: return launch4<true, true, true, true, true>(g, io, sc, forces_only, tiled, stream);
-    case 39: return launch4<false, false, true, true, true, true>(g, io, sc, forces_only, tiled, stream);
-    case 47: return launch4<true, false, true, true, true, true>(g, io, sc, forces_only, tiled, stream);
-    case 63: return launch4<true, true, true, true, true, true>(g, io, sc, forces_only, tiled, stream);
+    case 0: return launch4<false, false, false, false, false>(g, io, sc, mode, tiled, stream);
+    case 1: return launch4<false, false, false, false, true>(g, io, sc, mode, tiled, stream);
+    case 4: return launch4<false, false, true, false, false>(g, io, sc, mode, tiled, stream);
+    case 5: return launch4<false, false, true, false, true>(g, io, sc, mode, tiled, stream);
+    case 6: return launch4<false, false, true, true, false>(g, io, sc, mode, tiled, stream);
+    case 7: return launch4<false, false, true, true, true>(g, io, sc, mode, tiled, stream);
+    case 8: return launch4<true, false, false, false, false>(g, io, sc, mode, tiled, stream);
+    case 9: return launch4<true, false, false, false, true>(g, io, sc, mode, tiled, stream);
+    case 12: return launch4<true, false, true, false, false>(g, io, sc, mode, tiled, stream);
+    case 13: return launch4<true, false, true, false, true>(g, io, sc, mode, tiled, stream);
+    case 14: return launch4<true, false, true, true, false>(g, io, sc, mode, tiled, stream);
+    case 15: return launch4<true, false, true, true, true>(g, io, sc, mode, tiled, stream);
+    case 24: return launch4<true, true, false, false, false>(g, io, sc, mode, tiled, stream);
+    case 25: return launch4<true, true, false, false, true>(g, io, sc, mode, tiled, stream);
+    case 28: return launch4<true, true, true, false, false>(g, io, sc, mode, tiled, stream);
+    case 29: return launch4<true, true, true, false, true>(g, io, sc, mode, tiled, stream);
+    case 30: return launch4<true, true, true, true, false>(g, io, sc, mode, tiled, stream);
+    case 31: return launch4<true, true, true, true, true>(g, io, sc, mode, tiled, stream);
+    case 39: return launch4<false, false, true, true, true, true>(g, io, sc, mode, tiled, stream);
+    case 47: return launch4<true, false, true, true, true, true>(g, io, sc, mode, tiled, stream);
+    case 63: return launch4<true, true, true, true, true, true>(g, io, sc, mode, tiled, stream);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_gather_step(const GatherGraph &g, const StateIO &io, const StepConsts &sc, bool forces_only,
+                              bool tiled, hipStream_t stream)
+{
+    return dispatch_mode(g, io, sc, forces_only ? kModeForces : kModeStep, tiled, stream);
+}
+
+hipError_t launch_gather_stage(const GatherGraph &g, const StateIO &io, const StepConsts &sc, bool tiled,
+                               hipStream_t stream)
+{
+    return dispatch_mode(g, io, sc, kModeStage, tiled, stream);
+}
+
+hipError_t launch_verlet_drift(const float4 *U, const float4 *V, const float4 *A, float4 *Uo, float4 *Vo, int64_t n,
+                               float dt, hipStream_t stream)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(verlet_drift_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, U, V, A, Uo, Vo,
+                       n, dt);
+    return hipGetLastError();
 }
 
 }  // namespace titan

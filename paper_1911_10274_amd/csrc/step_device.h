@@ -166,6 +166,115 @@ __device__ __forceinline__ bool integrate_mass(const float4 &xi, const float4 &u
     return isfinite(uo.x) && isfinite(uo.y) && isfinite(uo.z) && isfinite(wx) && isfinite(wy) && isfinite(wz);
 }
 
+// ---- staged integrators (velocity Verlet, RK4; Sec. III-B) ----------------
+// They integrate the smooth forces -- springs with their dampers, gravity and
+// the ground's normal force at the evaluated position -- and apply Coulomb
+// friction once per step afterwards, as the Euler step does: normal force
+// from the step's starting height, tangential velocity scaled by
+// max(0, 1 - mu F_n dt / (m |v_t|)), the position moved by the velocity
+// change times dt.  Pinned masses keep position and velocity.
+
+// a = f / m + g (+ -k_g z / m while z < 0); 0 for a pinned mass.
+__device__ __forceinline__ float3 smooth_accel(const float4 &xi, const float4 &ui, float fx, float fy, float fz,
+                                               const StepConsts &sc)
+{
+#pragma clang fp contract(off)
+    const float im = ui.w;
+    if (im == 0.f)
+        return make_float3(0.f, 0.f, 0.f);
+    float az = fmaf(fz, im, sc.gz);
+    const float z = xi.z + ui.z;
+    if (sc.ground && z < 0.f)
+        az = fmaf(-sc.ground_k * z, im, az);
+    return make_float3(fmaf(fx, im, sc.gx), fmaf(fy, im, sc.gy), az);
+}
+
+// Friction after a smooth update of (u, v); zb: the step's starting height.
+__device__ __forceinline__ void friction_after(float zb, float im, const StepConsts &sc, float4 &u, float4 &v)
+{
+#pragma clang fp contract(off)
+    if (im == 0.f || !(sc.ground && zb < 0.f))
+        return;
+    const float fn = -sc.ground_k * zb;
+    const float vt = sqrtf(fmaf(v.x, v.x, v.y * v.y));
+    if (!(vt > 0.f))
+        return;
+    const float s = fmaxf(0.f, 1.f - sc.mu * fn * sc.dt * im / vt);
+    const float wx = v.x * s, wy = v.y * s;
+    u.x = fmaf(wx - v.x, sc.dt, u.x);
+    u.y = fmaf(wy - v.y, sc.dt, u.y);
+    v.x = wx;
+    v.y = wy;
+}
+
+__device__ __forceinline__ bool finite4(const float4 &u, const float4 &v)
+{
+    return isfinite(u.x) && isfinite(u.y) && isfinite(u.z) && isfinite(v.x) && isfinite(v.y) && isfinite(v.z);
+}
+
+// The epilogue of one stage for mass i: (xi, ui, vi) is the stage state the
+// force (fx, fy, fz) was evaluated at.  Returns false if a new state is not
+// finite.
+__device__ __forceinline__ bool stage_update(int64_t i, const float4 &xi, const float4 &ui, const float4 &vi,
+                                             float fx, float fy, float fz, const StateIO &io, const StepConsts &sc)
+{
+#pragma clang fp contract(off)
+    const float3 a = smooth_accel(xi, ui, fx, fy, fz, sc);
+    const float im = ui.w;
+    const float dt = sc.dt, half = 0.5f * sc.dt;
+    if (sc.stage == kStageVerletInit) {
+        io.A[i] = make_float4(a.x, a.y, a.z, 0.f);
+        return true;
+    }
+    if (sc.stage == kStageVerletKick) {
+        // (ui, vi) = (x', v'); the step started at U_base (same buffer as U_out)
+        const float zb = xi.z + io.U_base[i].z;
+        float4 u = ui, v = vi;
+        if (im != 0.f) {
+            v = make_float4(fmaf(half, a.x, vi.x), fmaf(half, a.y, vi.y), fmaf(half, a.z, vi.z), 0.f);
+            friction_after(zb, im, sc, u, v);
+        }
+        io.U_out[i] = u;
+        io.V_out[i] = v;
+        io.A[i] = make_float4(a.x, a.y, a.z, 0.f);
+        return finite4(u, v);
+    }
+    // RK4: sums of w_s v_s and w_s a_s, w = 1, 2, 2, 1 (times dt / 6)
+    const float4 ub = io.U_base[i], vb = io.V_base[i];
+    if (im == 0.f) {
+        io.U_out[i] = ub;
+        io.V_out[i] = vb;
+        return true;
+    }
+    float4 su, sv;
+    if (sc.stage == kStageRk1) {
+        su = make_float4(vi.x, vi.y, vi.z, 0.f);
+        sv = make_float4(a.x, a.y, a.z, 0.f);
+    } else {
+        const float w = sc.stage == kStageRk4 ? 1.f : 2.f;
+        su = io.sum_u[i];
+        sv = io.sum_v[i];
+        su = make_float4(fmaf(w, vi.x, su.x), fmaf(w, vi.y, su.y), fmaf(w, vi.z, su.z), 0.f);
+        sv = make_float4(fmaf(w, a.x, sv.x), fmaf(w, a.y, sv.y), fmaf(w, a.z, sv.z), 0.f);
+    }
+    if (sc.stage != kStageRk4) {
+        io.sum_u[i] = su;
+        io.sum_v[i] = sv;
+        // next stage state: base + c dt (v_s, a_s), c = 1/2, 1/2, 1
+        const float c = sc.stage == kStageRk1 + 2 ? dt : half;
+        io.U_out[i] = make_float4(fmaf(c, vi.x, ub.x), fmaf(c, vi.y, ub.y), fmaf(c, vi.z, ub.z), im);
+        io.V_out[i] = make_float4(fmaf(c, a.x, vb.x), fmaf(c, a.y, vb.y), fmaf(c, a.z, vb.z), 0.f);
+        return true;
+    }
+    const float h6 = sc.dt / 6.f;
+    float4 u = make_float4(fmaf(h6, su.x, ub.x), fmaf(h6, su.y, ub.y), fmaf(h6, su.z, ub.z), im);
+    float4 v = make_float4(fmaf(h6, sv.x, vb.x), fmaf(h6, sv.y, vb.y), fmaf(h6, sv.z, vb.z), 0.f);
+    friction_after(xi.z + ub.z, im, sc, u, v);
+    io.U_out[i] = u;
+    io.V_out[i] = v;
+    return finite4(u, v);
+}
+
 // Spring constants are read once per step: optionally as non-temporal loads
 // so they do not displace the state arrays from the caches.
 template <class T>

@@ -163,6 +163,10 @@ static int check_params(const titan_params *p)
         return fail(TITAN_EINVAL, "unknown actuation %d", p->actuation);
     if (p->actuation == TITAN_ACT_WAVE && !(std::isfinite(p->wave_period) && p->wave_period > 0))
         return fail(TITAN_EINVAL, "wave_period must be finite and > 0 (got %g)", p->wave_period);
+    if (p->integrator < TITAN_INTEG_EULER || p->integrator > TITAN_INTEG_RK4)
+        return fail(TITAN_EINVAL, "unknown integrator %d", p->integrator);
+    if (p->integrator != TITAN_INTEG_EULER && p->engine == TITAN_ENGINE_BATCHED)
+        return fail(TITAN_EINVAL, "the batched engine steps with the Euler integrator only");
     return TITAN_OK;
 }
 
@@ -272,6 +276,7 @@ extern "C" int titan_add_springs(titan_sim *s, int64_t n, const int64_t *ends, c
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
+    s->acc_valid = false;  // a carried Verlet acceleration is recomputed
     if (s->finalized && s->dev_error)
         return fail(TITAN_EDEVICE, "sim is in a failed device state");
     if (n < 0)
@@ -402,6 +407,7 @@ static int grow_state(titan_sim *s, float4 **buf, int64_t n_old, const std::vect
 static int add_masses_live(titan_sim *s, int64_t n, const float *pos, const float *vel, const float *mass,
                            const int32_t *body, int64_t *first_out)
 {
+    s->acc_valid = false;
     if (s->dev_error)
         return fail(TITAN_EDEVICE, "sim is in a failed device state");
     int32_t maxb = -1;
@@ -489,6 +495,7 @@ extern "C" int titan_remove_springs(titan_sim *s, int64_t n, const int64_t *spri
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
+    s->acc_valid = false;  // a carried Verlet acceleration is recomputed
     if (n < 0 || (n > 0 && !springs))
         return fail(TITAN_EINVAL, "bad spring list");
     if (s->dev_error)
@@ -506,6 +513,7 @@ extern "C" int titan_set_yield(titan_sim *s, int64_t first, int64_t count, const
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
+    s->acc_valid = false;  // a carried Verlet acceleration is recomputed
     const int64_t ns = (int64_t)s->h_k.size();
     if (first < 0 || count < 0 || first > ns || count > ns - first || (count > 0 && !yield))
         return fail(TITAN_EINVAL, "bad spring range [%lld, +%lld) of %lld", (long long)first, (long long)count,
@@ -557,6 +565,7 @@ extern "C" int titan_remove_masses(titan_sim *s, int64_t n, const int64_t *masse
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
+    s->acc_valid = false;  // a carried Verlet acceleration is recomputed
     if (n < 0 || (n > 0 && !masses))
         return fail(TITAN_EINVAL, "bad mass list");
     if (s->dev_error)
@@ -601,8 +610,17 @@ extern "C" int titan_set_params(titan_sim *s, const titan_params *p)
     if (s->finalized && p->actuation != s->params.actuation)
         return fail(TITAN_ESTATE, "the actuation law can only be chosen before the first step");
     const int32_t engine = s->finalized ? s->params.engine : p->engine;
+    if (s->finalized && engine == TITAN_ENGINE_BATCHED && p->integrator != TITAN_INTEG_EULER)
+        return fail(TITAN_ESTATE, "the batched engine steps with the Euler integrator only");
     s->params = *p;
     s->params.engine = engine;
+    s->acc_valid = false;
+    if (s->finalized) {  // the plain engines run the other integrators
+        if (p->integrator != TITAN_INTEG_EULER && s->engine == TITAN_ENGINE_BATCHED)
+            s->engine = s->tiled ? TITAN_ENGINE_TILED : TITAN_ENGINE_GATHER;
+        else if (p->integrator == TITAN_INTEG_EULER && s->batch && s->batch_step)
+            s->engine = TITAN_ENGINE_BATCHED;
+    }
     return TITAN_OK;
 }
 
@@ -929,6 +947,7 @@ extern "C" int titan_set_state(titan_sim *s, int64_t first, int64_t count, const
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
+    s->acc_valid = false;  // a carried Verlet acceleration is recomputed
     if (int rc = ready(s))
         return rc;
     if (int rc = check_range(s, first, count))
@@ -976,6 +995,7 @@ extern "C" int titan_set_step(titan_sim *s, int64_t step)
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
+    s->acc_valid = false;  // a carried Verlet acceleration is recomputed
     if (step < 0)
         return fail(TITAN_EINVAL, "negative step index");
     if (int rc = ready(s))
@@ -1021,6 +1041,7 @@ extern "C" int titan_set_springs(titan_sim *s, int64_t first, int64_t count, con
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
+    s->acc_valid = false;  // a carried Verlet acceleration is recomputed
     if (first < 0 || count < 0 || first + count > (int64_t)s->h_k.size())
         return fail(TITAN_EINVAL, "spring range [%lld, %lld) outside [0, %lld)", (long long)first,
                     (long long)(first + count), (long long)s->h_k.size());
@@ -1130,6 +1151,8 @@ extern "C" int titan_rollout_grad(titan_sim *s, int64_t nsteps, int32_t checkpoi
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->params.actuation != TITAN_ACT_PHASOR)
         return fail(TITAN_ESTATE, "the rollout adjoint covers phasor actuation only");
+    if (s->params.integrator != TITAN_INTEG_EULER)
+        return fail(TITAN_ESTATE, "the rollout adjoint covers the Euler integrator only");
     if (!s->h_yield.empty())
         return fail(TITAN_ESTATE, "the rollout adjoint covers unbreakable springs only");
     if (int rc = ready(s))

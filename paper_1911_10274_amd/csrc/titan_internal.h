@@ -24,7 +24,16 @@ struct StepConsts {
     double dt64;         // dt in FP64: the wave law's clock t_n = n * dt64
     double period;       // wave law: period t_p
     double omega;        // wave law: angular frequency
+    double t_add;        // added to n * dt64 (an RK4 stage's time offset c * dt)
+    int32_t stage;       // integrator stage of a staged launch (kStage*)
 };
+
+// Stages of the other integrators (Sec. III-B names Verlet and RK4): one
+// gather launch each, selected by StepConsts::stage.
+constexpr int32_t kStageRk1 = 1;         // RK4 stages 1-3: sums, next stage state
+constexpr int32_t kStageRk4 = 4;         // RK4 stage 4: the new state (+ friction)
+constexpr int32_t kStageVerletKick = 5;  // a' at (x', v'), v'' = v' + a' dt/2 (+ friction)
+constexpr int32_t kStageVerletInit = 6;  // a at (x, v): the acceleration Verlet carries
 
 // Largest number of steps whose clock entries one table holds.
 constexpr int kTrigChunk = 4096;
@@ -86,7 +95,18 @@ struct StateIO {
     float4 *V_out;
     float4 *F_out;                   // forces-only mode: summed spring force
     unsigned long long *first_bad;   // min step index that produced a non-finite value
+    // staged integrators: the step's starting state (own mass only), the
+    // RK4 sums of weighted velocities / accelerations, Verlet's acceleration
+    const float4 *U_base;
+    const float4 *V_base;
+    float4 *sum_u;
+    float4 *sum_v;
+    float4 *A;
 };
+
+// Verlet drift: v' = v + a dt/2, x' = x + v' dt (pinned masses unchanged).
+hipError_t launch_verlet_drift(const float4 *U, const float4 *V, const float4 *A, float4 *Uo, float4 *Vo, int64_t n,
+                               float dt, hipStream_t stream);
 
 // dst[slot[q]] = val[q] for q < m; dst[q] = v for q < m.
 hipError_t launch_scatter(float *dst, const int64_t *slot, const float *val, int64_t m, hipStream_t stream);
@@ -145,5 +165,8 @@ hipError_t launch_body_loss(const float *dux, const float *coef, const int64_t *
 // neighbour is read from global memory.
 hipError_t launch_gather_step(const GatherGraph &g, const StateIO &io, const StepConsts &sc,
                               bool forces_only, bool tiled, hipStream_t stream);
+// Launch one integrator stage (sc.stage) over the state io.U_in / io.V_in.
+hipError_t launch_gather_stage(const GatherGraph &g, const StateIO &io, const StepConsts &sc, bool tiled,
+                               hipStream_t stream);
 
 }  // namespace titan

@@ -90,6 +90,12 @@ struct titan_sim {
     std::vector<int64_t> h_group_off;  // batched layout: group ranges (empty: none)
     std::vector<float> h_yield;    // per spring: yield value (+inf: never breaks); empty: none
     std::vector<uint8_t> h_broken; // per spring: broken (as of the last sync_broken)
+    // staged integrators: RK4 stage states (two ping-pong pairs) and sums,
+    // Verlet's carried acceleration; sized for stage_n masses
+    float4 *stage_buf[6] = {};
+    float4 *verlet_acc = nullptr;
+    int64_t stage_n = 0;
+    bool acc_valid = false;        // verlet_acc holds the current state's acceleration
     int64_t layout_builds = 0;     // times the layouts were built
     int64_t springs_in_place = 0;  // springs inserted into spare slots
 

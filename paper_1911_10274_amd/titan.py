@@ -32,6 +32,9 @@ ENGINE_BATCHED = 2
 ENGINE_TILED = 3
 ACT_PHASOR = 0
 ACT_WAVE = 1
+INTEG_EULER = 0
+INTEG_VERLET = 1
+INTEG_RK4 = 2
 
 _ERR_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE", ENONFINITE: "ENONFINITE"}
 
@@ -53,6 +56,7 @@ class _Params(ctypes.Structure):
         ("omega", ctypes.c_double),
         ("actuation", ctypes.c_int32),
         ("wave_period", ctypes.c_double),
+        ("integrator", ctypes.c_int32),
     ]
 
 
@@ -183,6 +187,7 @@ class Params:
     engine: int = ENGINE_AUTO
     actuation: int = ACT_PHASOR
     wave_period: float = 1.0
+    integrator: int = INTEG_EULER
 
     def _c(self) -> _Params:
         p = _Params()
@@ -195,6 +200,7 @@ class Params:
         p.omega = self.omega
         p.actuation = int(self.actuation)
         p.wave_period = self.wave_period
+        p.integrator = int(self.integrator)
         return p
 
 

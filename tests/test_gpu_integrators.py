@@ -1,0 +1,161 @@
+"""Velocity Verlet and RK4 (Sec. III-B names both beside Euler) on the GPU
+against the FP64 oracle, through the C ABI.
+
+Full 10-step trajectories from the start, where both sides begin without a
+carried acceleration; windows later in a run are compared one step at a time
+from the GPU's own state (Verlet then restarts its acceleration on both
+sides: titan_set_state on the GPU, acc = None in the oracle)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1911_10274_amd import scenes
+from tests.parity import TOL, compare_series, gpu_series, rel
+
+pytestmark = pytest.mark.gpu
+
+DT = 5e-5
+OMEGA = 2 * math.pi * 2
+NAMES = {"verlet": 1, "rk4": 2}
+
+
+def _T():
+    from paper_1911_10274_amd import titan as T
+
+    return T
+
+
+def _params(integ, engine, dt=DT, omega=OMEGA, **kw):
+    T = _T()
+    return T.Params(dt=dt, gravity=(0.0, 0.0, -9.81), ground=True, ground_k=1e5, friction_mu=0.5, omega=omega,
+                    engine=engine, integrator=NAMES[integ], **kw)
+
+
+def _oparams(integ, dt=DT, omega=OMEGA, **kw):
+    return O.Params(dt=dt, gravity=(0.0, 0.0, -9.81), ground=True, ground_k=1e5, mu=0.5, omega=omega,
+                    integrator=integ, **kw)
+
+
+@pytest.mark.parametrize("integ", ["verlet", "rk4"])
+@pytest.mark.parametrize("engine", ["gather", "tiled"])
+def test_first_10_steps_match_the_oracle(integ, engine):
+    T = _T()
+    eng = T.ENGINE_GATHER if engine == "gather" else T.ENGINE_TILED
+    sc = scenes.jittered_actuated_lattice(n=10, seed=3)
+    sim = T.sim_from_scene(sc, _params(integ, eng))
+    gpu = gpu_series(sim, 10)
+    assert sim.info()["engine"] == eng
+    sim.close()
+    sysm = O.System(sc)
+    err = compare_series(gpu, sysm.trajectory(_oparams(integ), 10), sysm.mass)
+    print(integ, engine, err)
+    assert max(err.values()) <= TOL
+
+
+@pytest.mark.parametrize("integ", ["verlet", "rk4"])
+def test_contact_and_friction_window_step_by_step(integ):
+    """A cube sliding onto the ground (contact from step ~143): each step of
+    steps 130-170 from the GPU's state, the velocity change and position
+    change against one oracle step (each stored FP32 component allowed its
+    rounding first)."""
+    T = _T()
+    sc = scenes.contact_slide()
+    dt = 1e-4
+    sim = T.sim_from_scene(sc, _params(integ, T.ENGINE_TILED, dt=dt, omega=0.0))
+    sysm = O.System(sc)
+    sim.step(130)
+    worst = {"dV": 0.0, "dX": 0.0}
+    contact = 0
+    for n in range(130, 170):
+        p, v, step = sim.get_state(displacement=True)
+        assert step == n
+        sim.set_state(p, v, displacement=True)  # Verlet: both sides start afresh
+        x = sysm.x0 + p.astype(np.float64)
+        v = v.astype(np.float64)
+        contact += int((x[:, 2] < 0).sum())
+        sim.step(1)
+        p2, v2, _ = sim.get_state(displacement=True)
+        sysm.acc = None
+        x1, v1, _ = sysm.run(_oparams(integ, dt=dt, omega=0.0), x, v, n, 1)
+        for key, got, ref, stored in (("dV", v2 - v, v1 - v, v2), ("dX", (sysm.x0 + p2) - x, x1 - x, p2)):
+            d = got - ref
+            d = np.sign(d) * np.maximum(np.abs(d) - np.spacing(np.abs(stored)).astype(np.float64), 0.0)
+            worst[key] = max(worst[key], float(np.linalg.norm(d) / np.linalg.norm(ref)))
+    sim.close()
+    print(integ, "contact window", worst, "contacts", contact)
+    assert contact > 0
+    assert max(worst.values()) <= TOL
+
+
+@pytest.mark.parametrize("integ", ["verlet", "rk4"])
+def test_worm_wave_law(integ):
+    T = _T()
+    sc = scenes.worm()
+    tp = _params(integ, T.ENGINE_TILED, dt=1e-4, omega=20.0, actuation=T.ACT_WAVE, wave_period=1.0)
+    sim = T.sim_from_scene(sc, tp)
+    gpu = gpu_series(sim, 10)
+    sim.close()
+    sysm = O.System(dict(sc, phase=O.wave_offsets(sc["pos"], sc["ends"], sc.get("body"))))
+    op = _oparams(integ, dt=1e-4, omega=20.0, wave=True, period=1.0)
+    err = compare_series(gpu, sysm.trajectory(op, 10), sysm.mass)
+    print(integ, "worm", err)
+    assert max(err.values()) <= TOL
+
+
+@pytest.mark.parametrize("integ", ["verlet", "rk4"])
+def test_engines_agree_bitwise(integ):
+    T = _T()
+    sc = scenes.jittered_actuated_lattice(n=11, seed=5)
+    sc = dict(sc, **{"yield": np.full(sc["ends"].shape[0], 150.0, np.float32)})
+    outs = []
+    for eng in (T.ENGINE_GATHER, T.ENGINE_TILED):
+        sim = T.sim_from_scene(sc, _params(integ, eng))
+        sim.step(120)
+        sim.remove_springs([5, 77, 901])  # Verlet restarts its acceleration here
+        sim.step(180)
+        outs.append(sim.get_state(displacement=True)[:2] + (sim.get_forces(), sim.get_broken()))
+        sim.close()
+    assert outs[0][3].any()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
+def test_verlet_restart_only_when_something_changed():
+    T = _T()
+    sc = scenes.jittered_actuated_lattice(n=8, seed=1)
+    runs = []
+    for cut in (False, True):
+        sim = T.sim_from_scene(sc, _params("verlet", T.ENGINE_TILED))
+        sim.step(30)
+        if cut:
+            sim.step(0)
+            p, v, _ = sim.get_state(displacement=True)
+            sim.get_forces()
+        sim.step(30)
+        runs.append(sim.get_state(displacement=True))
+        sim.close()
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+
+
+def test_integrator_rules():
+    T = _T()
+    sc = scenes.lattice(4, origin=(0.0, 0.0, 0.5))
+    with pytest.raises(T.TitanError) as ei:
+        T.sim_from_scene(sc, _params("rk4", T.ENGINE_BATCHED))
+    assert ei.value.code == T.EINVAL
+    sim = T.sim_from_scene(sc, _params("rk4", T.ENGINE_AUTO))
+    sim.step(3)
+    assert sim.info()["engine"] != T.ENGINE_BATCHED
+    with pytest.raises(T.TitanError) as ei:
+        sim.rollout_grad(4, 2)
+    assert ei.value.code == T.ESTATE
+    # back to Euler mid-run, then Verlet: the state carries over
+    sim.set_params(T.Params(dt=DT, omega=OMEGA, engine=T.ENGINE_AUTO, integrator=T.INTEG_EULER))
+    sim.step(3)
+    sim.set_params(_params("verlet", T.ENGINE_AUTO))
+    sim.step(3)
+    p, v, s = sim.get_state()
+    assert s == 9 and np.isfinite(p).all() and np.isfinite(v).all()
+    sim.close()
