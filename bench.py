@@ -301,6 +301,30 @@ def bench_surrogate(T, batch: int = 1024, steps: int = 60, gemm_n: int = 8192):
                      "frac_of_bf16_peak": gflops / 2.5e15}}
 
 
+def bench_integrators(T, scene, steps: int = 1000):
+    """Velocity Verlet and RK4 (Sec. III-B) on the benchmark lattice, tiled
+    engine: time per step against the Euler step's.  A Verlet step is one
+    force evaluation plus a drift pass over the masses; an RK4 step is four
+    force evaluations."""
+    import torch
+
+    ns = scene["ends"].shape[0]
+    out = {"workload": f"the same lattice ({ns} springs), tiled engine, {steps} steps each"}
+    for name, integ, evals in (("verlet", T.INTEG_VERLET, 1), ("rk4", T.INTEG_RK4, 4)):
+        tp = T.Params(dt=PARAMS["dt"], gravity=PARAMS["gravity"], ground=PARAMS["ground"],
+                      ground_k=PARAMS["ground_k"], friction_mu=PARAMS["mu"], omega=PARAMS["omega"],
+                      engine=T.ENGINE_TILED, integrator=integ)
+        sim = T.sim_from_scene(scene, tp)
+        sim.finalize()
+        sim.step(20)
+        sim.sync()
+        ms = _timed_steps(sim, steps, torch.cuda.current_stream())
+        sim.close()
+        out[name] = {"ms_per_step": ms / steps, "steps_per_s": steps / (ms * 1e-3),
+                     "spring_evaluations_per_s": evals * ns * steps / (ms * 1e-3)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,6 +342,8 @@ def main():
     ap.add_argument("--robot-steps", type=int, default=2000)
     ap.add_argument("--loop-sample", type=int, default=32)
     ap.add_argument("--adjoint-robots", type=int, default=256, help="robots in the adjoint workload (0: skip)")
+    ap.add_argument("--integrator-steps", type=int, default=1000,
+                    help="steps of Verlet and of RK4 on the lattice (0: skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -399,6 +425,9 @@ def main():
         "cpu_baseline": cpu,
     }
     sim.close()
+    if args.integrator_steps > 0:
+        out["integrators"] = bench_integrators(T, scene, args.integrator_steps)
+        out["integrators"]["euler_ms_per_step"] = ms_per_step
     if args.robots > 0:
         out["batched"] = bench_batched(T, args.robots, args.robot_steps, args.loop_sample)
     if args.adjoint_robots > 0:
