@@ -310,20 +310,24 @@ hipError_t launch_tm(const GatherGraph &g, const BatchLayout &b, const AdjointIO
     return hipGetLastError();
 }
 
+// One mass per thread while a group fits 1024 threads: the reverse step is
+// a chain of LDS reads and workgroup barriers, so the more waves a CU holds
+// the more of that latency is hidden (85 VGPRs at one mass per thread, 143
+// at four; 1024 threads allow 128).  Groups up to 2048 masses take two masses
+// per thread (104 VGPRs).
 template <bool ACT, bool DAMP, bool DAMPV, bool REST>
 hipError_t launch4(const GatherGraph &g, const BatchLayout &b, const AdjointIO &a, const StepConsts &sc,
                    hipStream_t st)
 {
-    constexpr int T = 256;
-    const int per = (b.max_group + T - 1) / T;
-    if (per <= 1)
-        return launch_tm<ACT, DAMP, DAMPV, REST, T, 1>(g, b, a, sc, st);
-    if (per <= 2)
-        return launch_tm<ACT, DAMP, DAMPV, REST, T, 2>(g, b, a, sc, st);
-    if (per <= 4)
-        return launch_tm<ACT, DAMP, DAMPV, REST, T, 4>(g, b, a, sc, st);
-    if (per <= 8)
-        return launch_tm<ACT, DAMP, DAMPV, REST, T, 8>(g, b, a, sc, st);
+    const int m = b.max_group;
+    if (m <= 256)
+        return launch_tm<ACT, DAMP, DAMPV, REST, 256, 1>(g, b, a, sc, st);
+    if (m <= 512)
+        return launch_tm<ACT, DAMP, DAMPV, REST, 512, 1>(g, b, a, sc, st);
+    if (m <= 1024)
+        return launch_tm<ACT, DAMP, DAMPV, REST, 1024, 1>(g, b, a, sc, st);
+    if (m <= 2048)
+        return launch_tm<ACT, DAMP, DAMPV, REST, 1024, 2>(g, b, a, sc, st);
     return hipErrorInvalidValue;
 }
 
