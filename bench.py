@@ -284,21 +284,24 @@ def bench_surrogate(T, batch: int = 1024, steps: int = 60, gemm_n: int = 8192):
     # bf16 bit patterns of magnitude below 1 (sign and top exponent bit clear)
     A = torch.randint(-2**15, 2**15, (gemm_n, gemm_n), dtype=torch.int16, device="cuda") & 0x3F7F
     B = torch.randint(-2**15, 2**15, (gemm_n, gemm_n), dtype=torch.int16, device="cuda") & 0x3F7F
-    T.gemm_bf16(A, B)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 5
-    ev0.record()
-    for _ in range(reps):
-        T.gemm_bf16(A, B)
-    ev1.record()
-    torch.cuda.synchronize()
-    gms = ev0.elapsed_time(ev1) / reps
-    gflops = 2.0 * gemm_n ** 3 / (gms * 1e-3)
+    gemm = {"shape": [gemm_n, gemm_n, gemm_n]}
+    # NN: both operands row-major; NT: B given as its transpose (K contiguous
+    # in both operands), the layout of the network's forward product x W^T
+    for name, tb in (("nn", False), ("nt", True)):
+        T.gemm_bf16(A, B, tb=tb)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        ev0.record()
+        for _ in range(reps):
+            T.gemm_bf16(A, B, tb=tb)
+        ev1.record()
+        torch.cuda.synchronize()
+        gms = ev0.elapsed_time(ev1) / reps
+        gflops = 2.0 * gemm_n ** 3 / (gms * 1e-3)
+        gemm[name] = {"ms": gms, "tflops": gflops / 1e12, "frac_of_bf16_peak": gflops / 2.5e15}
     return {"workload": f"surrogate MLP 1536-512x4-3 (1,576,451 parameters), batch {batch}, {steps} Adam steps",
-            "train_ms_per_step": sec * 1e3 / steps, "train_tflops": train_flops / sec / 1e12,
-            "gemm": {"shape": [gemm_n, gemm_n, gemm_n], "ms": gms, "tflops": gflops / 1e12,
-                     "frac_of_bf16_peak": gflops / 2.5e15}}
+            "train_ms_per_step": sec * 1e3 / steps, "train_tflops": train_flops / sec / 1e12, "gemm": gemm}
 
 
 def bench_integrators(T, scene, steps: int = 1000):

@@ -205,6 +205,192 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, GemmEpi ep)
     }
 }
 
+// ---- large outputs: big workgroup tiles --------------------------------------
+// WM x WN waves, each computing (MI x 32) x (NJ x 32) as MI x NJ MFMA 32x32x16
+// tiles: per 16 K-values a wave reads MI + NJ fragments from LDS for MI * NJ
+// MFMAs (the 64 x 64 kernel reads two for one).  Operands whose K is not
+// contiguous in memory are loaded as 8 (K) x 4 (rows) blocks of 8-byte
+// pieces, transposed in registers and stored as 16-byte LDS writes.
+#ifndef TITAN_GEMM_BIG
+#define TITAN_GEMM_BIG 2
+#endif
+// Tile shapes (compile-time choice for tuning builds; 8192^3 in TFLOP/s for
+// the NN / NT / TN layouts on MI355X: 256 x 256 683 / 987 / 609, 256 x 128
+// 705 / 750 / 355, 128 x 128 608 / 833 / 490).
+#if TITAN_GEMM_BIG == 1
+constexpr int GWM = 2, GWN = 2, GMI = 4, GNJ = 2;  // 256 x 128, 4 waves of 128 x 64
+#elif TITAN_GEMM_BIG == 2
+constexpr int GWM = 2, GWN = 4, GMI = 4, GNJ = 2;  // 256 x 256, 8 waves of 128 x 64
+#else
+constexpr int GWM = 2, GWN = 2, GMI = 2, GNJ = 2;  // 128 x 128, 4 waves of 64 x 64
+#endif
+// (One LDS buffer per operand: double-buffering, one barrier per K step
+// instead of two, measured no faster -- LDS reads per MFMA set the pace.)
+constexpr int GBM = GWM * GMI * 32, GBN = GWN * GNJ * 32, GT = GWM * GWN * 64;
+
+template <bool KCONTIG, int ROWS>
+struct TileMoveBig {
+    static constexpr int CH = ROWS * (BK / 8) / GT;  // 16-byte chunks per thread (K contiguous)
+    static constexpr int BL = 2 * ROWS / GT;         // 8 x 4 blocks per thread (K strided)
+    static_assert(CH * GT == ROWS * (BK / 8) && BL * GT == 2 * ROWS, "tile must split evenly over the threads");
+    uint4 v[KCONTIG ? CH : 4 * BL];
+
+    __device__ __forceinline__ void load(const uint16_t *P, int ld, int r0, int R, int k0, int kend, bool vec,
+                                         int tid)
+    {
+        if (KCONTIG) {
+            // element (r, k) at P[r * ld + k]: 16-byte chunks of 8 K-values,
+            // chunk c = row c / 8, K offset (c % 8) * 8
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                const int c = tid + GT * q;
+                const int row = r0 + (c >> 3), k = k0 + (c & 7) * 8;
+                if (vec && row < R && k + 8 <= kend) {
+                    v[q] = *(const uint4 *)(P + (int64_t)row * ld + k);
+                } else {
+                    uint32_t w[4];
+#pragma unroll
+                    for (int e = 0; e < 8; e += 2) {
+                        const uint32_t x0 = (row < R && k + e < kend) ? P[(int64_t)row * ld + k + e] : 0u;
+                        const uint32_t x1 = (row < R && k + e + 1 < kend) ? P[(int64_t)row * ld + k + e + 1] : 0u;
+                        w[e / 2] = x0 | x1 << 16;
+                    }
+                    v[q] = make_uint4(w[0], w[1], w[2], w[3]);
+                }
+            }
+        } else {
+            // element (r, k) at P[k * ld + r]: block b = K k0 + 8 (b / (ROWS/4))
+            // .. +8, rows r0 + 4 (b % (ROWS/4)) .. +4 (consecutive threads read
+            // consecutive 8-byte pieces of a K row), transposed in registers
+#pragma unroll
+            for (int q = 0; q < BL; ++q) {
+                const int blk = tid + GT * q;
+                const int kb = k0 + 8 * (blk / (ROWS / 4)), rb = r0 + 4 * (blk % (ROWS / 4));
+                uint2 in[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int k = kb + e;
+                    if (vec && k < kend && rb + 4 <= R) {
+                        in[e] = *(const uint2 *)(P + (int64_t)k * ld + rb);
+                    } else {
+                        uint32_t h[4];
+#pragma unroll
+                        for (int n = 0; n < 4; ++n)
+                            h[n] = (k < kend && rb + n < R) ? P[(int64_t)k * ld + rb + n] : 0u;
+                        in[e] = make_uint2(h[0] | h[1] << 16, h[2] | h[3] << 16);
+                    }
+                }
+                // v[4q + n] = the 8 K-values of row rb + n
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+                    uint32_t w[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const uint32_t a = (n < 2) ? in[2 * j].x : in[2 * j].y;
+                        const uint32_t b = (n < 2) ? in[2 * j + 1].x : in[2 * j + 1].y;
+                        w[j] = (n & 1) ? ((a >> 16) | (b & 0xFFFF0000u)) : ((a & 0xFFFFu) | (b << 16));
+                    }
+                    v[4 * q + n] = make_uint4(w[0], w[1], w[2], w[3]);
+                }
+            }
+        }
+    }
+
+    __device__ __forceinline__ void store(uint16_t *S, int tid) const
+    {
+        if (KCONTIG) {
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                const int c = tid + GT * q;
+                *(uint4 *)&S[(c >> 3) * LDK + (c & 7) * 8] = v[q];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < BL; ++q) {
+                const int blk = tid + GT * q;
+                const int kb = 8 * (blk / (ROWS / 4)), rb = 4 * (blk % (ROWS / 4));
+#pragma unroll
+                for (int n = 0; n < 4; ++n)
+                    *(uint4 *)&S[(rb + n) * LDK + kb] = v[4 * q + n];
+            }
+        }
+    }
+};
+
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(GT) void gemm_big_kernel(GemmArgs g, GemmEpi ep)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t sA[GBM * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[GBN * LDK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+    const int wm = wave / GWN, wn = wave % GWN;
+    const int K = g.K;
+    // vector loads: 16 bytes along K, or 8 bytes along the rows
+    const bool va = TA ? (g.lda % 4 == 0 && ((uintptr_t)g.A & 7) == 0) : (g.lda % 8 == 0 && ((uintptr_t)g.A & 15) == 0);
+    const bool vb = TB ? (g.ldb % 8 == 0 && ((uintptr_t)g.B & 15) == 0) : (g.ldb % 4 == 0 && ((uintptr_t)g.B & 7) == 0);
+    TileMoveBig<!TA, GBM> ta;
+    TileMoveBig<TB, GBN> tb;
+    f32x16_t acc[GMI][GNJ];
+#pragma unroll
+    for (int i = 0; i < GMI; ++i)
+#pragma unroll
+        for (int j = 0; j < GNJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                acc[i][j][r] = 0.f;
+    auto multiply = [&](const uint16_t *A_, const uint16_t *B_) {
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+            bf16x8_t a[GMI], b[GNJ];
+#pragma unroll
+            for (int i = 0; i < GMI; ++i)
+                a[i] = *(const bf16x8_t *)&A_[(wm * GMI * 32 + i * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5)];
+#pragma unroll
+            for (int j = 0; j < GNJ; ++j)
+                b[j] = *(const bf16x8_t *)&B_[(wn * GNJ * 32 + j * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5)];
+#pragma unroll
+            for (int i = 0; i < GMI; ++i)
+#pragma unroll
+                for (int j = 0; j < GNJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    };
+    if (K > 0) {
+        ta.load(g.A, g.lda, m0, g.M, 0, K, va, tid);
+        tb.load(g.B, g.ldb, n0, g.N, 0, K, vb, tid);
+    }
+    // the next K tile is loaded into registers while this one is multiplied
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        ta.store(sA, tid);
+        tb.store(sB, tid);
+        __syncthreads();
+        if (k0 + BK < K) {
+            ta.load(g.A, g.lda, m0, g.M, k0 + BK, K, va, tid);
+            tb.load(g.B, g.ldb, n0, g.N, k0 + BK, K, vb, tid);
+        }
+        multiply(sA, sB);
+        __syncthreads();
+    }
+
+    // D layout of the 32x32 MFMA: lane l holds column l % 32 and, for
+    // r = 0..15, row 8 (r / 4) + 4 (l / 32) + r % 4.
+#pragma unroll
+    for (int j = 0; j < GNJ; ++j) {
+        const int col = n0 + wn * GNJ * 32 + j * 32 + (lane & 31);
+        if (col >= g.N)
+            continue;
+#pragma unroll
+        for (int i = 0; i < GMI; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + wm * GMI * 32 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (row < g.M)
+                    epi_store<EPI>(row, col, acc[i][j][r], ep);
+            }
+    }
+}
+
 // Split-K: sum the partials of each output element in split order, then the
 // epilogue.
 template <int EPI>
@@ -230,6 +416,14 @@ hipError_t gemm(int M, int N, int K, const uint16_t *A, int lda, const uint16_t 
 {
     if (M <= 0 || N <= 0)
         return hipSuccess;
+    // large outputs (at least 128 big tiles): one pass of the big-tile kernel
+    const int big_tiles = ((N + GBN - 1) / GBN) * ((M + GBM - 1) / GBM);
+    if (big_tiles >= 128) {
+        GemmArgs g{M, N, K, A, lda, B, ldb, std::max(K, 1), nullptr};
+        const dim3 grid((unsigned)((N + GBN - 1) / GBN), (unsigned)((M + GBM - 1) / GBM), 1);
+        hipLaunchKernelGGL((gemm_big_kernel<TA, TB, EPI>), grid, dim3(GT), 0, st, g, ep);
+        return hipGetLastError();
+    }
     const int tiles = ((N + BN - 1) / BN) * ((M + BM - 1) / BM);
     const int kt = std::max(1, (K + BK - 1) / BK);
     int splits = 1;

@@ -21,7 +21,10 @@ def _bf16_bits(a):
 
 @pytest.mark.parametrize("ta", [0, 1])
 @pytest.mark.parametrize("tb", [0, 1])
-@pytest.mark.parametrize("shape", [(64, 64, 32), (100, 70, 48), (1, 3, 512), (257, 129, 1536)])
+# the last two take the 128 x 128 kernel (outputs of >= 128 such tiles), the
+# last one with ragged edges in M, N and K
+@pytest.mark.parametrize("shape", [(64, 64, 32), (100, 70, 48), (1, 3, 512), (257, 129, 1536), (1024, 2048, 96),
+                                   (1100, 1900, 200)])
 def test_gemm_bf16_layouts(ta, tb, shape):
     import torch
 
