@@ -405,8 +405,12 @@ __global__ void gemm_reduce_kernel(int M, int N, int splits, const float *part, 
     epi_store<EPI>((int)(q / N), (int)(q % N), v, ep);
 }
 
-// Workgroups a GEMM aims for before it splits K.
-constexpr int kGemmTarget = 768;
+// Workgroups a GEMM aims for before it splits K (a split costs a partial-sum
+// write and a reduce launch).
+#ifndef TITAN_GEMM_TARGET
+#define TITAN_GEMM_TARGET 256
+#endif
+constexpr int kGemmTarget = TITAN_GEMM_TARGET;
 
 // part (capacity part_cap floats) enables split-K when the output has too few
 // tiles; null: one pass.
@@ -523,8 +527,18 @@ __global__ void bias_final_kernel(const float *part, int chunks, int N, float *d
     db[j] = acc;
 }
 
+// Where the weight matrices sit in the flat parameters and in the bf16 copy
+// the GEMMs read (biases stay FP32).
+constexpr int kMaxLayersFused = 8;
+struct WeightMap {
+    int L;
+    int64_t woff[kMaxLayersFused], wn[kMaxLayersFused], wboff[kMaxLayersFused];
+};
+
+// Adam on the FP32 master parameters; with wb, also the bf16 copy of every
+// updated weight (what a separate conversion pass would write).
 __global__ void adam_kernel(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
-                            float eps, float bc1, float bc2)
+                            float eps, float bc1, float bc2, WeightMap map, uint16_t *wb)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n)
@@ -534,7 +548,12 @@ __global__ void adam_kernel(float *p, const float *g, float *m, float *v, int64_
     const float vq = b2 * v[q] + (1.f - b2) * gq * gq;
     m[q] = mq;
     v[q] = vq;
-    p[q] -= lr * (mq / bc1) / (sqrtf(vq / bc2) + eps);
+    const float pq = p[q] - lr * (mq / bc1) / (sqrtf(vq / bc2) + eps);
+    p[q] = pq;
+    if (wb)
+        for (int l = 0; l < map.L; ++l)
+            if (q >= map.woff[l] && q < map.woff[l] + map.wn[l])
+                wb[map.wboff[l] + (q - map.woff[l])] = f2bf(pq);
 }
 
 hipError_t launch1d(void (*k)(const float *, uint16_t *, int64_t), const float *x, uint16_t *y, int64_t n,
@@ -931,11 +950,23 @@ extern "C" int titan_mlp_train(titan_mlp *m, int64_t nsteps, int32_t batch, cons
         m->adam_t += 1;
         const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)m->adam_t));
         const float bc2 = (float)(1.0 - std::pow((double)beta2, (double)m->adam_t));
+        WeightMap map{};
+        const bool fused = m->L() <= kMaxLayersFused;
+        if (fused) {
+            map.L = m->L();
+            for (int l = 0; l < m->L(); ++l) {
+                map.woff[l] = m->woff[l];
+                map.wn[l] = (int64_t)m->dims[l] * m->dims[l + 1];
+                map.wboff[l] = m->wboff[l];
+            }
+        }
         hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((m->nparam + 255) / 256)), dim3(256), 0, m->stream, m->P,
-                           m->G, m->Mo, m->Vo, m->nparam, lr, beta1, beta2, eps, bc1, bc2);
+                           m->G, m->Mo, m->Vo, m->nparam, lr, beta1, beta2, eps, bc1, bc2, map,
+                           fused ? m->Wb : nullptr);
         MLP_TRY(hipGetLastError());
-        if (int rc = refresh_bf16(m))
-            return rc;
+        if (!fused)
+            if (int rc = refresh_bf16(m))
+                return rc;
     }
     if (loss_out && nsteps)
         MLP_TRY(hipMemcpyAsync(loss_out, dloss, sizeof(float) * nsteps, hipMemcpyDeviceToHost, m->stream));
