@@ -623,9 +623,11 @@ static int ensure_stage_buffers(titan_sim *s, bool rk4)
                 dev_free(s, b);
             b = nullptr;
         }
-        if (s->verlet_acc)
-            dev_free(s, s->verlet_acc);
-        s->verlet_acc = nullptr;
+        for (float4 *&b : s->verlet_acc) {
+            if (b)
+                dev_free(s, b);
+            b = nullptr;
+        }
         s->acc_valid = false;
         s->stage_n = s->n;
     }
@@ -635,16 +637,18 @@ static int ensure_stage_buffers(titan_sim *s, bool rk4)
             if (!b)
                 if (int rc = dev_alloc(s, bytes, (void **)&b))
                     return rc;
-    } else if (!s->verlet_acc) {
-        if (int rc = dev_alloc(s, bytes, (void **)&s->verlet_acc))
-            return rc;
+    } else if (!s->verlet_acc[0]) {
+        for (float4 *&b : s->verlet_acc)
+            if (int rc = dev_alloc(s, bytes, (void **)&b))
+                return rc;
         s->acc_valid = false;
     }
     return TITAN_OK;
 }
 
 // Velocity Verlet and RK4 (Sec. III-B): one gather launch per force
-// evaluation, on the plain engines.
+// evaluation (Verlet's drift is done by its kick launch), on the plain
+// engines.
 static int enqueue_staged(titan_sim *s, int64_t first_step, int64_t count)
 {
     const bool rk4 = s->params.integrator == TITAN_INTEG_RK4;
@@ -692,29 +696,31 @@ static int enqueue_staged(titan_sim *s, int64_t first_step, int64_t count)
                 s->cur = 1 - s->cur;
                 continue;
             }
-            // velocity Verlet
-            io.A = s->verlet_acc;
+            // velocity Verlet: one launch drifts every mass it reads (from
+            // its state and carried acceleration), kicks, and writes the new
+            // state and acceleration into the other buffers
             if (!s->acc_valid) {
                 io.U_in = U0;
                 io.V_in = V0;
+                io.A = s->verlet_acc[s->acc_cur];
                 StepConsts sc = consts_for(s, n, s->trig + q);
                 sc.stage = kStageVerletInit;
                 HIP_TRY(s, launch_gather_stage(s->gg, io, sc, s->tiled, s->stream));
                 s->acc_valid = true;
             }
-            HIP_TRY(s, launch_verlet_drift(U0, V0, s->verlet_acc, U1, V1, s->n, (float)dt, s->stream));
-            // the kick reads the drifted state and writes the step's result
-            // back over the starting state (each mass reads its own starting
-            // height first)
-            io.U_in = U1;
-            io.V_in = V1;
+            io.U_in = U0;
+            io.V_in = V0;
+            io.A_in = s->verlet_acc[s->acc_cur];
             io.U_base = U0;
-            io.U_out = U0;
-            io.V_out = V0;
+            io.U_out = U1;
+            io.V_out = V1;
+            io.A = s->verlet_acc[1 - s->acc_cur];
             StepConsts sc = consts_for(s, n, s->trig + q + 1);
             sc.t_add = dt;
             sc.stage = kStageVerletKick;
             HIP_TRY(s, launch_gather_stage(s->gg, io, sc, s->tiled, s->stream));
+            s->cur = 1 - s->cur;
+            s->acc_cur = 1 - s->acc_cur;
         }
     }
     return TITAN_OK;

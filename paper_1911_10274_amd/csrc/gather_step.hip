@@ -35,8 +35,12 @@ __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateI
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n)
         return;
-    const float4 ui = io.U_in[i];
-    const float4 vi = io.V_in[i];
+    // the Verlet kick evaluates the drifted state of every mass it reads
+    const bool drifting = MODE == kModeStage && sc.stage == kStageVerletKick;
+    float4 ui = io.U_in[i];
+    float4 vi = io.V_in[i];
+    if (drifting)
+        verlet_drift(ui, vi, io.A_in[i], sc.dt, ui, vi);
     const float4 xi = g.X0[i];
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
     float fx = 0.f, fy = 0.f, fz = 0.f;
@@ -46,7 +50,13 @@ __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateI
         [&](int j, float4 &xj, float4 &uj, float4 &vj) {
             uj = io.U_in[j];
             xj = g.X0[j];
-            vj = DAMP ? io.V_in[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (MODE == kModeStage && drifting) {
+                float4 vv = io.V_in[j];
+                verlet_drift(uj, vv, io.A_in[j], sc.dt, uj, vv);
+                vj = DAMP ? vv : make_float4(0.f, 0.f, 0.f, 0.f);
+            } else {
+                vj = DAMP ? io.V_in[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
         },
         fx, fy, fz);
     if (MODE == kModeForces) {
@@ -79,10 +89,14 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
     const int tid = threadIdx.x;
     const int64_t i = (int64_t)t * kTile + tid;
     const bool valid = i < g.n;
+    // the Verlet kick stages the drifted state of the tile and its halo
+    const bool drifting = MODE == kModeStage && sc.stage == kStageVerletKick;
     float4 ui = make_float4(0.f, 0.f, 0.f, 0.f), vi = ui, xi = ui;
     if (valid) {
         ui = io.U_in[i];
         vi = io.V_in[i];
+        if (MODE == kModeStage && drifting)
+            verlet_drift(ui, vi, io.A_in[i], sc.dt, ui, vi);
         xi = g.X0[i];
         sU[tid] = ui;
         sX[tid] = xi;
@@ -93,10 +107,17 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
     for (int64_t h = hb + tid; h < he; h += kTile) {
         const int j = g.halo_idx[h];
         const int q = kTile + (int)(h - hb);
-        sU[q] = io.U_in[j];
-        sX[q] = g.X0[j];
-        if (DAMP)
+        float4 uj = io.U_in[j];
+        if (MODE == kModeStage && drifting) {
+            float4 vj = io.V_in[j];
+            verlet_drift(uj, vj, io.A_in[j], sc.dt, uj, vj);
+            if (DAMP)
+                sV[q] = vj;
+        } else if (DAMP) {
             sV[q] = io.V_in[j];
+        }
+        sU[q] = uj;
+        sX[q] = g.X0[j];
     }
     __syncthreads();
     if (!valid)
@@ -156,25 +177,6 @@ hipError_t launch4(const GatherGraph &g, const StateIO &io, const StepConsts &sc
     else
         launch_mode<ACT, WAVE, DAMP, DAMPV, REST, YIELD, kModeStep>(g, io, sc, tiled, st);
     return hipGetLastError();
-}
-
-__global__ void verlet_drift_kernel(const float4 *U, const float4 *V, const float4 *A, float4 *Uo, float4 *Vo,
-                                    int64_t n, float dt)
-{
-#pragma clang fp contract(off)
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
-        return;
-    const float4 u = U[i], v = V[i], a = A[i];
-    if (u.w == 0.f) {  // pinned
-        Uo[i] = u;
-        Vo[i] = v;
-        return;
-    }
-    const float half = 0.5f * dt;
-    const float4 vh = make_float4(fmaf(half, a.x, v.x), fmaf(half, a.y, v.y), fmaf(half, a.z, v.z), 0.f);
-    Uo[i] = make_float4(fmaf(dt, vh.x, u.x), fmaf(dt, vh.y, u.y), fmaf(dt, vh.z, u.z), u.w);
-    Vo[i] = vh;
 }
 
 __global__ void trig_table_kernel(float2 *trig, int64_t first, int count, double omega, double dt)
@@ -339,14 +341,5 @@ hipError_t launch_gather_stage(const GatherGraph &g, const StateIO &io, const St
     return dispatch_mode(g, io, sc, kModeStage, tiled, stream);
 }
 
-hipError_t launch_verlet_drift(const float4 *U, const float4 *V, const float4 *A, float4 *Uo, float4 *Vo, int64_t n,
-                               float dt, hipStream_t stream)
-{
-    if (n <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(verlet_drift_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, U, V, A, Uo, Vo,
-                       n, dt);
-    return hipGetLastError();
-}
 
 }  // namespace titan

@@ -207,6 +207,22 @@ __device__ __forceinline__ void friction_after(float zb, float im, const StepCon
     v.y = wy;
 }
 
+// Verlet drift of one mass: v' = v + a dt/2, x' = x + v' dt (pinned: kept).
+__device__ __forceinline__ void verlet_drift(const float4 &u, const float4 &v, const float4 &a, float dt, float4 &uo,
+                                             float4 &vo)
+{
+#pragma clang fp contract(off)
+    if (u.w == 0.f) {
+        uo = u;
+        vo = v;
+        return;
+    }
+    const float half = 0.5f * dt;
+    const float4 vh = make_float4(fmaf(half, a.x, v.x), fmaf(half, a.y, v.y), fmaf(half, a.z, v.z), 0.f);
+    uo = make_float4(fmaf(dt, vh.x, u.x), fmaf(dt, vh.y, u.y), fmaf(dt, vh.z, u.z), u.w);
+    vo = vh;
+}
+
 __device__ __forceinline__ bool finite4(const float4 &u, const float4 &v)
 {
     return isfinite(u.x) && isfinite(u.y) && isfinite(u.z) && isfinite(v.x) && isfinite(v.y) && isfinite(v.z);
@@ -227,7 +243,7 @@ __device__ __forceinline__ bool stage_update(int64_t i, const float4 &xi, const 
         return true;
     }
     if (sc.stage == kStageVerletKick) {
-        // (ui, vi) = (x', v'); the step started at U_base (same buffer as U_out)
+        // (ui, vi) = (x', v'), drifted from the step's starting state U_base
         const float zb = xi.z + io.U_base[i].z;
         float4 u = ui, v = vi;
         if (im != 0.f) {

@@ -32,7 +32,8 @@ struct StepConsts {
 // gather launch each, selected by StepConsts::stage.
 constexpr int32_t kStageRk1 = 1;         // RK4 stages 1-3: sums, next stage state
 constexpr int32_t kStageRk4 = 4;         // RK4 stage 4: the new state (+ friction)
-constexpr int32_t kStageVerletKick = 5;  // a' at (x', v'), v'' = v' + a' dt/2 (+ friction)
+constexpr int32_t kStageVerletKick = 5;  // drift x' = x + v' dt, v' = v + a dt/2 of every mass read;
+                                         // a' at (x', v'), v'' = v' + a' dt/2 (+ friction)
 constexpr int32_t kStageVerletInit = 6;  // a at (x, v): the acceleration Verlet carries
 
 // Largest number of steps whose clock entries one table holds.
@@ -101,12 +102,9 @@ struct StateIO {
     const float4 *V_base;
     float4 *sum_u;
     float4 *sum_v;
-    float4 *A;
+    const float4 *A_in;  // Verlet: the carried acceleration of every mass
+    float4 *A;           // Verlet: the new acceleration (own mass)
 };
-
-// Verlet drift: v' = v + a dt/2, x' = x + v' dt (pinned masses unchanged).
-hipError_t launch_verlet_drift(const float4 *U, const float4 *V, const float4 *A, float4 *Uo, float4 *Vo, int64_t n,
-                               float dt, hipStream_t stream);
 
 // dst[slot[q]] = val[q] for q < m; dst[q] = v for q < m.
 hipError_t launch_scatter(float *dst, const int64_t *slot, const float *val, int64_t m, hipStream_t stream);

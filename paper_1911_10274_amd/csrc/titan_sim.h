@@ -93,9 +93,10 @@ struct titan_sim {
     // staged integrators: RK4 stage states (two ping-pong pairs) and sums,
     // Verlet's carried acceleration; sized for stage_n masses
     float4 *stage_buf[6] = {};
-    float4 *verlet_acc = nullptr;
+    float4 *verlet_acc[2] = {};    // ping-pong: the kick reads one, writes the other
+    int acc_cur = 0;
     int64_t stage_n = 0;
-    bool acc_valid = false;        // verlet_acc holds the current state's acceleration
+    bool acc_valid = false;        // verlet_acc[acc_cur] holds the current state's acceleration
     int64_t layout_builds = 0;     // times the layouts were built
     int64_t springs_in_place = 0;  // springs inserted into spare slots
 
