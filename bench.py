@@ -328,6 +328,31 @@ def bench_integrators(T, scene, steps: int = 1000):
     return out
 
 
+def bench_graphs(T, steps: int = 10000, graph_steps: int = 512):
+    """A small system, where launches rather than bytes bound a step: the
+    10^3 falling cube (10,476 springs, dt = 1e-4) on the tiled engine, one
+    launch per step against replays of a captured graph of graph_steps
+    launches."""
+    import torch
+
+    from paper_1911_10274_amd import scenes
+
+    sc = scenes.cube_drop(10)
+    ns = sc["ends"].shape[0]
+    out = {"workload": f"10^3 cube ({ns} springs), tiled engine, {steps} steps", "graph_steps": graph_steps}
+    for name, g in (("launches", 0), ("graph", graph_steps)):
+        tp = T.Params(dt=1e-4, gravity=(0.0, 0.0, -9.81), ground=True, ground_k=1e5, friction_mu=0.5,
+                      engine=T.ENGINE_TILED, graph_steps=g)
+        sim = T.sim_from_scene(sc, tp)
+        sim.finalize()
+        sim.step(2 * graph_steps)
+        sim.sync()
+        ms = _timed_steps(sim, steps, torch.cuda.current_stream())
+        sim.close()
+        out[name] = {"us_per_step": 1e3 * ms / steps, "spring_updates_per_s": ns * steps / (ms * 1e-3)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,6 +372,7 @@ def main():
     ap.add_argument("--adjoint-robots", type=int, default=256, help="robots in the adjoint workload (0: skip)")
     ap.add_argument("--integrator-steps", type=int, default=1000,
                     help="steps of Verlet and of RK4 on the lattice (0: skip)")
+    ap.add_argument("--no-graphs", action="store_true", help="skip the captured-step-loop figure")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -431,6 +457,8 @@ def main():
     if args.integrator_steps > 0:
         out["integrators"] = bench_integrators(T, scene, args.integrator_steps)
         out["integrators"]["euler_ms_per_step"] = ms_per_step
+    if not args.no_graphs:
+        out["graphs"] = bench_graphs(T)
     if args.robots > 0:
         out["batched"] = bench_batched(T, args.robots, args.robot_steps, args.loop_sample)
     if args.adjoint_robots > 0:

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TITAN_ABI_VERSION 4
+#define TITAN_ABI_VERSION 5
 
 /* Status codes. */
 #define TITAN_OK 0
@@ -123,6 +123,15 @@ typedef struct titan_params {
     double wave_period; /* TITAN_ACT_WAVE: period t_p, s (> 0) */
     int32_t integrator; /* TITAN_INTEG_*: the time integrator (Sec. III-B
                            names Euler, Verlet and RK4) */
+    int32_t graph_steps; /* 0, or an even number <= 4096: the gather and tiled
+                            engines (Euler integrator) replay a captured HIP
+                            graph of this many step launches, the step index
+                            read from a device clock, for every whole group of
+                            graph_steps steps of a titan_step call (the rest
+                            launch one by one).  Same results bit for bit;
+                            fewer host launches for small systems.  The graph
+                            is captured again after anything that changes the
+                            system or the parameters. */
 } titan_params;
 
 /* Optional device-memory provider.  alloc returns a device pointer aligned

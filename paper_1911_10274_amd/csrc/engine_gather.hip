@@ -726,12 +726,116 @@ static int enqueue_staged(titan_sim *s, int64_t first_step, int64_t count)
     return TITAN_OK;
 }
 
+void destroy_step_graphs(titan_sim *s)
+{
+    bool any = false;
+    for (hipGraphExec_t g : s->step_graph)
+        any |= g != nullptr;
+    if (any)
+        (void)hipStreamSynchronize(s->stream);  // no replay in flight
+    for (hipGraphExec_t &g : s->step_graph) {
+        if (g)
+            (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+    if (s->capture_stream)
+        (void)hipStreamDestroy(s->capture_stream);
+    s->capture_stream = nullptr;
+    (void)hipGetLastError();
+}
+
+void invalidate_step_cache(titan_sim *s)
+{
+    s->acc_valid = false;
+    bool any = false;
+    for (hipGraphExec_t g : s->step_graph)
+        any |= g != nullptr;
+    if (!any)
+        return;
+    (void)hipStreamSynchronize(s->stream);
+    for (hipGraphExec_t &g : s->step_graph) {
+        if (g)
+            (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+    (void)hipGetLastError();  // leave no error of this cleanup for the next launch check
+}
+
+// Capture graph_steps Euler step launches, for the current parity of cur: a
+// clock-table node (first step = *d_clock), the steps (step index = *d_clock
+// + q), and a node that advances the clock.  Captured on a stream of the
+// sim's own (default priority); kernel nodes only.
+static int capture_step_graph(titan_sim *s, hipGraphExec_t *out)
+{
+    const int G = s->params.graph_steps;
+    if (!s->capture_stream)
+        HIP_TRY(s, hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = s->capture_stream;
+    HIP_TRY(s, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_trig_table_clock(s->trig, s->d_clock, G, s->params.omega, s->params.dt, cs);
+    int c = s->cur;
+    for (int q = 0; q < G && e == hipSuccess; ++q) {
+        StateIO io{};
+        io.U_in = s->U[c];
+        io.V_in = s->V[c];
+        io.U_out = s->U[1 - c];
+        io.V_out = s->V[1 - c];
+        io.first_bad = s->first_bad;
+        StepConsts sc = consts_for(s, q, s->trig + q);
+        sc.clock = s->d_clock;
+        e = launch_gather_step(s->gg, io, sc, false, s->tiled, cs);
+        c = 1 - c;
+    }
+    if (e == hipSuccess)
+        e = launch_clock(s->d_clock, 0, G, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess)
+        e = e2;
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    if (graph)
+        (void)hipGraphDestroy(graph);
+    if (e != hipSuccess)
+        return hip_fail(s, e, "capturing the step loop");
+    return TITAN_OK;
+}
+
+// reps replays of the captured step loop from step `first` (parity of cur
+// unchanged: graph_steps is even).
+static int replay_step_graph(titan_sim *s, int64_t first, int64_t reps)
+{
+    if (!s->d_clock) {  // lives as long as the sim (not a layout allocation)
+        if (int rc = dev_alloc(s, sizeof(int64_t), (void **)&s->d_clock))
+            return rc;
+        s->clock_host = -1;
+    }
+    hipGraphExec_t &ex = s->step_graph[s->cur];
+    if (!ex)
+        if (int rc = capture_step_graph(s, &ex))
+            return rc;
+    if (s->clock_host != first)
+        HIP_TRY(s, launch_clock(s->d_clock, first, 0, s->stream));
+    for (int64_t r = 0; r < reps; ++r)
+        HIP_TRY(s, hipGraphLaunch(ex, s->stream));
+    s->clock_host = first + reps * s->params.graph_steps;
+    return TITAN_OK;
+}
+
 int enqueue_steps(titan_sim *s, int64_t first_step, int64_t count)
 {
     if (s->params.integrator != TITAN_INTEG_EULER)
         return enqueue_staged(s, first_step, count);
     if (s->engine == TITAN_ENGINE_BATCHED && s->batch && s->batch_step)
         return enqueue_batch_steps(s, first_step, count);
+    const int G = s->params.graph_steps;
+    if (G > 0 && count >= G) {
+        const int64_t reps = count / G;
+        if (int rc = replay_step_graph(s, first_step, reps))
+            return rc;
+        first_step += reps * G;
+        count -= reps * G;
+    }
     for (int64_t c0 = 0; c0 < count; c0 += kTrigChunk) {
         const int nc = (int)std::min<int64_t>(kTrigChunk, count - c0);
         HIP_TRY(s, launch_trig_table(s->trig, first_step + c0, nc, s->params.omega, s->params.dt, s->stream));
@@ -1005,6 +1109,7 @@ int rebuild_engines(titan_sim *s)
 {
     if (int rc = sync_broken(s))
         return rc;
+    invalidate_step_cache(s);
     destroy_batch_engine(s);
     dev_free_engine(s);
     s->gg = GatherGraph{};

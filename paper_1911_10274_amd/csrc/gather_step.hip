@@ -44,7 +44,8 @@ __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateI
     const float4 xi = g.X0[i];
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
     float fx = 0.f, fy = 0.f, fz = 0.f;
-    const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), (double)sc.step * sc.dt64 + sc.t_add};
+    const int64_t n = step_index(sc);
+    const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), (double)n * sc.dt64 + sc.t_add};
     sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE, yield_mode<YIELD, MODE>>(
         g, base, slice_width(g, i), xi, ui, vi, ck, sc, [&](int64_t e) { return stream_load(g.nbr + e); },
         [&](int j, float4 &xj, float4 &uj, float4 &vj) {
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateI
     }
     if (MODE == kModeStage) {
         if (!stage_update(i, xi, ui, vi, fx, fy, fz, io, sc))
-            atomicMin(io.first_bad, (unsigned long long)sc.step);
+            atomicMin(io.first_bad, (unsigned long long)n);
         return;
     }
     float4 uo, vo;
@@ -73,7 +74,7 @@ __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateI
     io.U_out[i] = uo;
     io.V_out[i] = vo;
     if (!ok)
-        atomicMin(io.first_bad, (unsigned long long)sc.step);
+        atomicMin(io.first_bad, (unsigned long long)n);
 }
 
 template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, int MODE, bool YIELD>
@@ -125,7 +126,8 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
 
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
     float fx = 0.f, fy = 0.f, fz = 0.f;
-    const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), (double)sc.step * sc.dt64 + sc.t_add};
+    const int64_t n = step_index(sc);
+    const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), (double)n * sc.dt64 + sc.t_add};
     sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE, yield_mode<YIELD, MODE>>(
         g, base, slice_width(g, i), xi, ui, vi, ck, sc, [&](int64_t e) { return (int)stream_load(g.nbr_local + e); },
         [&](int q, float4 &xj, float4 &uj, float4 &vj) {
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
     }
     if (MODE == kModeStage) {
         if (!stage_update(i, xi, ui, vi, fx, fy, fz, io, sc))
-            atomicMin(io.first_bad, (unsigned long long)sc.step);
+            atomicMin(io.first_bad, (unsigned long long)n);
         return;
     }
     float4 uo, vo;
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
     io.U_out[i] = uo;
     io.V_out[i] = vo;
     if (!ok)
-        atomicMin(io.first_bad, (unsigned long long)sc.step);
+        atomicMin(io.first_bad, (unsigned long long)n);
 }
 
 template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool YIELD, int MODE>
@@ -186,6 +188,24 @@ __global__ void trig_table_kernel(float2 *trig, int64_t first, int count, double
         return;
     const double ph = omega * ((double)(first + s) * dt);
     trig[s] = make_float2((float)sin(ph), (float)cos(ph));
+}
+
+// The same table with its first step read from the device clock (a node of a
+// captured step loop).
+__global__ void trig_table_clock_kernel(float2 *trig, const int64_t *clock, int count, double omega, double dt)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= count)
+        return;
+    const double ph = omega * ((double)(*clock + s) * dt);
+    trig[s] = make_float2((float)sin(ph), (float)cos(ph));
+}
+
+// *clock = value (add == 0) or *clock += add: one thread, a vector store.
+__global__ void clock_kernel(int64_t *clock, int64_t value, int64_t add)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *clock = add ? *clock + add : value;
 }
 
 __global__ void scatter_kernel(float *dst, const int64_t *slot, const float *val, int64_t m)
@@ -231,6 +251,22 @@ __global__ void fill_kernel(float *dst, float v, int64_t m)
 }
 
 }  // namespace
+
+hipError_t launch_trig_table_clock(float2 *trig, const int64_t *clock, int count, double omega, double dt,
+                                   hipStream_t stream)
+{
+    if (count <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(trig_table_clock_kernel, dim3((count + 255) / 256), dim3(256), 0, stream, trig, clock, count,
+                       omega, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_clock(int64_t *clock, int64_t value, int64_t add, hipStream_t stream)
+{
+    hipLaunchKernelGGL(clock_kernel, dim3(1), dim3(64), 0, stream, clock, value, add);
+    return hipGetLastError();
+}
 
 hipError_t launch_scatter(float *dst, const int64_t *slot, const float *val, int64_t m, hipStream_t stream)
 {

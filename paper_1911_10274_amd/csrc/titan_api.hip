@@ -167,6 +167,8 @@ static int check_params(const titan_params *p)
         return fail(TITAN_EINVAL, "unknown integrator %d", p->integrator);
     if (p->integrator != TITAN_INTEG_EULER && p->engine == TITAN_ENGINE_BATCHED)
         return fail(TITAN_EINVAL, "the batched engine steps with the Euler integrator only");
+    if (p->graph_steps < 0 || p->graph_steps > 4096 || (p->graph_steps & 1))
+        return fail(TITAN_EINVAL, "graph_steps must be 0 or an even number up to 4096 (got %d)", p->graph_steps);
     return TITAN_OK;
 }
 
@@ -216,6 +218,7 @@ extern "C" int titan_destroy(titan_sim *s)
                 (void)hipStreamDestroy(s->side_stream);
             if (s->host_stage)
                 (void)hipHostFree(s->host_stage);
+            destroy_step_graphs(s);
             destroy_engines(s);
             dev_free_all(s);
         }
@@ -276,7 +279,7 @@ extern "C" int titan_add_springs(titan_sim *s, int64_t n, const int64_t *ends, c
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
-    s->acc_valid = false;  // a carried Verlet acceleration is recomputed
+    invalidate_step_cache(s);
     if (s->finalized && s->dev_error)
         return fail(TITAN_EDEVICE, "sim is in a failed device state");
     if (n < 0)
@@ -407,7 +410,7 @@ static int grow_state(titan_sim *s, float4 **buf, int64_t n_old, const std::vect
 static int add_masses_live(titan_sim *s, int64_t n, const float *pos, const float *vel, const float *mass,
                            const int32_t *body, int64_t *first_out)
 {
-    s->acc_valid = false;
+    invalidate_step_cache(s);
     if (s->dev_error)
         return fail(TITAN_EDEVICE, "sim is in a failed device state");
     int32_t maxb = -1;
@@ -495,7 +498,7 @@ extern "C" int titan_remove_springs(titan_sim *s, int64_t n, const int64_t *spri
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
-    s->acc_valid = false;  // a carried Verlet acceleration is recomputed
+    invalidate_step_cache(s);
     if (n < 0 || (n > 0 && !springs))
         return fail(TITAN_EINVAL, "bad spring list");
     if (s->dev_error)
@@ -513,7 +516,7 @@ extern "C" int titan_set_yield(titan_sim *s, int64_t first, int64_t count, const
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
-    s->acc_valid = false;  // a carried Verlet acceleration is recomputed
+    invalidate_step_cache(s);
     const int64_t ns = (int64_t)s->h_k.size();
     if (first < 0 || count < 0 || first > ns || count > ns - first || (count > 0 && !yield))
         return fail(TITAN_EINVAL, "bad spring range [%lld, +%lld) of %lld", (long long)first, (long long)count,
@@ -565,7 +568,7 @@ extern "C" int titan_remove_masses(titan_sim *s, int64_t n, const int64_t *masse
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
-    s->acc_valid = false;  // a carried Verlet acceleration is recomputed
+    invalidate_step_cache(s);
     if (n < 0 || (n > 0 && !masses))
         return fail(TITAN_EINVAL, "bad mass list");
     if (s->dev_error)
@@ -614,7 +617,8 @@ extern "C" int titan_set_params(titan_sim *s, const titan_params *p)
         return fail(TITAN_ESTATE, "the batched engine steps with the Euler integrator only");
     s->params = *p;
     s->params.engine = engine;
-    s->acc_valid = false;
+    if (s->finalized)
+        invalidate_step_cache(s);
     if (s->finalized) {  // the plain engines run the other integrators
         if (p->integrator != TITAN_INTEG_EULER && s->engine == TITAN_ENGINE_BATCHED)
             s->engine = s->tiled ? TITAN_ENGINE_TILED : TITAN_ENGINE_GATHER;
@@ -947,7 +951,7 @@ extern "C" int titan_set_state(titan_sim *s, int64_t first, int64_t count, const
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
-    s->acc_valid = false;  // a carried Verlet acceleration is recomputed
+    invalidate_step_cache(s);
     if (int rc = ready(s))
         return rc;
     if (int rc = check_range(s, first, count))
@@ -995,7 +999,7 @@ extern "C" int titan_set_step(titan_sim *s, int64_t step)
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
-    s->acc_valid = false;  // a carried Verlet acceleration is recomputed
+    invalidate_step_cache(s);
     if (step < 0)
         return fail(TITAN_EINVAL, "negative step index");
     if (int rc = ready(s))
@@ -1041,7 +1045,7 @@ extern "C" int titan_set_springs(titan_sim *s, int64_t first, int64_t count, con
     if (!s)
         return fail(TITAN_EINVAL, "sim is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
-    s->acc_valid = false;  // a carried Verlet acceleration is recomputed
+    invalidate_step_cache(s);
     if (first < 0 || count < 0 || first + count > (int64_t)s->h_k.size())
         return fail(TITAN_EINVAL, "spring range [%lld, %lld) outside [0, %lld)", (long long)first,
                     (long long)(first + count), (long long)s->h_k.size());

@@ -26,7 +26,11 @@ struct StepConsts {
     double omega;        // wave law: angular frequency
     double t_add;        // added to n * dt64 (an RK4 stage's time offset c * dt)
     int32_t stage;       // integrator stage of a staged launch (kStage*)
+    const int64_t *clock;  // non-null in a captured step loop: n = *clock + step
 };
+
+// The step index n of a gather-engine launch.
+__device__ __forceinline__ int64_t step_index(const StepConsts &sc) { return sc.clock ? *sc.clock + sc.step : sc.step; }
 
 // Stages of the other integrators (Sec. III-B names Verlet and RK4): one
 // gather launch each, selected by StepConsts::stage.
@@ -42,6 +46,11 @@ constexpr int kTrigChunk = 4096;
 // trig[s] = (sin, cos)(omega * (first + s) * dt) for s < count (FP64, rounded).
 hipError_t launch_trig_table(float2 *trig, int64_t first, int count, double omega, double dt,
                              hipStream_t stream);
+// The same with first = *clock (read on the device).
+hipError_t launch_trig_table_clock(float2 *trig, const int64_t *clock, int count, double omega, double dt,
+                                   hipStream_t stream);
+// *clock = value, or with add != 0, *clock += add (stream order).
+hipError_t launch_clock(int64_t *clock, int64_t value, int64_t add, hipStream_t stream);
 
 // Masses per tile of the tiled kernel (one workgroup, one thread per mass).
 // Compile-time tuning of the tiled kernel (overridable with -D for tuning

@@ -96,6 +96,12 @@ struct titan_sim {
     float4 *verlet_acc[2] = {};    // ping-pong: the kick reads one, writes the other
     int acc_cur = 0;
     int64_t stage_n = 0;
+    // captured step loops (params.graph_steps > 0): one graph per parity of
+    // cur, replayed from the device clock d_clock
+    hipGraphExec_t step_graph[2] = {};
+    int64_t *d_clock = nullptr;
+    int64_t clock_host = -1;       // d_clock after the queued work (-1: unknown)
+    hipStream_t capture_stream = nullptr;
     bool acc_valid = false;        // verlet_acc[acc_cur] holds the current state's acceleration
     int64_t layout_builds = 0;     // times the layouts were built
     int64_t springs_in_place = 0;  // springs inserted into spare slots
@@ -149,6 +155,11 @@ void destroy_engines(titan_sim *s);
 // the layout otherwise (in both cases nothing is written and the layouts must
 // be rebuilt); or an error code (< 0).
 int insert_springs(titan_sim *s, int64_t first, int64_t count);
+// Something the step launches depend on changed: a carried Verlet
+// acceleration is recomputed and captured step loops are captured again.
+void invalidate_step_cache(titan_sim *s);
+// Release the captured step loops and their stream (titan_destroy).
+void destroy_step_graphs(titan_sim *s);
 // Copy the breaks the steps have recorded into h_broken (and h_removed);
 // waits for the stream.
 int sync_broken(titan_sim *s);

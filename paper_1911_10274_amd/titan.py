@@ -57,6 +57,7 @@ class _Params(ctypes.Structure):
         ("actuation", ctypes.c_int32),
         ("wave_period", ctypes.c_double),
         ("integrator", ctypes.c_int32),
+        ("graph_steps", ctypes.c_int32),
     ]
 
 
@@ -188,6 +189,7 @@ class Params:
     actuation: int = ACT_PHASOR
     wave_period: float = 1.0
     integrator: int = INTEG_EULER
+    graph_steps: int = 0
 
     def _c(self) -> _Params:
         p = _Params()
@@ -201,6 +203,7 @@ class Params:
         p.actuation = int(self.actuation)
         p.wave_period = self.wave_period
         p.integrator = int(self.integrator)
+        p.graph_steps = int(self.graph_steps)
         return p
 
 
