@@ -86,9 +86,12 @@ struct GemmArgs {
 
 // One operand tile (64 rows x BK of K) moved global -> registers -> LDS, the
 // LDS tile holding K contiguous per row.  KCONTIG: element (r, k) at
-// P[r * ld + k] (K contiguous in memory), else at P[k * ld + r].  Each of the
-// 256 threads moves two 16-byte chunks of 8 elements; vector loads when the
-// chunk is in range and aligned, element loads with zero fill otherwise.
+// P[r * ld + k] (K contiguous in memory): each of the 256 threads moves two
+// 16-byte chunks of 8 K-values.  Otherwise element (r, k) at P[k * ld + r]:
+// each thread moves a block of 8 K-values x 2 rows, read as eight 4-byte
+// pieces along the rows (32 consecutive threads cover one 128-byte K row),
+// transposed in registers and stored as two 16-byte LDS writes.  Vector loads
+// when in range and aligned, element loads with zero fill otherwise.
 template <bool KCONTIG>
 struct TileMove {
     uint4 v[2];
@@ -96,52 +99,64 @@ struct TileMove {
     __device__ __forceinline__ void load(const uint16_t *P, int ld, int r0, int R, int k0, int kend, bool vec,
                                          int tid)
     {
+        if (KCONTIG) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = tid + 256 * q;
-            const int hi = c >> 3, lo = (c & 7) * 8;
-            // KCONTIG: row r0 + hi, K k0 + lo .. +8; else K k0 + hi, rows r0 + lo .. +8
-            const int row = KCONTIG ? r0 + hi : r0 + lo, k = KCONTIG ? k0 + lo : k0 + hi;
-            const bool full = KCONTIG ? (row < R && k + 8 <= kend) : (k < kend && row + 8 <= R);
-            if (vec && full) {
-                v[q] = KCONTIG ? *(const uint4 *)(P + (int64_t)row * ld + k) : *(const uint4 *)(P + (int64_t)k * ld + row);
-            } else {
+            for (int q = 0; q < 2; ++q) {
+                const int c = tid + 256 * q;
+                const int row = r0 + (c >> 3), k = k0 + (c & 7) * 8;
+                if (vec && row < R && k + 8 <= kend) {
+                    v[q] = *(const uint4 *)(P + (int64_t)row * ld + k);
+                } else {
+                    uint32_t w[4];
+#pragma unroll
+                    for (int e = 0; e < 8; e += 2) {
+                        const uint32_t x0 = (row < R && k + e < kend) ? P[(int64_t)row * ld + k + e] : 0u;
+                        const uint32_t x1 = (row < R && k + e + 1 < kend) ? P[(int64_t)row * ld + k + e + 1] : 0u;
+                        w[e / 2] = x0 | x1 << 16;
+                    }
+                    v[q] = make_uint4(w[0], w[1], w[2], w[3]);
+                }
+            }
+        } else {
+            const int kb = k0 + 8 * (tid >> 5), rb = r0 + 2 * (tid & 31);
+            uint32_t in[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = kb + e;
+                if (vec && k < kend && rb + 2 <= R) {
+                    in[e] = *(const uint32_t *)(P + (int64_t)k * ld + rb);
+                } else {
+                    const uint32_t x0 = (k < kend && rb < R) ? P[(int64_t)k * ld + rb] : 0u;
+                    const uint32_t x1 = (k < kend && rb + 1 < R) ? P[(int64_t)k * ld + rb + 1] : 0u;
+                    in[e] = x0 | x1 << 16;
+                }
+            }
+            // v[n] = the 8 K-values of row rb + n
+#pragma unroll
+            for (int n = 0; n < 2; ++n) {
                 uint32_t w[4];
 #pragma unroll
-                for (int e = 0; e < 8; e += 2) {
-                    uint32_t x0 = 0, x1 = 0;
-                    if (KCONTIG) {
-                        if (row < R && k + e < kend)
-                            x0 = P[(int64_t)row * ld + k + e];
-                        if (row < R && k + e + 1 < kend)
-                            x1 = P[(int64_t)row * ld + k + e + 1];
-                    } else {
-                        if (k < kend && row + e < R)
-                            x0 = P[(int64_t)k * ld + row + e];
-                        if (k < kend && row + e + 1 < R)
-                            x1 = P[(int64_t)k * ld + row + e + 1];
-                    }
-                    w[e / 2] = x0 | x1 << 16;
-                }
-                v[q] = make_uint4(w[0], w[1], w[2], w[3]);
+                for (int j = 0; j < 4; ++j)
+                    w[j] = n ? ((in[2 * j] >> 16) | (in[2 * j + 1] & 0xFFFF0000u))
+                             : ((in[2 * j] & 0xFFFFu) | (in[2 * j + 1] << 16));
+                v[n] = make_uint4(w[0], w[1], w[2], w[3]);
             }
         }
     }
 
     __device__ __forceinline__ void store(uint16_t *S, int tid) const
     {
+        if (KCONTIG) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = tid + 256 * q;
-            const int hi = c >> 3, lo = (c & 7) * 8;
-            if (KCONTIG) {
-                *(uint4 *)&S[hi * LDK + lo] = v[q];
-            } else {
-                const uint32_t w[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
-#pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    S[(lo + e) * LDK + hi] = (uint16_t)(w[e / 2] >> (16 * (e & 1)));
+            for (int q = 0; q < 2; ++q) {
+                const int c = tid + 256 * q;
+                *(uint4 *)&S[(c >> 3) * LDK + (c & 7) * 8] = v[q];
             }
+        } else {
+            const int kb = 8 * (tid >> 5), rb = 2 * (tid & 31);
+#pragma unroll
+            for (int n = 0; n < 2; ++n)
+                *(uint4 *)&S[(rb + n) * LDK + kb] = v[n];
         }
     }
 };
@@ -162,8 +177,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, GemmEpi ep)
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int wm = wave >> 1, wn = wave & 1;
     const int kb = blockIdx.z * g.kslice, ke = min(g.K, kb + g.kslice);
-    const bool va = (g.lda % 8 == 0) && (((uintptr_t)g.A & 15) == 0);
-    const bool vb = (g.ldb % 8 == 0) && (((uintptr_t)g.B & 15) == 0);
+    // vector loads: 16 bytes along K, or 4 bytes along the rows
+    const bool va = TA ? (g.lda % 2 == 0 && ((uintptr_t)g.A & 3) == 0) : (g.lda % 8 == 0 && ((uintptr_t)g.A & 15) == 0);
+    const bool vb = TB ? (g.ldb % 8 == 0 && ((uintptr_t)g.B & 15) == 0) : (g.ldb % 2 == 0 && ((uintptr_t)g.B & 3) == 0);
     TileMove<!TA> ta;
     TileMove<TB> tb;
     f32x16_t acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
