@@ -111,6 +111,28 @@ def copy_calibration(mib: int = 1024, reps: int = 5):
     print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4, "reps": reps}))
 
 
+def copy_bandwidth(mib: int = 2048, reps: int = 10):
+    """What this GPU's HBM delivers to a plain device-to-device copy (bytes
+    read + written per second): context for the roofline, whose peak stays
+    the published 8 TB/s."""
+    import torch
+
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    sec = ev0.elapsed_time(ev1) / reps * 1e-3
+    del a, b
+    return {"bytes": 2 * n * 4, "gbs": 2 * n * 4 / sec / 1e9}
+
+
 def _timed_steps(sim, steps, stream):
     """Milliseconds of ``steps`` steps, HIP events on the sim's stream."""
     import torch
@@ -424,6 +446,7 @@ def main():
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic,
     }
+    roofline["copy_gbs"] = round(copy_bandwidth()["gbs"], 1)  # context: a plain 2 GiB copy on this GPU
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scene, args.cpu_steps)
