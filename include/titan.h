@@ -103,9 +103,10 @@ typedef struct titan_sim titan_sim;
  * force evaluations per step.  Verlet and RK4 integrate springs, dampers,
  * gravity and the ground's normal force; Coulomb friction is applied after
  * the step as in the Euler step (normal force from the starting height), the
- * position moving by the velocity change times dt.  They run on the gather
- * and tiled engines; the batched engine and the rollout adjoint take EULER
- * only. */
+ * position moving by the velocity change times dt.  Every engine runs them
+ * with identical results (the batched engine when its groups hold at most
+ * 4096 masses for VERLET, 2048 for RK4; under TITAN_ENGINE_AUTO larger groups
+ * step with a per-step engine); the rollout adjoint takes EULER only. */
 #define TITAN_INTEG_EULER 0
 #define TITAN_INTEG_VERLET 1
 #define TITAN_INTEG_RK4 2

@@ -267,6 +267,43 @@ int enqueue_batch_steps(titan_sim *s, int64_t first_step, int64_t count)
     return TITAN_OK;
 }
 
+const BatchLayout &batch_layout(const titan_sim *s) { return s->batch->lay; }
+
+// Velocity Verlet / RK4 on the batched layout: chunks of steps per launch,
+// the clock tables as the per-step engines build them (RK4: half steps).
+int enqueue_batch_integ(titan_sim *s, int64_t first_step, int64_t count)
+{
+    BatchEngine *be = s->batch;
+    const int integ = s->params.integrator;
+    const bool rk4 = integ == TITAN_INTEG_RK4;
+    if (int rc = ensure_stage_buffers(s, false))  // Verlet's acceleration buffers
+        return rc;
+    const double dt = s->params.dt;
+    const int chunk = rk4 ? kTrigChunk / 2 : kTrigChunk;
+    for (int64_t c0 = 0; c0 < count; c0 += chunk) {
+        const int nc = (int)std::min<int64_t>(chunk, count - c0);
+        const int64_t n0 = first_step + c0;
+        if (rk4)
+            HIP_TRY(s, launch_trig_table(s->trig, 2 * n0, 2 * nc + 1, s->params.omega, 0.5 * dt, s->stream));
+        else
+            HIP_TRY(s, launch_trig_table(s->trig, n0, nc + 1, s->params.omega, dt, s->stream));
+        StateIO io{};
+        io.U_in = s->U[s->cur];
+        io.V_in = s->V[s->cur];
+        io.U_out = s->U[1 - s->cur];
+        io.V_out = s->V[1 - s->cur];
+        io.first_bad = s->first_bad;
+        io.A_in = s->verlet_acc[s->acc_cur];
+        io.A = s->verlet_acc[s->acc_cur];  // each mass's entry: read at the start, written at the end
+        const StepConsts sc = consts_for(s, n0, s->trig);
+        HIP_TRY(s, launch_batch_integ(s->gg, be->lay, io, sc, nc, integ, s->acc_valid ? 1 : 0, s->stream));
+        if (!rk4)
+            s->acc_valid = true;
+        s->cur = 1 - s->cur;
+    }
+    return TITAN_OK;
+}
+
 uint16_t *batch_nbr_group(titan_sim *s)
 {
     return s->batch ? const_cast<uint16_t *>(s->batch->lay.nbr_group) : nullptr;

@@ -18,6 +18,7 @@
 namespace titan {
 
 int build_batch_engine(titan_sim *s, bool may_step);  // engine_batch.hip
+int enqueue_batch_integ(titan_sim *s, int64_t first_step, int64_t count);
 int enqueue_batch_steps(titan_sim *s, int64_t first_step, int64_t count);
 void destroy_batch_engine(titan_sim *s);
 
@@ -463,10 +464,17 @@ int build_engines(titan_sim *s)
     // The batched layout is built whenever the bodies fit it (the adjoint
     // uses it); it steps the system when asked for, or when AUTO times it
     // faster.
-    // (the batched engine steps with the Euler integrator only)
-    if (int rc = build_batch_engine(s, (want == TITAN_ENGINE_BATCHED || want == TITAN_ENGINE_AUTO) &&
-                                           s->params.integrator == TITAN_INTEG_EULER))
+    if (int rc = build_batch_engine(s, want == TITAN_ENGINE_BATCHED || want == TITAN_ENGINE_AUTO))
         return rc;
+    // (the Verlet and RK4 kernels hold more per mass: larger groups step with
+    // the per-step engines under AUTO)
+    if (s->batch && s->batch_step && s->params.integrator != TITAN_INTEG_EULER &&
+        !batch_integ_fits(batch_layout(s), s->params.integrator)) {
+        if (want == TITAN_ENGINE_BATCHED)
+            return fail(TITAN_EINVAL, "the batched engine cannot run this integrator on this system (a group of "
+                                      "%d masses is too large)", batch_layout(s).max_group);
+        s->batch_step = false;
+    }
     if (s->batch && s->batch_step)
         s->engine = TITAN_ENGINE_BATCHED;
     else if (want == TITAN_ENGINE_BATCHED)
@@ -615,7 +623,7 @@ StepConsts consts_for(const titan_sim *s, int64_t step, const float2 *trig)
 }
 
 // Buffers of the staged integrators, for the current number of masses.
-static int ensure_stage_buffers(titan_sim *s, bool rk4)
+int ensure_stage_buffers(titan_sim *s, bool rk4)
 {
     if (s->stage_n != s->n) {
         for (float4 *&b : s->stage_buf) {
@@ -652,6 +660,8 @@ static int ensure_stage_buffers(titan_sim *s, bool rk4)
 static int enqueue_staged(titan_sim *s, int64_t first_step, int64_t count)
 {
     const bool rk4 = s->params.integrator == TITAN_INTEG_RK4;
+    if (s->engine == TITAN_ENGINE_BATCHED && s->batch && s->batch_step)
+        return enqueue_batch_integ(s, first_step, count);
     if (int rc = ensure_stage_buffers(s, rk4))
         return rc;
     const double dt = s->params.dt;

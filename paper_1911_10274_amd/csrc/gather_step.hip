@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateI
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
     float fx = 0.f, fy = 0.f, fz = 0.f;
     const int64_t n = step_index(sc);
-    const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), (double)n * sc.dt64 + sc.t_add};
+    const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), step_time(n, sc.dt64, sc.t_add)};
     sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE, yield_mode<YIELD, MODE>>(
         g, base, slice_width(g, i), xi, ui, vi, ck, sc, [&](int64_t e) { return stream_load(g.nbr + e); },
         [&](int j, float4 &xj, float4 &uj, float4 &vj) {
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
     float fx = 0.f, fy = 0.f, fz = 0.f;
     const int64_t n = step_index(sc);
-    const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), (double)n * sc.dt64 + sc.t_add};
+    const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), step_time(n, sc.dt64, sc.t_add)};
     sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE, yield_mode<YIELD, MODE>>(
         g, base, slice_width(g, i), xi, ui, vi, ck, sc, [&](int64_t e) { return (int)stream_load(g.nbr_local + e); },
         [&](int q, float4 &xj, float4 &uj, float4 &vj) {

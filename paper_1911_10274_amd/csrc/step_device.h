@@ -49,6 +49,15 @@ struct Clock {
     double t;
 };
 
+// The FP64 time of step n plus an offset (an RK4 stage's c dt), rounded the
+// same way by every kernel (product, then sum; no fused multiply-add), so
+// every engine folds the wave law's period at the same instants.
+__device__ __forceinline__ double step_time(int64_t n, double dt64, double add)
+{
+#pragma clang fp contract(off)
+    return (double)n * dt64 + add;
+}
+
 // Actuation factor of one incidence: the rest length is L0 (1 + factor).
 // Phasor law: C sin(omega t) + S cos(omega t) = amp sin(omega t + phase).
 // Wave law (Sec. IV-B, Eqs. 3-4): amp sin(omega tau) with
@@ -228,64 +237,105 @@ __device__ __forceinline__ bool finite4(const float4 &u, const float4 &v)
     return isfinite(u.x) && isfinite(u.y) && isfinite(u.z) && isfinite(v.x) && isfinite(v.y) && isfinite(v.z);
 }
 
-// The epilogue of one stage for mass i: (xi, ui, vi) is the stage state the
-// force (fx, fy, fz) was evaluated at.  Returns false if a new state is not
-// finite.
+// Pieces of the stage updates, shared by every engine so that all of them
+// give identical bits.
+
+// RK4 running sums of w_s v_s and w_s a_s, w = 1, 2, 2, 1 (times dt / 6):
+// stage 1 starts them.
+__device__ __forceinline__ void rk_sums(int stage, const float4 &vi, const float3 &a, float4 &su, float4 &sv)
+{
+#pragma clang fp contract(off)
+    if (stage == kStageRk1) {
+        su = make_float4(vi.x, vi.y, vi.z, 0.f);
+        sv = make_float4(a.x, a.y, a.z, 0.f);
+        return;
+    }
+    const float w = stage == kStageRk4 ? 1.f : 2.f;
+    su = make_float4(fmaf(w, vi.x, su.x), fmaf(w, vi.y, su.y), fmaf(w, vi.z, su.z), 0.f);
+    sv = make_float4(fmaf(w, a.x, sv.x), fmaf(w, a.y, sv.y), fmaf(w, a.z, sv.z), 0.f);
+}
+
+// The state RK4 stage `stage` (1-3) hands to the next: base + c dt (v_s, a_s),
+// c = 1/2, 1/2, 1.
+__device__ __forceinline__ void rk_next(int stage, const float4 &ub, const float4 &vb, const float4 &vi,
+                                        const float3 &a, float dt, float4 &uo, float4 &vo)
+{
+#pragma clang fp contract(off)
+    const float c = stage == kStageRk1 + 2 ? dt : 0.5f * dt;
+    uo = make_float4(fmaf(c, vi.x, ub.x), fmaf(c, vi.y, ub.y), fmaf(c, vi.z, ub.z), ub.w);
+    vo = make_float4(fmaf(c, a.x, vb.x), fmaf(c, a.y, vb.y), fmaf(c, a.z, vb.z), 0.f);
+}
+
+// RK4's new state from the base state and the complete sums, then friction
+// (zb: the step's starting height).
+__device__ __forceinline__ void rk_final(const float4 &ub, const float4 &vb, const float4 &su, const float4 &sv,
+                                         float zb, const StepConsts &sc, float4 &u, float4 &v)
+{
+#pragma clang fp contract(off)
+    const float h6 = sc.dt / 6.f;
+    u = make_float4(fmaf(h6, su.x, ub.x), fmaf(h6, su.y, ub.y), fmaf(h6, su.z, ub.z), ub.w);
+    v = make_float4(fmaf(h6, sv.x, vb.x), fmaf(h6, sv.y, vb.y), fmaf(h6, sv.z, vb.z), 0.f);
+    friction_after(zb, ub.w, sc, u, v);
+}
+
+// Verlet's kick of a drifted mass (ui, vi) = (x', v') with its new
+// acceleration a, then friction (zb: the step's starting height).
+__device__ __forceinline__ void verlet_kick(const float4 &ui, const float4 &vi, const float3 &a, float zb,
+                                            const StepConsts &sc, float4 &u, float4 &v)
+{
+#pragma clang fp contract(off)
+    const float half = 0.5f * sc.dt;
+    u = ui;
+    v = vi;
+    if (ui.w != 0.f) {
+        v = make_float4(fmaf(half, a.x, vi.x), fmaf(half, a.y, vi.y), fmaf(half, a.z, vi.z), 0.f);
+        friction_after(zb, ui.w, sc, u, v);
+    }
+}
+
+// The epilogue of one stage for mass i on the per-step engines: (xi, ui, vi)
+// is the stage state the force (fx, fy, fz) was evaluated at.  Returns false
+// if a new state is not finite.
 __device__ __forceinline__ bool stage_update(int64_t i, const float4 &xi, const float4 &ui, const float4 &vi,
                                              float fx, float fy, float fz, const StateIO &io, const StepConsts &sc)
 {
-#pragma clang fp contract(off)
     const float3 a = smooth_accel(xi, ui, fx, fy, fz, sc);
-    const float im = ui.w;
-    const float dt = sc.dt, half = 0.5f * sc.dt;
     if (sc.stage == kStageVerletInit) {
         io.A[i] = make_float4(a.x, a.y, a.z, 0.f);
         return true;
     }
     if (sc.stage == kStageVerletKick) {
         // (ui, vi) = (x', v'), drifted from the step's starting state U_base
-        const float zb = xi.z + io.U_base[i].z;
-        float4 u = ui, v = vi;
-        if (im != 0.f) {
-            v = make_float4(fmaf(half, a.x, vi.x), fmaf(half, a.y, vi.y), fmaf(half, a.z, vi.z), 0.f);
-            friction_after(zb, im, sc, u, v);
-        }
+        float4 u, v;
+        verlet_kick(ui, vi, a, xi.z + io.U_base[i].z, sc, u, v);
         io.U_out[i] = u;
         io.V_out[i] = v;
         io.A[i] = make_float4(a.x, a.y, a.z, 0.f);
         return finite4(u, v);
     }
-    // RK4: sums of w_s v_s and w_s a_s, w = 1, 2, 2, 1 (times dt / 6)
     const float4 ub = io.U_base[i], vb = io.V_base[i];
-    if (im == 0.f) {
+    if (ui.w == 0.f) {  // pinned
         io.U_out[i] = ub;
         io.V_out[i] = vb;
         return true;
     }
-    float4 su, sv;
-    if (sc.stage == kStageRk1) {
-        su = make_float4(vi.x, vi.y, vi.z, 0.f);
-        sv = make_float4(a.x, a.y, a.z, 0.f);
-    } else {
-        const float w = sc.stage == kStageRk4 ? 1.f : 2.f;
+    float4 su = make_float4(0.f, 0.f, 0.f, 0.f), sv = su;
+    if (sc.stage != kStageRk1) {
         su = io.sum_u[i];
         sv = io.sum_v[i];
-        su = make_float4(fmaf(w, vi.x, su.x), fmaf(w, vi.y, su.y), fmaf(w, vi.z, su.z), 0.f);
-        sv = make_float4(fmaf(w, a.x, sv.x), fmaf(w, a.y, sv.y), fmaf(w, a.z, sv.z), 0.f);
     }
+    rk_sums(sc.stage, vi, a, su, sv);
     if (sc.stage != kStageRk4) {
         io.sum_u[i] = su;
         io.sum_v[i] = sv;
-        // next stage state: base + c dt (v_s, a_s), c = 1/2, 1/2, 1
-        const float c = sc.stage == kStageRk1 + 2 ? dt : half;
-        io.U_out[i] = make_float4(fmaf(c, vi.x, ub.x), fmaf(c, vi.y, ub.y), fmaf(c, vi.z, ub.z), im);
-        io.V_out[i] = make_float4(fmaf(c, a.x, vb.x), fmaf(c, a.y, vb.y), fmaf(c, a.z, vb.z), 0.f);
+        float4 uo, vo;
+        rk_next(sc.stage, ub, vb, vi, a, sc.dt, uo, vo);
+        io.U_out[i] = uo;
+        io.V_out[i] = vo;
         return true;
     }
-    const float h6 = sc.dt / 6.f;
-    float4 u = make_float4(fmaf(h6, su.x, ub.x), fmaf(h6, su.y, ub.y), fmaf(h6, su.z, ub.z), im);
-    float4 v = make_float4(fmaf(h6, sv.x, vb.x), fmaf(h6, sv.y, vb.y), fmaf(h6, sv.z, vb.z), 0.f);
-    friction_after(xi.z + ub.z, im, sc, u, v);
+    float4 u, v;
+    rk_final(ub, vb, su, sv, xi.z + ub.z, sc, u, v);
     io.U_out[i] = u;
     io.V_out[i] = v;
     return finite4(u, v);

@@ -165,8 +165,6 @@ static int check_params(const titan_params *p)
         return fail(TITAN_EINVAL, "wave_period must be finite and > 0 (got %g)", p->wave_period);
     if (p->integrator < TITAN_INTEG_EULER || p->integrator > TITAN_INTEG_RK4)
         return fail(TITAN_EINVAL, "unknown integrator %d", p->integrator);
-    if (p->integrator != TITAN_INTEG_EULER && p->engine == TITAN_ENGINE_BATCHED)
-        return fail(TITAN_EINVAL, "the batched engine steps with the Euler integrator only");
     if (p->graph_steps < 0 || p->graph_steps > 4096 || (p->graph_steps & 1))
         return fail(TITAN_EINVAL, "graph_steps must be 0 or an even number up to 4096 (got %d)", p->graph_steps);
     return TITAN_OK;
@@ -613,17 +611,21 @@ extern "C" int titan_set_params(titan_sim *s, const titan_params *p)
     if (s->finalized && p->actuation != s->params.actuation)
         return fail(TITAN_ESTATE, "the actuation law can only be chosen before the first step");
     const int32_t engine = s->finalized ? s->params.engine : p->engine;
-    if (s->finalized && engine == TITAN_ENGINE_BATCHED && p->integrator != TITAN_INTEG_EULER)
-        return fail(TITAN_ESTATE, "the batched engine steps with the Euler integrator only");
     s->params = *p;
     s->params.engine = engine;
-    if (s->finalized)
+    if (s->finalized) {
         invalidate_step_cache(s);
-    if (s->finalized) {  // the plain engines run the other integrators
-        if (p->integrator != TITAN_INTEG_EULER && s->engine == TITAN_ENGINE_BATCHED)
+        // groups too large for the batched Verlet / RK4 kernels step with the
+        // per-step engine
+        if (s->engine == TITAN_ENGINE_BATCHED && p->integrator != TITAN_INTEG_EULER &&
+            !batch_integ_fits(batch_layout(s), p->integrator)) {
+            if (engine == TITAN_ENGINE_BATCHED)
+                return fail(TITAN_ESTATE, "the batched engine cannot run this integrator on this system");
             s->engine = s->tiled ? TITAN_ENGINE_TILED : TITAN_ENGINE_GATHER;
-        else if (p->integrator == TITAN_INTEG_EULER && s->batch && s->batch_step)
+        } else if (s->batch && s->batch_step && engine != TITAN_ENGINE_GATHER && engine != TITAN_ENGINE_TILED &&
+                   (p->integrator == TITAN_INTEG_EULER || batch_integ_fits(batch_layout(s), p->integrator))) {
             s->engine = TITAN_ENGINE_BATCHED;
+        }
     }
     return TITAN_OK;
 }

@@ -136,6 +136,14 @@ struct BatchLayout {
     int32_t max_group;           // masses of the largest group
 };
 
+// Velocity Verlet / RK4 steps on the batched layout (batch_integ.hip):
+// nsteps steps from io.U_in / V_in into io.U_out / V_out; Verlet reads its
+// carried acceleration from io.A_in (acc_valid) or computes it, and writes it
+// to io.A.  batch_integ_fits: whether the layout's groups fit the kernels.
+bool batch_integ_fits(const BatchLayout &b, int integ);
+hipError_t launch_batch_integ(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc,
+                              int nsteps, int integ, int acc_valid, hipStream_t stream);
+
 // Threads per workgroup of the batched kernel (variants the tuner picks from).
 constexpr int kBatchThreadChoices[] = {256, 512, 1024};
 

@@ -155,6 +155,11 @@ void destroy_engines(titan_sim *s);
 // the layout otherwise (in both cases nothing is written and the layouts must
 // be rebuilt); or an error code (< 0).
 int insert_springs(titan_sim *s, int64_t first, int64_t count);
+// The batched engine's layout (s->batch must be set).
+const BatchLayout &batch_layout(const titan_sim *s);
+// Allocate the staged integrators' buffers for the current masses (RK4's
+// stage states and sums, or Verlet's acceleration pair).
+int ensure_stage_buffers(titan_sim *s, bool rk4);
 // Something the step launches depend on changed: a carried Verlet
 // acceleration is recomputed and captured step loops are captured again.
 void invalidate_step_cache(titan_sim *s);

@@ -39,10 +39,10 @@ def _oparams(integ, dt=DT, omega=OMEGA, **kw):
 
 
 @pytest.mark.parametrize("integ", ["verlet", "rk4"])
-@pytest.mark.parametrize("engine", ["gather", "tiled"])
+@pytest.mark.parametrize("engine", ["gather", "tiled", "batched"])
 def test_first_10_steps_match_the_oracle(integ, engine):
     T = _T()
-    eng = T.ENGINE_GATHER if engine == "gather" else T.ENGINE_TILED
+    eng = {"gather": T.ENGINE_GATHER, "tiled": T.ENGINE_TILED, "batched": T.ENGINE_BATCHED}[engine]
     sc = scenes.jittered_actuated_lattice(n=10, seed=3)
     sim = T.sim_from_scene(sc, _params(integ, eng))
     gpu = gpu_series(sim, 10)
@@ -106,20 +106,41 @@ def test_worm_wave_law(integ):
 
 @pytest.mark.parametrize("integ", ["verlet", "rk4"])
 def test_engines_agree_bitwise(integ):
+    """Gather, tiled and batched engines: identical bits, with breakable
+    springs and an edit mid-run (Verlet restarts its acceleration there); the
+    batched engine runs its steps in chunks across the edit."""
     T = _T()
     sc = scenes.jittered_actuated_lattice(n=11, seed=5)
     sc = dict(sc, **{"yield": np.full(sc["ends"].shape[0], 150.0, np.float32)})
     outs = []
-    for eng in (T.ENGINE_GATHER, T.ENGINE_TILED):
+    for eng in (T.ENGINE_GATHER, T.ENGINE_TILED, T.ENGINE_BATCHED):
         sim = T.sim_from_scene(sc, _params(integ, eng))
         sim.step(120)
-        sim.remove_springs([5, 77, 901])  # Verlet restarts its acceleration here
-        sim.step(180)
+        sim.remove_springs([5, 77, 901])
+        sim.step(100)
+        sim.step(80)
+        assert sim.info()["engine"] == eng
         outs.append(sim.get_state(displacement=True)[:2] + (sim.get_forces(), sim.get_broken()))
         sim.close()
     assert outs[0][3].any()
-    for a, b in zip(outs[0], outs[1]):
-        assert np.array_equal(a, b)
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("integ", ["verlet", "rk4"])
+def test_batched_wave_law_agrees_with_tiled(integ):
+    T = _T()
+    sc = scenes.worm_batch(3, nx=12)
+    outs = []
+    for eng in (T.ENGINE_TILED, T.ENGINE_BATCHED):
+        tp = _params(integ, eng, dt=1e-4, omega=20.0, actuation=T.ACT_WAVE, wave_period=1.0)
+        sim = T.sim_from_scene(sc, tp)
+        sim.step(1500)  # crosses period boundaries of several offsets
+        assert sim.info()["engine"] == eng
+        outs.append(sim.get_state(displacement=True)[:2])
+        sim.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
 def test_verlet_restart_only_when_something_changed():
@@ -142,12 +163,12 @@ def test_verlet_restart_only_when_something_changed():
 def test_integrator_rules():
     T = _T()
     sc = scenes.lattice(4, origin=(0.0, 0.0, 0.5))
-    with pytest.raises(T.TitanError) as ei:
-        T.sim_from_scene(sc, _params("rk4", T.ENGINE_BATCHED))
-    assert ei.value.code == T.EINVAL
+    sim = T.sim_from_scene(sc, _params("rk4", T.ENGINE_BATCHED))
+    sim.step(3)
+    assert sim.info()["engine"] == T.ENGINE_BATCHED
+    sim.close()
     sim = T.sim_from_scene(sc, _params("rk4", T.ENGINE_AUTO))
     sim.step(3)
-    assert sim.info()["engine"] != T.ENGINE_BATCHED
     with pytest.raises(T.TitanError) as ei:
         sim.rollout_grad(4, 2)
     assert ei.value.code == T.ESTATE
