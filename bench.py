@@ -173,11 +173,31 @@ def bench_batched(T, robots_n: int, steps: int, loop_sample: int):
         sim.finalize()
         return sim
 
+    def other_integrators(sim, engine, isteps=200):
+        """Verlet and RK4 on the same sim (switched by set_params, same layout)."""
+        out = {}
+        for name, integ in (("verlet", T.INTEG_VERLET), ("rk4", T.INTEG_RK4)):
+            tp = T.Params(dt=1e-4, gravity=(0.0, 0.0, -9.81), ground=True, ground_k=1e5, friction_mu=0.5,
+                          omega=2 * math.pi * 2, engine=engine, integrator=integ)
+            try:
+                sim.set_params(tp)
+            except T.TitanError as e:
+                out[name] = {"not_run": str(e)}
+                continue
+            sim.step(5)
+            sim.sync()
+            ims = _timed_steps(sim, isteps, stream)
+            out[name] = {"ms_per_step": ims / isteps, "engine": {T.ENGINE_BATCHED: "batched",
+                                                                  T.ENGINE_TILED: "tiled",
+                                                                  T.ENGINE_GATHER: "gather"}[sim.info()["engine"]]}
+        return out
+
     sim = mk(T.ENGINE_BATCHED)
     info = sim.info()
     sim.step(20)
     sim.sync()
     ms = _timed_steps(sim, steps, stream)
+    integ_batched = other_integrators(sim, T.ENGINE_BATCHED)
     sim.close()
     res.update(value=ns * steps / (ms / 1e3), ms_per_step=ms / steps, engine="batched",
                workgroup_threads=info["batch_threads"])
@@ -185,7 +205,9 @@ def bench_batched(T, robots_n: int, steps: int, loop_sample: int):
     sim.step(20)
     sim.sync()
     ms_plain = _timed_steps(sim, steps, stream)
+    integ_plain = other_integrators(sim, T.ENGINE_TILED)
     sim.close()
+    res["integrators"] = {"batched": integ_batched, "plain": integ_plain, "steps": 200}
     res["plain_same_system"] = {"value": ns * steps / (ms_plain / 1e3), "ms_per_step": ms_plain / steps,
                                 "engine": "tiled"}
 
