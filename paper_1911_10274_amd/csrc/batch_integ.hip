@@ -243,6 +243,13 @@ bool batch_integ_fits(const BatchLayout &b, int integ)
     return integ == TITAN_INTEG_VERLET ? per <= 8 : per <= 4;
 }
 
+bool batch_integ_preferred(const BatchLayout &b)
+{
+    // at most two masses per thread: beyond, the serial masses per thread and
+    // the extra barriers cost more than the per-step engines' launches
+    return (b.max_group + kIntegThreads - 1) / kIntegThreads <= 2;
+}
+
 hipError_t launch_batch_integ(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc,
                               int nsteps, int integ, int acc_valid, hipStream_t stream)
 {

@@ -475,7 +475,9 @@ int build_engines(titan_sim *s)
                                       "%d masses is too large)", batch_layout(s).max_group);
         s->batch_step = false;
     }
-    if (s->batch && s->batch_step)
+    const bool integ_ok = s->params.integrator == TITAN_INTEG_EULER || want == TITAN_ENGINE_BATCHED ||
+                          (s->batch && batch_integ_preferred(batch_layout(s)));
+    if (s->batch && s->batch_step && integ_ok)
         s->engine = TITAN_ENGINE_BATCHED;
     else if (want == TITAN_ENGINE_BATCHED)
         return fail(TITAN_EINVAL, "the batched engine cannot run this system (a body does not fit in LDS)");

@@ -611,21 +611,27 @@ extern "C" int titan_set_params(titan_sim *s, const titan_params *p)
     if (s->finalized && p->actuation != s->params.actuation)
         return fail(TITAN_ESTATE, "the actuation law can only be chosen before the first step");
     const int32_t engine = s->finalized ? s->params.engine : p->engine;
+    // which engine steps under the new integrator (decided before anything
+    // changes, so that a refused call leaves the sim as it was)
+    int32_t new_engine = s->engine;
+    if (s->finalized && s->batch && s->batch_step) {
+        const bool euler = p->integrator == TITAN_INTEG_EULER;
+        const bool fits = euler || batch_integ_fits(batch_layout(s), p->integrator);
+        if (engine == TITAN_ENGINE_BATCHED) {
+            if (!fits)
+                return fail(TITAN_ESTATE, "the batched engine cannot run this integrator on this system");
+            new_engine = TITAN_ENGINE_BATCHED;
+        } else {  // AUTO: the batched Verlet / RK4 kernels for small groups only
+            new_engine = (euler || (fits && batch_integ_preferred(batch_layout(s))))
+                             ? TITAN_ENGINE_BATCHED
+                             : (s->tiled ? TITAN_ENGINE_TILED : TITAN_ENGINE_GATHER);
+        }
+    }
     s->params = *p;
     s->params.engine = engine;
     if (s->finalized) {
         invalidate_step_cache(s);
-        // groups too large for the batched Verlet / RK4 kernels step with the
-        // per-step engine
-        if (s->engine == TITAN_ENGINE_BATCHED && p->integrator != TITAN_INTEG_EULER &&
-            !batch_integ_fits(batch_layout(s), p->integrator)) {
-            if (engine == TITAN_ENGINE_BATCHED)
-                return fail(TITAN_ESTATE, "the batched engine cannot run this integrator on this system");
-            s->engine = s->tiled ? TITAN_ENGINE_TILED : TITAN_ENGINE_GATHER;
-        } else if (s->batch && s->batch_step && engine != TITAN_ENGINE_GATHER && engine != TITAN_ENGINE_TILED &&
-                   (p->integrator == TITAN_INTEG_EULER || batch_integ_fits(batch_layout(s), p->integrator))) {
-            s->engine = TITAN_ENGINE_BATCHED;
-        }
+        s->engine = new_engine;
     }
     return TITAN_OK;
 }

@@ -141,6 +141,9 @@ struct BatchLayout {
 // carried acceleration from io.A_in (acc_valid) or computes it, and writes it
 // to io.A.  batch_integ_fits: whether the layout's groups fit the kernels.
 bool batch_integ_fits(const BatchLayout &b, int integ);
+// Whether TITAN_ENGINE_AUTO steps Verlet / RK4 with the batched kernels (small
+// groups) rather than the per-step engines.
+bool batch_integ_preferred(const BatchLayout &b);
 hipError_t launch_batch_integ(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc,
                               int nsteps, int integ, int acc_valid, hipStream_t stream);
 

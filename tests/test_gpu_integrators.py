@@ -180,3 +180,29 @@ def test_integrator_rules():
     p, v, s = sim.get_state()
     assert s == 9 and np.isfinite(p).all() and np.isfinite(v).all()
     sim.close()
+
+
+def test_batched_engine_rules_for_large_groups():
+    """A 13^3 body (2,197 masses) fits the batched Verlet kernels but not the
+    batched RK4 ones: an explicit request for RK4 there is refused and leaves
+    the sim stepping as before; AUTO steps Verlet on such groups with a
+    per-step engine (the batched Verlet kernels pay for small groups)."""
+    T = _T()
+    sc = scenes.lattice(13, origin=(0.0, 0.0, 0.5))
+    sim = T.sim_from_scene(sc, _params("verlet", T.ENGINE_BATCHED))
+    sim.step(3)
+    assert sim.info()["engine"] == T.ENGINE_BATCHED
+    with pytest.raises(T.TitanError) as ei:
+        sim.set_params(_params("rk4", T.ENGINE_BATCHED))
+    assert ei.value.code == T.ESTATE
+    sim.step(3)
+    p, v, s = sim.get_state()
+    assert s == 6 and np.isfinite(p).all() and sim.info()["engine"] == T.ENGINE_BATCHED
+    sim.close()
+    with pytest.raises(T.TitanError) as ei:
+        T.sim_from_scene(sc, _params("rk4", T.ENGINE_BATCHED)).step(1)
+    assert ei.value.code == T.EINVAL
+    auto = T.sim_from_scene(sc, _params("verlet", T.ENGINE_AUTO))
+    auto.step(2)
+    assert auto.info()["engine"] in (T.ENGINE_TILED, T.ENGINE_GATHER)
+    auto.close()
