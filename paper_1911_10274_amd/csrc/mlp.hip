@@ -45,7 +45,7 @@ __device__ __forceinline__ float gelu_grad(float z)
     return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
-enum Epi { EPI_BIAS_GELU = 1, EPI_BIAS = 2, EPI_GELU_BWD = 3, EPI_F32 = 4 };
+enum Epi { EPI_BIAS_GELU = 1, EPI_BIAS = 2, EPI_GELU_BWD = 3, EPI_F32 = 4, EPI_WGRAD = 5 };
 
 struct GemmEpi {
     const float *bias;  // [N]
@@ -53,6 +53,7 @@ struct GemmEpi {
     const float *Zin;   // fp32 pre-activation read by EPI_GELU_BWD, row stride ldz
     uint16_t *Yb;       // bf16 out, row stride ldy
     int ldz, ldy;
+    float *db;          // EPI_WGRAD: column ldz (the activations' ones column) -> db[row]
 };
 
 constexpr int BM = 64, BN = 64, BK = 64, LDK = BK + 8;
@@ -69,6 +70,13 @@ __device__ __forceinline__ void epi_store(int i, int j, float v, const GemmEpi &
         ep.Z[(int64_t)i * ep.ldz + j] = v + ep.bias[j];
     } else if (EPI == EPI_GELU_BWD) {
         ep.Yb[(int64_t)i * ep.ldy + j] = f2bf(v * gelu_grad(ep.Zin[(int64_t)i * ep.ldz + j]));
+    } else if (EPI == EPI_WGRAD) {
+        // dW = dz^T x over the activations and their ones column: the last
+        // column is the column sum of dz, the bias gradient
+        if (j < ep.ldz)
+            ep.Z[(int64_t)i * ep.ldz + j] = v;
+        else
+            ep.db[i] = v;
     } else {
         ep.Z[(int64_t)i * ep.ldz + j] = v;
     }
@@ -471,14 +479,36 @@ __global__ void to_bf16_kernel(const float *x, uint16_t *y, int64_t n)
         y[q] = f2bf(x[q]);
 }
 
+// Rows of n floats to bf16 rows of stride ld.
+__global__ void to_bf16_rows_kernel(const float *x, uint16_t *y, int64_t rows, int n, int ld)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < rows * n)
+        y[(q / n) * ld + q % n] = f2bf(x[q]);
+}
+
+// The padding of activation rows: column n = 1.0 (the ones column that turns
+// the weight-gradient product into the bias gradient too), columns n+1 .. ld-1
+// zero.  Written once per allocation; the GEMMs write only columns < n.
+__global__ void activation_pad_kernel(uint16_t *x, int64_t rows, int n, int ld)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int pad = ld - n;
+    if (q < rows * pad) {
+        const int64_t r = q / pad;
+        const int c = n + (int)(q % pad);
+        x[r * ld + c] = c == n ? (uint16_t)0x3F80 : (uint16_t)0;
+    }
+}
+
 __global__ void gather_rows_kernel(const uint16_t *X, const float *Y, const int64_t *idx, int B, int in, int out,
-                                   uint16_t *xb, float *yb)
+                                   uint16_t *xb, int ldx, float *yb)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nx = (int64_t)B * in;
     if (q < nx) {
         const int64_t b = q / in, c = q % in;
-        xb[q] = X[idx[b] * in + c];
+        xb[b * ldx + c] = X[idx[b] * in + c];
     } else if (q < nx + (int64_t)B * out) {
         const int64_t r = q - nx, b = r / out, c = r % out;
         yb[r] = Y[idx[b] * out + c];
@@ -507,40 +537,6 @@ __global__ __launch_bounds__(256) void mse_kernel(const float *out, const float 
     }
     if (t == 0)
         *loss = red[0] / (float)n;
-}
-
-// Bias gradient db[j] = sum over rows b of dz[b, j], in two passes with a
-// fixed summation order (so the result does not depend on scheduling):
-// workgroup (x, y) sums rows [y*kBiasRows, (y+1)*kBiasRows) of 64 columns,
-// four row phases per column combined in order; then each column adds its
-// partial sums in row-chunk order.
-constexpr int kBiasRows = 64;
-
-__global__ __launch_bounds__(256) void bias_partial_kernel(const uint16_t *dz, int B, int N, float *part)
-{
-    __shared__ float red[4][64];
-    const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
-    const int j = blockIdx.x * 64 + c;
-    const int r0 = blockIdx.y * kBiasRows, r1 = min(B, r0 + kBiasRows);
-    float acc = 0.f;
-    if (j < N)
-        for (int b = r0 + ph; b < r1; b += 4)
-            acc += bf2f(dz[(int64_t)b * N + j]);
-    red[ph][c] = acc;
-    __syncthreads();
-    if (ph == 0 && j < N)
-        part[(int64_t)blockIdx.y * N + j] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
-}
-
-__global__ void bias_final_kernel(const float *part, int chunks, int N, float *db)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N)
-        return;
-    float acc = 0.f;
-    for (int y = 0; y < chunks; ++y)
-        acc += part[(int64_t)y * N + j];
-    db[j] = acc;
 }
 
 // Where the weight matrices sit in the flat parameters and in the bf16 copy
@@ -609,11 +605,11 @@ struct titan_mlp {
     float *Y = nullptr;
     // workspace for batches up to cap
     int cap = 0;
-    std::vector<uint16_t *> xs;  // x_l, l = 0..L-1 (bf16)
+    std::vector<uint16_t *> xs;  // x_l, l = 0..L-1 (bf16), row stride xld[l]: dims[l] values, a ones column, zeros
+    std::vector<int> xld;
     std::vector<float *> zs;     // z_l (fp32)
     uint16_t *dz[2] = {nullptr, nullptr};
     float *yb = nullptr;
-    float *bpart = nullptr;  // bias-gradient partial sums, ceil(cap / kBiasRows) x widest layer
     float *gpart = nullptr;  // split-K partial sums of the GEMMs
     int64_t gpart_cap = 0;   // floats in gpart
     int64_t *idx = nullptr;
@@ -672,18 +668,23 @@ static int ensure_cap(titan_mlp *m, int B)
         mlp_free(m, p);
     for (auto *p : m->zs)
         mlp_free(m, p);
-    for (auto *p : {(void *)m->dz[0], (void *)m->dz[1], (void *)m->yb, (void *)m->idx, (void *)m->bpart,
-                    (void *)m->gpart})
+    for (auto *p : {(void *)m->dz[0], (void *)m->dz[1], (void *)m->yb, (void *)m->idx, (void *)m->gpart})
         if (p)
             mlp_free(m, p);
     m->xs.assign(m->L(), nullptr);
     m->zs.assign(m->L(), nullptr);
+    m->xld.assign(m->L(), 0);
     int maxd = 0;
     for (int d : m->dims)
         maxd = std::max(maxd, d);
     for (int l = 0; l < m->L(); ++l) {
-        if (int rc = mlp_alloc(m, sizeof(uint16_t) * (size_t)B * m->dims[l], (void **)&m->xs[l]))
+        m->xld[l] = (m->dims[l] + 1 + 7) / 8 * 8;  // room for the ones column; 16-byte rows
+        if (int rc = mlp_alloc(m, sizeof(uint16_t) * (size_t)B * m->xld[l], (void **)&m->xs[l]))
             return rc;
+        const int64_t pad = (int64_t)B * (m->xld[l] - m->dims[l]);
+        hipLaunchKernelGGL(activation_pad_kernel, dim3((unsigned)((pad + 255) / 256)), dim3(256), 0, m->stream,
+                           m->xs[l], (int64_t)B, m->dims[l], m->xld[l]);
+        MLP_TRY(hipGetLastError());
         if (int rc = mlp_alloc(m, sizeof(float) * (size_t)B * m->dims[l + 1], (void **)&m->zs[l]))
             return rc;
     }
@@ -694,9 +695,7 @@ static int ensure_cap(titan_mlp *m, int B)
         return rc;
     if (int rc = mlp_alloc(m, sizeof(int64_t) * (size_t)B, (void **)&m->idx))
         return rc;
-    if (int rc = mlp_alloc(m, sizeof(float) * (size_t)((B + kBiasRows - 1) / kBiasRows) * maxd, (void **)&m->bpart))
-        return rc;
-    m->gpart_cap = 4 * std::max<int64_t>((int64_t)B * maxd, (int64_t)maxd * maxd);
+    m->gpart_cap = 4 * std::max<int64_t>((int64_t)B * maxd, (int64_t)maxd * (maxd + 1));
     if (int rc = mlp_alloc(m, sizeof(float) * (size_t)m->gpart_cap, (void **)&m->gpart))
         return rc;
     m->cap = B;
@@ -723,12 +722,12 @@ static int forward(titan_mlp *m, int B)
         ep.ldz = out;
         if (l < L - 1) {
             ep.Yb = m->xs[l + 1];
-            ep.ldy = out;
-            MLP_TRY((gemm<false, true, EPI_BIAS_GELU>(B, out, in, m->xs[l], in, m->Wb + m->wboff[l], in, ep, m->stream,
-                                                      m->gpart, m->gpart_cap)));
+            ep.ldy = m->xld[l + 1];
+            MLP_TRY((gemm<false, true, EPI_BIAS_GELU>(B, out, in, m->xs[l], m->xld[l], m->Wb + m->wboff[l], in, ep,
+                                                      m->stream, m->gpart, m->gpart_cap)));
         } else {
-            MLP_TRY((gemm<false, true, EPI_BIAS>(B, out, in, m->xs[l], in, m->Wb + m->wboff[l], in, ep, m->stream,
-                                                 m->gpart, m->gpart_cap)));
+            MLP_TRY((gemm<false, true, EPI_BIAS>(B, out, in, m->xs[l], m->xld[l], m->Wb + m->wboff[l], in, ep,
+                                                 m->stream, m->gpart, m->gpart_cap)));
         }
     }
     return TITAN_OK;
@@ -748,18 +747,13 @@ static int backward(titan_mlp *m, int B, float *loss_dev)
     for (int l = L - 1; l >= 0; --l) {
         const int in = m->dims[l], out = m->dims[l + 1];
         uint16_t *dz = m->dz[cur];
+        // dW and db in one product: dz^T [x_l, 1]
         GemmEpi ew{};
         ew.Z = m->G + m->woff[l];
         ew.ldz = in;
-        MLP_TRY((gemm<true, false, EPI_F32>(out, in, B, dz, out, m->xs[l], in, ew, m->stream, m->gpart,
-                                            m->gpart_cap)));
-        const int chunks = (B + kBiasRows - 1) / kBiasRows;
-        hipLaunchKernelGGL(bias_partial_kernel, dim3((out + 63) / 64, chunks), dim3(256), 0, m->stream, dz, B, out,
-                           m->bpart);
-        MLP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(bias_final_kernel, dim3((out + 255) / 256), dim3(256), 0, m->stream, m->bpart, chunks,
-                           out, m->G + m->boff[l]);
-        MLP_TRY(hipGetLastError());
+        ew.db = m->G + m->boff[l];
+        MLP_TRY((gemm<true, false, EPI_WGRAD>(out, in + 1, B, dz, out, m->xs[l], m->xld[l], ew, m->stream, m->gpart,
+                                              m->gpart_cap)));
         if (l > 0) {
             GemmEpi ed{};
             ed.Zin = m->zs[l - 1];
@@ -781,7 +775,9 @@ static int upload_batch_f32(titan_mlp *m, int B, const float *X, const float *Y)
     if (int rc = mlp_alloc(m, sizeof(float) * (size_t)B * in, (void **)&tmp))
         return rc;
     MLP_TRY(hipMemcpyAsync(tmp, X, sizeof(float) * (size_t)B * in, hipMemcpyHostToDevice, m->stream));
-    MLP_TRY(launch1d(to_bf16_kernel, tmp, m->xs[0], (int64_t)B * in, m->stream));
+    hipLaunchKernelGGL(to_bf16_rows_kernel, dim3((unsigned)(((int64_t)B * in + 255) / 256)), dim3(256), 0,
+                       m->stream, tmp, m->xs[0], (int64_t)B, in, m->xld[0]);
+    MLP_TRY(hipGetLastError());
     if (Y)
         MLP_TRY(hipMemcpyAsync(m->yb, Y, sizeof(float) * (size_t)B * m->dims.back(), hipMemcpyHostToDevice,
                                m->stream));
@@ -959,7 +955,7 @@ extern "C" int titan_mlp_train(titan_mlp *m, int64_t nsteps, int32_t batch, cons
     for (int64_t s = 0; s < nsteps; ++s) {
         const int64_t tot = (int64_t)batch * (in + out);
         hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, m->stream, m->X,
-                           m->Y, didx + s * batch, batch, in, out, m->xs[0], m->yb);
+                           m->Y, didx + s * batch, batch, in, out, m->xs[0], m->xld[0], m->yb);
         MLP_TRY(hipGetLastError());
         if (int rc = backward(m, batch, dloss + s))
             return rc;
