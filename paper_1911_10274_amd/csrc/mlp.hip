@@ -456,7 +456,7 @@ hipError_t gemm(int M, int N, int K, const uint16_t *A, int lda, const uint16_t 
     const int kt = std::max(1, (K + BK - 1) / BK);
     int splits = 1;
     if (part && tiles < kGemmTarget)
-        splits = std::max(1, std::min(kGemmTarget / tiles, kt / 2));
+        splits = std::max(1, std::min((kGemmTarget + tiles - 1) / tiles, kt / 2));  // at least the target
     while (splits > 1 && (int64_t)splits * M * N > part_cap)
         --splits;
     const int kslice = ((kt + splits - 1) / splits) * BK;
