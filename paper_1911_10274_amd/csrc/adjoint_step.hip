@@ -272,21 +272,47 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
                     const float4 xi = sX[q], ui = sU[q], vi = sV[q], mi = sM[q];
                     const int64_t base = g.slice_off[i >> 6] + (i & 63);
                     const int width = slice_width(g, i);
-                    for (int w = 0; w < width; ++w) {
-                        const int64_t e = base + (int64_t)w * kSlice;
-                        const int jr = nbr(e);
-                        const SpringConst p = load_const<ACT, DAMPV, REST, false>(g, e);
+                    // one slot: its adjoint terms, and at the spring's owner
+                    // slot (lower internal index end) the parameter gradients
+                    auto slot = [&](int64_t e, int jr, const SpringConst &p, float4 acc) {
                         float gk, gC, gS;
                         spring_adjoint<ACT, DAMP, REST>(xi, ui, vi, sX[jr], sU[jr],
                                                         DAMP ? sV[jr] : make_float4(0.f, 0.f, 0.f, 0.f), p, tr.x,
                                                         tr.y, mi, sM[jr], lx[k], lv[k], gk, gC, gS);
-                        if (jr > q) {  // owner slot of this spring: lower internal index end
-                            float4 acc = a.gslot[e];
+                        if (jr > q) {
                             acc.x += gk;
                             acc.y += gC;
                             acc.z += gS;
                             a.gslot[e] = acc;
                         }
+                    };
+                    // as in the force sum, the global loads of kUnroll slots
+                    // (neighbour, constants, then the owners' running
+                    // gradients) are issued before any of them is used
+                    int w = 0;
+                    for (; w + kUnroll <= width; w += kUnroll) {
+                        int ref[kUnroll];
+                        SpringConst p[kUnroll];
+                        float4 acc[kUnroll];
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u) {
+                            const int64_t e = base + (int64_t)(w + u) * kSlice;
+                            ref[u] = nbr(e);
+                            p[u] = load_const<ACT, DAMPV, REST, false>(g, e);
+                        }
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u)
+                            acc[u] = ref[u] > q ? a.gslot[base + (int64_t)(w + u) * kSlice]
+                                                : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u)
+                            slot(base + (int64_t)(w + u) * kSlice, ref[u], p[u], acc[u]);
+                    }
+                    for (; w < width; ++w) {
+                        const int64_t e = base + (int64_t)w * kSlice;
+                        const int jr = nbr(e);
+                        slot(e, jr, load_const<ACT, DAMPV, REST, false>(g, e),
+                             jr > q ? a.gslot[e] : make_float4(0.f, 0.f, 0.f, 0.f));
                     }
                 }
             }
