@@ -158,8 +158,9 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
         xj = sX[r];
         vj = DAMP ? sV[r] : make_float4(0.f, 0.f, 0.f, 0.f);
     };
-    // one forward step of the group in LDS (same arithmetic as every engine)
-    auto forward = [&](int s) {
+    // one forward step of the group in LDS (same arithmetic as every engine);
+    // with fout, the summed spring forces are kept too
+    auto forward = [&](int s, float4 *fout) {
         const float2 tr = ACT ? a.trig[s] : make_float2(0.f, 1.f);
         float4 nu[MAXM], nv[MAXM];
         bool ok = true;
@@ -173,6 +174,8 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
                 sum_forces<ACT, DAMP, DAMPV, REST, false, false>(g, g.slice_off[i >> 6] + (i & 63),
                                                                  slice_width(g, i), xi, ui, vi, Clock{tr, 0.0}, sc,
                                                                  nbr, state, fx, fy, fz);
+                if (fout)
+                    fout[q] = make_float4(fx, fy, fz, 0.f);
                 ok &= integrate_mass(xi, ui, vi, fx, fy, fz, sc, nu[k], nv[k]);
             }
         }
@@ -203,7 +206,7 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
     // 1. forward with checkpoints
     const int nseg = (a.nsteps + K - 1) / K;
     for (int s = 0; s < a.nsteps; ++s) {
-        forward(s);
+        forward(s, nullptr);
         if ((s + 1) % K == 0 && (s + 1) / K < nseg)
             for (int q = tid; q < nm; q += T) {
                 a.ckU[(int64_t)((s + 1) / K) * n + m0 + q] = sU[q];
@@ -236,7 +239,7 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
                 a.segV[(int64_t)r * n + m0 + q] = sV[q];
             }
             if (r + 1 < len)
-                forward(s0 + r);
+                forward(s0 + r, a.segF + (int64_t)r * n + m0);
         }
         for (int r = len - 1; r >= 0; --r) {
             const int s = s0 + r;
@@ -248,7 +251,8 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
                 sV[q] = a.segV[(int64_t)r * n + m0 + q];
             }
             __syncthreads();
-            // mass pass
+            // mass pass (the forces of every state but the segment's last
+            // were kept by the recompute)
 #pragma unroll
             for (int k = 0; k < MAXM; ++k) {
                 const int q = tid + k * T;
@@ -256,9 +260,16 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
                     const int64_t i = m0 + q;
                     const float4 xi = sX[q], ui = sU[q], vi = sV[q];
                     float fx = 0.f, fy = 0.f, fz = 0.f;
-                    sum_forces<ACT, DAMP, DAMPV, REST, false, false>(g, g.slice_off[i >> 6] + (i & 63),
-                                                                     slice_width(g, i), xi, ui, vi, Clock{tr, 0.0},
-                                                                     sc, nbr, state, fx, fy, fz);
+                    if (r + 1 < len) {
+                        const float4 f = a.segF[(int64_t)r * n + i];
+                        fx = f.x;
+                        fy = f.y;
+                        fz = f.z;
+                    } else {
+                        sum_forces<ACT, DAMP, DAMPV, REST, false, false>(g, g.slice_off[i >> 6] + (i & 63),
+                                                                         slice_width(g, i), xi, ui, vi,
+                                                                         Clock{tr, 0.0}, sc, nbr, state, fx, fy, fz);
+                    }
                     sM[q] = mass_adjoint(xi, ui, vi, fx, fy, fz, scs, lx[k], lv[k]);
                 }
             }

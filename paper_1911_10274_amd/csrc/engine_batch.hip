@@ -399,6 +399,7 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
     if ((rc = get(sizeof(float4) * n * std::max<int64_t>(nseg, 1), (void **)&a.ckU)) ||
         (rc = get(sizeof(float4) * n * std::max<int64_t>(nseg, 1), (void **)&a.ckV)) ||
         (rc = get(sizeof(float4) * n * K, (void **)&a.segU)) || (rc = get(sizeof(float4) * n * K, (void **)&a.segV)) ||
+        (rc = get(sizeof(float4) * n * K, (void **)&a.segF)) ||
         (rc = get(sizeof(float4) * std::max<int64_t>(nslots, 1), (void **)&a.gslot)) ||
         (rc = get(sizeof(float) * n, (void **)&dseed)) || (rc = get(sizeof(float) * n, (void **)&dcoef)) ||
         (rc = get(sizeof(float) * n, (void **)&a.dux)) || (rc = get(sizeof(float) * nruns, (void **)&dloss)) ||

@@ -161,6 +161,7 @@ struct AdjointIO {
     const float4 *U0, *V0;    // starting state
     float4 *ckU, *ckV;        // [ceil(nsteps/K) * n] checkpoints (state at steps 0, K, 2K, ...)
     float4 *segU, *segV;      // [K * n] states of the segment being reversed
+    float4 *segF;             // [K * n] summed spring force at those states (w unused)
     float4 *gslot;            // [slots] (dJ/dk, dJ/dC, dJ/dS, 0) on each spring's owner slot; zeroed
     const float *seed;        // [n] dJ/dx_N (x component)
     float *dux;               // [n] x-displacement over the rollout
