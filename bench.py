@@ -259,6 +259,13 @@ def bench_adjoint(T, robots_n: int, steps: int, K: int):
     for _ in range(reps):
         sim.rollout_grad(steps, K)
     sec = (_t.perf_counter() - t0) / reps
+    # every state kept (one segment, no recompute): 48 B per mass per step
+    sim.rollout_grad(steps, steps)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    for _ in range(reps):
+        sim.rollout_grad(steps, steps)
+    sec_all = (_t.perf_counter() - t0) / reps
     ms_fwd = _timed_steps(sim, steps, torch.cuda.current_stream())
     sim.close()
     return {"workload": f"{robots_n} voxel robots, side U{{4..8}}, {steps}-step rollout, checkpoints every {K} "
@@ -267,7 +274,10 @@ def bench_adjoint(T, robots_n: int, steps: int, K: int):
             "value": steps / sec, "unit": "adjoint steps/s",
             "robot_steps_per_s": robots_n * steps / sec,
             "ms_per_gradient": sec * 1e3,
-            "forward_ms": ms_fwd, "gradient_over_forward": sec * 1e3 / ms_fwd}
+            "forward_ms": ms_fwd, "gradient_over_forward": sec * 1e3 / ms_fwd,
+            "all_states_kept": {"checkpoint_every": steps, "segment_bytes": 48 * nm * steps,
+                                "ms_per_gradient": sec_all * 1e3, "value": steps / sec_all,
+                                "gradient_over_forward": sec_all * 1e3 / ms_fwd}}
 
 
 def bench_worms(T, count: int = 100, steps: int = 10000):

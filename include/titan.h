@@ -330,7 +330,9 @@ int titan_set_springs(titan_sim *sim, int64_t first, int64_t count, const float 
 /* Gradient of a rollout by the adjoint method: backward in time through the
  * steps, with the forward states recomputed from checkpoints taken every
  * `checkpoint_every` steps (memory: one state per checkpoint plus one
- * segment of states).  The rollout starts from the current state (after all
+ * segment of states and spring forces, 48 bytes per mass per step; the last
+ * segment is kept by the forward pass itself, so checkpoint_every >= nsteps
+ * recomputes nothing).  The rollout starts from the current state (after all
  * enqueued steps) at the current step index and runs `nsteps` steps; the
  * simulation itself is not advanced.  Loss: J = sum_b w_b J_b with
  * J_b = -(x-displacement of the centre of mass of body b), the

@@ -203,10 +203,22 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
     }
     __syncthreads();
 
-    // 1. forward with checkpoints
+    // 1. forward with checkpoints; the last segment's states and forces go
+    // straight to the segment buffers (that segment is reversed first and
+    // needs no recompute)
     const int nseg = (a.nsteps + K - 1) / K;
+    const int last0 = (nseg - 1) * K;
     for (int s = 0; s < a.nsteps; ++s) {
-        forward(s, nullptr);
+        if (s >= last0) {
+            const int r = s - last0;
+            for (int q = tid; q < nm; q += T) {
+                a.segU[(int64_t)r * n + m0 + q] = sU[q];
+                a.segV[(int64_t)r * n + m0 + q] = sV[q];
+            }
+            forward(s, a.segF + (int64_t)r * n + m0);
+        } else {
+            forward(s, nullptr);
+        }
         if ((s + 1) % K == 0 && (s + 1) / K < nseg)
             for (int q = tid; q < nm; q += T) {
                 a.ckU[(int64_t)((s + 1) / K) * n + m0 + q] = sU[q];
@@ -227,19 +239,22 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
     for (int c = nseg - 1; c >= 0; --c) {
         const int s0 = c * K;
         const int len = min(K, a.nsteps - s0);
-        __syncthreads();
-        for (int q = tid; q < nm; q += T) {
-            sU[q] = a.ckU[(int64_t)c * n + m0 + q];
-            sV[q] = a.ckV[(int64_t)c * n + m0 + q];
-        }
-        __syncthreads();
-        for (int r = 0; r < len; ++r) {
+        const bool kept = c == nseg - 1;  // states and forces stored by the forward pass
+        if (!kept) {
+            __syncthreads();
             for (int q = tid; q < nm; q += T) {
-                a.segU[(int64_t)r * n + m0 + q] = sU[q];
-                a.segV[(int64_t)r * n + m0 + q] = sV[q];
+                sU[q] = a.ckU[(int64_t)c * n + m0 + q];
+                sV[q] = a.ckV[(int64_t)c * n + m0 + q];
             }
-            if (r + 1 < len)
-                forward(s0 + r, a.segF + (int64_t)r * n + m0);
+            __syncthreads();
+            for (int r = 0; r < len; ++r) {
+                for (int q = tid; q < nm; q += T) {
+                    a.segU[(int64_t)r * n + m0 + q] = sU[q];
+                    a.segV[(int64_t)r * n + m0 + q] = sV[q];
+                }
+                if (r + 1 < len)
+                    forward(s0 + r, a.segF + (int64_t)r * n + m0);
+            }
         }
         for (int r = len - 1; r >= 0; --r) {
             const int s = s0 + r;
@@ -251,8 +266,8 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
                 sV[q] = a.segV[(int64_t)r * n + m0 + q];
             }
             __syncthreads();
-            // mass pass (the forces of every state but the segment's last
-            // were kept by the recompute)
+            // mass pass (the forces of every state but a recomputed
+            // segment's last were kept)
 #pragma unroll
             for (int k = 0; k < MAXM; ++k) {
                 const int q = tid + k * T;
@@ -260,7 +275,7 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
                     const int64_t i = m0 + q;
                     const float4 xi = sX[q], ui = sU[q], vi = sV[q];
                     float fx = 0.f, fy = 0.f, fz = 0.f;
-                    if (r + 1 < len) {
+                    if (kept || r + 1 < len) {
                         const float4 f = a.segF[(int64_t)r * n + i];
                         fx = f.x;
                         fy = f.y;
