@@ -256,14 +256,35 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
                     forward(s0 + r, a.segF + (int64_t)r * n + m0);
             }
         }
+        // the next reverse step's state and force are fetched into
+        // registers while the current spring pass runs (each thread reads
+        // only what it wrote itself)
+        float4 pu[MAXM], pv[MAXM], pf[MAXM];
+        auto fetch = [&](int r) {
+#pragma unroll
+            for (int k = 0; k < MAXM; ++k) {
+                const int q = tid + k * T;
+                if (q < nm) {
+                    const int64_t o = (int64_t)r * n + m0 + q;
+                    pu[k] = a.segU[o];
+                    pv[k] = a.segV[o];
+                    pf[k] = (kept || r + 1 < len) ? a.segF[o] : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+        };
+        fetch(len - 1);
         for (int r = len - 1; r >= 0; --r) {
             const int s = s0 + r;
             const float2 tr = ACT ? a.trig[s] : make_float2(0.f, 1.f);
             StepConsts scs = sc;
             __syncthreads();
-            for (int q = tid; q < nm; q += T) {
-                sU[q] = a.segU[(int64_t)r * n + m0 + q];
-                sV[q] = a.segV[(int64_t)r * n + m0 + q];
+#pragma unroll
+            for (int k = 0; k < MAXM; ++k) {
+                const int q = tid + k * T;
+                if (q < nm) {
+                    sU[q] = pu[k];
+                    sV[q] = pv[k];
+                }
             }
             __syncthreads();
             // mass pass (the forces of every state but a recomputed
@@ -274,13 +295,9 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
                 if (q < nm) {
                     const int64_t i = m0 + q;
                     const float4 xi = sX[q], ui = sU[q], vi = sV[q];
-                    float fx = 0.f, fy = 0.f, fz = 0.f;
-                    if (kept || r + 1 < len) {
-                        const float4 f = a.segF[(int64_t)r * n + i];
-                        fx = f.x;
-                        fy = f.y;
-                        fz = f.z;
-                    } else {
+                    float fx = pf[k].x, fy = pf[k].y, fz = pf[k].z;
+                    if (!(kept || r + 1 < len)) {
+                        fx = fy = fz = 0.f;
                         sum_forces<ACT, DAMP, DAMPV, REST, false, false>(g, g.slice_off[i >> 6] + (i & 63),
                                                                          slice_width(g, i), xi, ui, vi,
                                                                          Clock{tr, 0.0}, sc, nbr, state, fx, fy, fz);
@@ -289,6 +306,8 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
                 }
             }
             __syncthreads();
+            if (r > 0)
+                fetch(r - 1);
             // spring pass
 #pragma unroll
             for (int k = 0; k < MAXM; ++k) {
