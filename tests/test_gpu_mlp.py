@@ -66,7 +66,10 @@ def _split(flat, dims):
     return gW, gb
 
 
-@pytest.mark.parametrize("dims,B", [([40, 64, 64, 3], 33), ([1536, 512, 512, 512, 512, 3], 128)])
+# B = 1024 and 1000: the training batch, where every weight-gradient product
+# (and its ones column, the bias gradient) runs split over K; 1000 is ragged
+@pytest.mark.parametrize("dims,B", [([40, 64, 64, 3], 33), ([1536, 512, 512, 512, 512, 3], 128),
+                                    ([1536, 512, 512, 512, 512, 3], 1024), ([1536, 512, 512, 512, 512, 3], 1000)])
 def test_mlp_forward_and_gradients_match_oracle(dims, B):
     from paper_1911_10274_amd import titan as T
 
