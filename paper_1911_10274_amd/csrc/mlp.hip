@@ -195,6 +195,20 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, GemmEpi ep)
         ta.load(g.A, g.lda, m0, g.M, kb, ke, va, tid);
         tb.load(g.B, g.ldb, n0, g.N, kb, ke, vb, tid);
     }
+    // D layout of the 32x32 MFMA: lane l holds column l % 32 and, for
+    // r = 0..15, row 8 (r / 4) + 4 (l / 32) + r % 4.
+    const int j = n0 + wn * 32 + (lane & 31);
+    auto row = [&](int r) { return m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); };
+    // the epilogue's own inputs are loaded before the K loop, so their
+    // latency hides behind it (one pass; a split leaves them to the reduction)
+    float pre[16];
+    if (!g.part && (EPI == EPI_GELU_BWD || EPI == EPI_BIAS_GELU || EPI == EPI_BIAS)) {
+        const float bj = (EPI != EPI_GELU_BWD && j < g.N) ? ep.bias[j] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            pre[r] = EPI == EPI_GELU_BWD ? ((j < g.N && row(r) < g.M) ? ep.Zin[(int64_t)row(r) * ep.ldz + j] : 0.f)
+                                         : bj;
+    }
     for (int k0 = kb; k0 < ke; k0 += BK) {
         ta.store(sA, tid);
         tb.store(sB, tid);
@@ -212,20 +226,26 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, GemmEpi ep)
         __syncthreads();
     }
 
-    // D layout of the 32x32 MFMA: lane l holds column l % 32 and, for
-    // r = 0..15, row 8 (r / 4) + 4 (l / 32) + r % 4.
-    const int j = n0 + wn * 32 + (lane & 31);
     if (j >= g.N)
         return;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const int i = m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int i = row(r);
         if (i >= g.M)
             continue;
-        if (g.part)
+        if (g.part) {
             g.part[((int64_t)blockIdx.z * g.M + i) * g.N + j] = acc[r];
-        else
+        } else if (EPI == EPI_GELU_BWD) {
+            ep.Yb[(int64_t)i * ep.ldy + j] = f2bf(acc[r] * gelu_grad(pre[r]));
+        } else if (EPI == EPI_BIAS_GELU) {
+            const float z = acc[r] + pre[r];
+            ep.Z[(int64_t)i * ep.ldz + j] = z;
+            ep.Yb[(int64_t)i * ep.ldy + j] = f2bf(gelu(z));
+        } else if (EPI == EPI_BIAS) {
+            ep.Z[(int64_t)i * ep.ldz + j] = acc[r] + pre[r];
+        } else {
             epi_store<EPI>(i, j, acc[r], ep);
+        }
     }
 }
 
