@@ -29,6 +29,12 @@ constexpr int kModeStep = 0, kModeForces = 1, kModeStage = 2;
 template <bool YIELD, int MODE>
 constexpr int yield_mode = YIELD ? (MODE == kModeForces ? 1 : 2) : 0;
 
+// Slots per load batch of the tiled kernel: more in flight for the lean
+// phasor-law slots (about 18 more registers, within what three 512-mass tiles
+// per CU allow), the default where a slot carries more state.
+template <bool WAVE, bool DAMPV, bool REST, bool YIELD>
+constexpr int plain_unroll = (WAVE || DAMPV || REST || YIELD) ? kUnroll : kUnrollPlain;
+
 template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, int MODE, bool YIELD>
 __global__ __launch_bounds__(256) void untiled_step_kernel(GatherGraph g, StateIO io, StepConsts sc)
 {
@@ -128,7 +134,8 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
     float fx = 0.f, fy = 0.f, fz = 0.f;
     const int64_t n = step_index(sc);
     const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), step_time(n, sc.dt64, sc.t_add)};
-    sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE, yield_mode<YIELD, MODE>>(
+    sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE, yield_mode<YIELD, MODE>,
+               plain_unroll<WAVE, DAMPV, REST, YIELD>>(
         g, base, slice_width(g, i), xi, ui, vi, ck, sc, [&](int64_t e) { return (int)stream_load(g.nbr_local + e); },
         [&](int q, float4 &xj, float4 &uj, float4 &vj) {
             uj = sU[q];

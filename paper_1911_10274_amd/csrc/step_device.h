@@ -387,25 +387,27 @@ __device__ __forceinline__ SpringConst load_const(const GatherGraph &g, int64_t 
 // fetches that neighbour's state.  YIELD: 0 unbreakable springs; 1 apply the
 // yield test (a force query); 2 apply it and record breaks in the slot.
 constexpr int kUnroll = TITAN_UNROLL;
+constexpr int kUnrollPlain = TITAN_UNROLL_PLAIN;
 
-template <bool ACT, bool DAMP, bool DAMPV, bool REST, bool NT, bool WAVE, int YIELD = 0, class Nbr, class State>
+template <bool ACT, bool DAMP, bool DAMPV, bool REST, bool NT, bool WAVE, int YIELD = 0, int UNROLL = kUnroll,
+          class Nbr, class State>
 __device__ __forceinline__ void sum_forces(const GatherGraph &g, int64_t base, int width, const float4 &xi,
                                            const float4 &ui, const float4 &vi, const Clock &ck,
                                            const StepConsts &sc, Nbr nbr, State state, float &fx, float &fy,
                                            float &fz)
 {
     int w = 0;
-    for (; w + kUnroll <= width; w += kUnroll) {
-        int ref[kUnroll];
-        SpringConst p[kUnroll];
+    for (; w + UNROLL <= width; w += UNROLL) {
+        int ref[UNROLL];
+        SpringConst p[UNROLL];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < UNROLL; ++u) {
             const int64_t e = base + (int64_t)(w + u) * kSlice;
             ref[u] = nbr(e);
             p[u] = load_const<ACT, DAMPV, REST, NT, WAVE, YIELD != 0>(g, e);
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < UNROLL; ++u) {
             float4 xj, uj, vj;
             state(ref[u], xj, uj, vj);
             const bool broke = spring_force<ACT, DAMP, REST, YIELD != 0>(

@@ -54,13 +54,19 @@ hipError_t launch_clock(int64_t *clock, int64_t value, int64_t add, hipStream_t 
 
 // Masses per tile of the tiled kernel (one workgroup, one thread per mass).
 // Compile-time tuning of the tiled kernel (overridable with -D for tuning
-// builds): tile size, incidence loads issued per batch, and non-temporal
+// builds): tile size, incidence slots whose loads are issued together
+// (TITAN_UNROLL_PLAIN in the gather and tiled kernels for the phasor law with
+// uniform damping, no per-slot rest lengths and no yields; TITAN_UNROLL
+// everywhere else, where each slot carries more state), and non-temporal
 // loads for the once-per-step streams of spring constants.
 #ifndef TITAN_TILE
 #define TITAN_TILE 512
 #endif
 #ifndef TITAN_UNROLL
 #define TITAN_UNROLL 4
+#endif
+#ifndef TITAN_UNROLL_PLAIN
+#define TITAN_UNROLL_PLAIN 8
 #endif
 #ifndef TITAN_NT_LOADS
 #define TITAN_NT_LOADS 1
