@@ -100,6 +100,31 @@ def test_mlp_forward_and_gradients_match_oracle(dims, B):
     net.close()
 
 
+def test_gradients_across_batch_sizes_on_one_network():
+    """One network, batches of 128, 1024 (its buffers grow) and then 1000
+    and 64 (they do not): the activations' ones column, which turns the
+    weight-gradient product into the bias gradient too, must hold each time."""
+    from paper_1911_10274_amd import titan as T
+
+    dims = [96, 64, 64, 3]
+    Ws, bs, flat = _init(dims, 21)
+    net = T.Mlp(dims)
+    net.set_params(flat)
+    for B in (128, 1024, 1000, 64):
+        rng = np.random.Generator(np.random.PCG64(B))
+        X = rng.normal(0, 1, (B, dims[0])).astype(np.float32)
+        Y = rng.normal(0, 1, (B, dims[-1])).astype(np.float32)
+        _, g = net.grad(X, Y)
+        _, rW, rb = MO.loss_and_grads(Ws, bs, X.astype(np.float64), Y.astype(np.float64), bf16=True)
+        gW, gb = _split(g.astype(np.float64), dims)
+        for l in range(len(dims) - 1):
+            for got, want in ((gW[l], rW[l]), (gb[l], rb[l])):
+                got, want = got.ravel(), want.ravel()
+                rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+                assert rel <= 2e-2, (B, l, rel)
+    net.close()
+
+
 def test_adam_step_matches_reference_and_training_learns():
     from paper_1911_10274_amd import titan as T
 
