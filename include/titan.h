@@ -170,21 +170,25 @@ typedef struct titan_info {
                                  into spare slots without a rebuild */
 } titan_info;
 
-/* ABI version this library implements (TITAN_ABI_VERSION). */
+/* ABI version this library implements (TITAN_ABI_VERSION).  Library
+ * bookkeeping, not in the paper. */
 int titan_abi_version(void);
 
 /* Message of the last failing call on the calling thread ("" if none).  The
- * pointer stays valid until the next titan_* call on this thread. */
+ * pointer stays valid until the next titan_* call on this thread.  Error
+ * reporting of this interface, not in the paper. */
 const char *titan_last_error(void);
 
-/* Create an empty sim.  p: parameters (copied).  stream: a hipStream_t to
+/* Create an empty sim (Sec. III-A: a simulation holds the masses, springs
+ * and constraints that the library steps).  p: parameters (copied).  stream: a hipStream_t to
  * run on, or NULL for the device's null stream; the caller keeps it alive
  * until titan_destroy.  alloc: NULL or a device allocator (copied).  No device
  * work happens before the first titan_step.  *out receives the sim. */
 int titan_create(const titan_params *p, void *stream, const titan_allocator *alloc, titan_sim **out);
 
-/* Wait for the sim's queued work, free all its memory and the sim itself.
- * NULL is accepted. */
+/* Wait for the sim's queued work, free all its memory and the sim itself
+ * (Sec. III-C: the objects live on the GPU until released).  NULL is
+ * accepted. */
 int titan_destroy(titan_sim *sim);
 
 /* Append n masses (Sec. III-C: masses are the primitive objects springs act
@@ -232,8 +236,9 @@ int titan_add_springs(titan_sim *sim, int64_t n, const int64_t *ends_n2, const f
  * bitwise unchanged.  Layouts rebuilt later leave it out. */
 int titan_remove_springs(titan_sim *sim, int64_t n, const int64_t *springs_n);
 
-/* Yield values of springs [first, first + count) (Sec. III-B: material yield
- * values compared against in the force calculation to find broken springs).
+/* Yield values of springs [first, first + count) (Sec. III-E: per-spring
+ * material yield values, tested in the force calculation, mark springs as
+ * broken).
  * yield_count: > 0, or +inf for a spring that never breaks; springs never
  * given one have +inf.  A spring whose elastic force |k (l - L(t))| (damping
  * excluded) exceeds its yield value in a step's force evaluation breaks: it
@@ -248,33 +253,40 @@ int titan_remove_springs(titan_sim *sim, int64_t n, const int64_t *springs_n);
 int titan_set_yield(titan_sim *sim, int64_t first, int64_t count, const float *yield_count);
 
 /* Broken flags (1 broken, 0 intact) of springs [first, first + count) after
- * the steps enqueued so far (waits for them).  Springs of a sim without
- * yield values are never broken. */
+ * the steps enqueued so far (waits for them); Sec. III-E's yield test.
+ * Springs of a sim without yield values are never broken. */
 int titan_get_broken(titan_sim *sim, int64_t first, int64_t count, uint8_t *broken_count);
 
-/* Remove n masses: every spring touching them is removed (as above) and the
- * masses stay where they are, pinned (mass 0) and at rest.  Indices are kept.
+/* Remove n masses (Sec. III-C's deletion of masses): every spring touching
+ * them is removed (as above) and the masses stay where they are, pinned
+ * (mass 0) and at rest.  Indices are kept.
  * Cost O(springs) to find the touching springs. */
 int titan_remove_masses(titan_sim *sim, int64_t n, const int64_t *masses_n);
 
-/* Replace the parameters.  Takes effect for steps enqueued after this call
- * (while paused at a breakpoint: from the breakpoint on).  The engine field
+/* Replace the parameters (Sec. III-A: time resolution, gravity, plane
+ * constraint and friction; Sec. III-D: updates queued while the simulation
+ * runs are applied when it stops).  Takes effect for steps enqueued after
+ * this call (while paused at a breakpoint: from the breakpoint on).  The engine field
  * may change only before the first step; afterwards it must be
  * TITAN_ENGINE_AUTO or the engine first asked for. */
 int titan_set_params(titan_sim *sim, const titan_params *p);
 
 /* Build the device representation now (otherwise done by the first
  * titan_step): validation, internal ordering, incidence lists, upload and
- * engine selection. */
+ * engine selection (Sec. III-B: each mass's springs in a fixed order for the
+ * accumulation-based sum; Sec. III-C: all components reside on the GPU). */
 int titan_finalize(titan_sim *sim);
 
-/* Ask for n more steps (n >= 0).  Asynchronous: work is enqueued on the
- * sim's stream and the call returns; step n of the run uses t = n*dt.  Steps
+/* Ask for n more steps (n >= 0) of the spring pass and the mass update
+ * (Sec. III-B, Eq. 1).  Asynchronous (Sec. III-D: the GPU keeps stepping
+ * while the CPU runs freely): work is enqueued on the sim's stream and the
+ * call returns; step n of the run uses t = n*dt.  Steps
  * beyond a pause breakpoint are held until titan_resume. */
 int titan_step(titan_sim *sim, int64_t n);
 
 /* Breakpoint at absolute step index `step` (the state after `step` steps),
- * which must not be behind the steps already enqueued.  kind: TITAN_BP_*.
+ * which must not be behind the steps already enqueued (Sec. III-D's
+ * setBreakpoint).  kind: TITAN_BP_*.
  * *bp_out receives a handle for titan_wait / titan_get_snapshot. */
 int titan_set_breakpoint(titan_sim *sim, int64_t step, int32_t kind, uint64_t *bp_out);
 
@@ -283,25 +295,30 @@ int titan_set_breakpoint(titan_sim *sim, int64_t step, int32_t kind, uint64_t *b
  * steps requested so far. */
 int titan_wait(titan_sim *sim, uint64_t bp);
 
-/* Release a pause breakpoint and enqueue the held steps. */
+/* Release a pause breakpoint and enqueue the held steps (Sec. III-D: a CPU
+ * thread reactivates the halted simulation). */
 int titan_resume(titan_sim *sim);
 
-/* Block until all enqueued work is done; reports non-finite state. */
+/* Block until all enqueued work is done; reports non-finite state
+ * (Sec. III-D: the CPU blocks only when it issues a blocking call). */
 int titan_sync(titan_sim *sim);
 
 /* Copy the state of masses [first, first+count) after all enqueued steps
- * (blocks until they are done).  pos_n3 / vel_n3 may be NULL.  flags:
+ * (blocks until they are done; Sec. III-D: copies from the GPU happen when
+ * the simulation has stopped).  pos_n3 / vel_n3 may be NULL.  flags:
  * TITAN_STATE_DISPLACEMENT.  *step_out (may be NULL) gets the step index. */
 int titan_get_state(titan_sim *sim, int64_t first, int64_t count, float *pos_n3, float *vel_n3,
                     int32_t flags, int64_t *step_out);
 
 /* Copy the state saved at breakpoint bp (blocks until it is reached), while
- * later steps may still be running. */
+ * later steps may still be running (Sec. III-D's results read at a
+ * breakpoint). */
 int titan_get_snapshot(titan_sim *sim, uint64_t bp, int64_t first, int64_t count, float *pos_n3,
                        float *vel_n3, int32_t flags, int64_t *step_out);
 
 /* Overwrite the state of masses [first, first+count), in stream order: it
- * applies after the steps enqueued so far (at the breakpoint if paused).
+ * applies after the steps enqueued so far (at the breakpoint if paused;
+ * Sec. III-D: state pushed to the GPU while the simulation is stopped).
  * pos_n3 / vel_n3 may be NULL to keep that part.  With
  * TITAN_STATE_DISPLACEMENT pos is x - x0. */
 int titan_set_state(titan_sim *sim, int64_t first, int64_t count, const float *pos_n3,
@@ -314,7 +331,8 @@ int titan_set_state(titan_sim *sim, int64_t first, int64_t count, const float *p
 int titan_set_step(titan_sim *sim, int64_t step);
 
 /* Centre-of-mass displacement of every body after all enqueued steps
- * (blocks): disp_nb3[b] = sum_i m_i (x_i - x0_i) / M_b over the masses of
+ * (blocks; Sec. IV-B/IV-C measure locomotion by how far a body moves):
+ * disp_nb3[b] = sum_i m_i (x_i - x0_i) / M_b over the masses of
  * body b (n_bodies x 3 floats). */
 int titan_get_body_displacement(titan_sim *sim, float *disp_nb3);
 
@@ -327,8 +345,9 @@ int titan_get_body_displacement(titan_sim *sim, float *disp_nb3);
 int titan_set_springs(titan_sim *sim, int64_t first, int64_t count, const float *k_n, const float *damping_n,
                       const float *amp_n, const float *phase_n);
 
-/* Gradient of a rollout by the adjoint method: backward in time through the
- * steps, with the forward states recomputed from checkpoints taken every
+/* Gradient of a rollout by the adjoint method (not in the paper; Sec. II
+ * names differentiable simulation as related work): backward in time through
+ * the steps, with the forward states recomputed from checkpoints taken every
  * `checkpoint_every` steps (memory: one state per checkpoint plus one
  * segment of states and spring forces, 48 bytes per mass per step; the last
  * segment is kept by the forward pass itself, so checkpoint_every >= nsteps
@@ -349,10 +368,11 @@ int titan_rollout_grad(titan_sim *sim, int64_t nsteps, int32_t checkpoint_every,
                        float *loss_out, float *grad_k, float *grad_act_c, float *grad_act_s);
 
 /* Summed spring force on masses [first, first+count) at the current state
- * and the current step's time (blocks).  f_n3 receives N. */
+ * and the current step's time (blocks): the spring pass of Sec. III-B
+ * (Eq. 1) alone.  f_n3 receives N. */
 int titan_get_forces(titan_sim *sim, int64_t first, int64_t count, float *f_n3);
 
-/* Fill *info. */
+/* Fill *info (library bookkeeping, not in the paper). */
 int titan_get_info(titan_sim *sim, titan_info *info);
 
 /* ------------------------------------------------------------------------
@@ -368,30 +388,38 @@ int titan_get_info(titan_sim *sim, titan_info *info);
  * ------------------------------------------------------------------------ */
 typedef struct titan_mlp titan_mlp;
 
-/* Create a network of n_layers layers with widths dims[0..n_layers]
+/* (The surrogate is not in the paper; every titan_mlp_* call belongs to it.)
+ * Create a network of n_layers layers with widths dims[0..n_layers]
  * (1..65536 each).  stream / alloc as in titan_create.  Parameters start at
  * zero: set them with titan_mlp_set_params. */
 int titan_mlp_create(int32_t n_layers, const int32_t *dims, void *stream, const titan_allocator *alloc,
                      titan_mlp **out);
+/* Free the network and its device memory (not in the paper).  NULL is
+ * accepted. */
 int titan_mlp_destroy(titan_mlp *mlp);
-/* Number of parameters (length of the flat array), or -1 for NULL. */
+/* Number of parameters (length of the flat array), or -1 for NULL (not in
+ * the paper). */
 int64_t titan_mlp_param_count(titan_mlp *mlp);
-/* Copy all parameters in (resets the Adam state) or out. */
+/* Copy all parameters in (resets the Adam state); not in the paper. */
 int titan_mlp_set_params(titan_mlp *mlp, const float *params);
+/* Copy all parameters out (not in the paper). */
 int titan_mlp_get_params(titan_mlp *mlp, float *params);
-/* Keep a training set on the device: X (n x dims[0], stored as bfloat16),
+/* Keep a training set on the device (not in the paper): X (n x dims[0],
+ * stored as bfloat16),
  * Y (n x dims[L], FP32 targets).  Replaces any previous set. */
 int titan_mlp_set_data(titan_mlp *mlp, int64_t n, const float *X, const float *Y);
-/* nsteps Adam steps (learning rate lr, beta1, beta2, eps) on mini-batches of
+/* nsteps Adam steps (not in the paper; learning rate lr, beta1, beta2, eps) on
+ * mini-batches of
  * `batch` rows of the training set; idx (nsteps x batch) lists the rows of
  * each step.  loss_out (nsteps, may be NULL) receives each step's loss. */
 int titan_mlp_train(titan_mlp *mlp, int64_t nsteps, int32_t batch, const int64_t *idx, float lr, float beta1,
                     float beta2, float eps, float *loss_out);
-/* Outputs (n x dims[L]) for inputs X (n x dims[0]). */
+/* Outputs (n x dims[L]) for inputs X (n x dims[0]); not in the paper. */
 int titan_mlp_predict(titan_mlp *mlp, int64_t n, const float *X, float *out);
-/* Loss and the gradient of every parameter (flat layout) on one batch. */
+/* Loss and the gradient of every parameter (flat layout) on one batch (not
+ * in the paper). */
 int titan_mlp_grad(titan_mlp *mlp, int32_t batch, const float *X, const float *Y, float *loss, float *grads);
-/* The GEMM alone, on device arrays: C (M x N, FP32, row-major) = op(A) op(B)
+/* The GEMM alone (not in the paper), on device arrays: C (M x N, FP32, row-major) = op(A) op(B)
  * with op(A)[m][k] = ta ? A[k*lda + m] : A[m*lda + k] and
  * op(B)[k][n] = tb ? B[n*ldb + k] : B[k*ldb + n] (bfloat16 bit patterns).
  * Asynchronous on `stream`. */

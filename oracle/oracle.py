@@ -142,7 +142,7 @@ class System:
     computed in FP64 from the (FP32) initial positions.
 
     A scene with a ``yield`` array (per spring; inf = never breaks) has
-    breakable springs (Sec. III-B): ``broken`` holds one flag per spring,
+    breakable springs (Sec. III-E): ``broken`` holds one flag per spring,
     starts all clear and is updated by ``run``, ``trajectory`` and
     ``spring_forces`` unless they are given a flag array of their own (then
     that array is updated in place).

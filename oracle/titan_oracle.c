@@ -26,8 +26,8 @@
  *     taken non-negative (tau in [0, period)); the per-spring offset t_o is
  *     passed in the phase array.  Eq. 5 defines t_o from the reference
  *     positions: the smaller x of the two ends minus the body's smallest x.
- *   - Sec. III-B (material properties): a spring may carry a yield value that
- *     is compared against in the force calculation to find broken springs.
+ *   - Sec. III-E (real materials): a spring may carry a yield value; the
+ *     force calculation tests it to decide whether the spring has broken.
  *     Reading taken here: the value compared is the magnitude of the spring's
  *     elastic force |k (l - L(t))| (the damper's force is not a material
  *     load); a spring whose elastic force exceeds its yield value breaks in
@@ -47,8 +47,9 @@
  *     from (x, v, t) when none is carried).  RK4: the classical four stages
  *     on (x, v) at t, t + dt/2, t + dt/2, t + dt, weights 1/6, 2/6, 2/6, 1/6.
  *
- * Accumulation is a serial scatter loop over springs in index order
- * (Sec. III-B's "apply to each corresponding mass"), all in double precision.
+ * Accumulation is a serial scatter loop over springs in index order, each
+ * spring adding its force to both of its masses (Sec. III-B's spring pass),
+ * all in double precision.
  */
 #include <math.h>
 #include <stdint.h>

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <unordered_map>
 #include <vector>
 
@@ -179,9 +180,28 @@ static double wave_offset(const titan_sim *s, const std::vector<double> &xmin, i
     return std::min((double)s->h_pos[3 * a], (double)s->h_pos[3 * b]) - xmin[s->h_body[a]];
 }
 
-static int build_gather(titan_sim *s, bool allow_tiled)
+// Host tables of the gather layout, planned without touching the device.
+struct GatherPlan {
+    bool allow_tiled = false, tiled = false;
+    bool k_uniform = true, damp_uniform = true, act = false, wave = false, rest = false, yield = false;
+    int64_t q0 = -1, nt = 0, nsl = 0, slots = 0;
+    int32_t max_local = 0;
+    std::vector<int32_t> deg, nbr, halo_idx;
+    std::vector<int64_t> off, halo_off;
+    std::vector<uint16_t> nbr_local;
+    std::vector<float> kk, cc, ac, as, d0, L0, yy;
+    std::vector<double> to;
+};
+
+// Plan the gather layout on the host (internal order already in s->perm):
+// incidence rows, tiles and halos, sliced-ELL slots and per-slot constants.
+// Also fills s->inv_perm and each spring's two slots.  Host work on the host
+// tables only; every size may be zero (no springs, no masses).
+static void plan_gather(titan_sim *s, bool allow_tiled, GatherPlan &P)
 {
     const int64_t n = s->n, ns = s->ns;
+    P = GatherPlan{};
+    P.allow_tiled = allow_tiled;
     std::vector<int64_t> &inv = s->inv_perm;
     inv.assign(n, 0);
     for (int64_t i = 0; i < n; ++i)
@@ -191,7 +211,8 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     // index (then spring index): the summation order, hence the result, does
     // not depend on the internal order or on the tiling.
     auto live = [&](int64_t q) { return s->h_removed.empty() || !s->h_removed[q]; };
-    std::vector<int32_t> deg(n, 0);
+    std::vector<int32_t> &deg = P.deg;
+    deg.assign(n, 0);
     for (int64_t q = 0; q < ns; ++q) {
         if (!live(q))
             continue;
@@ -223,9 +244,11 @@ static int build_gather(titan_sim *s, bool allow_tiled)
 
     // Tiles and halos.
     const int64_t nt = (n + kTile - 1) / kTile;
-    std::vector<int64_t> halo_off(nt + 1, 0);
-    std::vector<int32_t> halo_idx;
-    int32_t max_local = 0;
+    P.nt = nt;
+    std::vector<int64_t> &halo_off = P.halo_off;
+    halo_off.assign(nt + 1, 0);
+    std::vector<int32_t> &halo_idx = P.halo_idx;
+    int32_t &max_local = P.max_local;
     for (int64_t t = 0; t < nt; ++t) {
         const int64_t a = t * kTile, b = std::min(n, a + kTile);
         std::vector<int32_t> h;
@@ -242,15 +265,17 @@ static int build_gather(titan_sim *s, bool allow_tiled)
         max_local = std::max<int32_t>(max_local, kTile + (int32_t)h.size());
     }
     // LDS per tile: 3 float4 per local entry must fit the default 64 KB.
-    const bool tiled = allow_tiled && max_local * 3 * (int64_t)sizeof(float4) <= 65536;
+    const bool tiled = P.tiled = allow_tiled && max_local * 3 * (int64_t)sizeof(float4) <= 65536;
 
     // Per-spring constants (FP64 -> FP32).
     // (over the springs present; q0: the first of them)
     // Breakable springs keep damping and rest lengths per slot (one kernel
     // variant per actuation law).
-    const bool yield = !s->h_yield.empty();
-    int64_t q0 = -1;
-    bool act = false, rest = yield, damp_uniform = !yield, k_uniform = true;
+    const bool yield = P.yield = !s->h_yield.empty();
+    int64_t &q0 = P.q0;
+    bool &act = P.act, &rest = P.rest, &damp_uniform = P.damp_uniform, &k_uniform = P.k_uniform;
+    rest = yield;
+    damp_uniform = !yield;
     for (int64_t q = 0; q < ns; ++q) {
         if (!live(q))
             continue;
@@ -261,7 +286,7 @@ static int build_gather(titan_sim *s, bool allow_tiled)
         damp_uniform &= s->h_damp[q] == s->h_damp[q0];
         k_uniform &= s->h_k[q] == s->h_k[q0];
     }
-    const bool wave = act && s->params.actuation == TITAN_ACT_WAVE;
+    const bool wave = P.wave = act && s->params.actuation == TITAN_ACT_WAVE;
     std::vector<float> sC, sS, sD0, sL0;
     std::vector<double> sT;
     if (act && !wave) {
@@ -287,8 +312,9 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     }
 
     // Sliced ELL (slices of 64 masses; a tile is 4 slices).
-    const int64_t nsl = (n + kSlice - 1) / kSlice;
-    std::vector<int64_t> off(nsl + 1, 0);
+    const int64_t nsl = P.nsl = (n + kSlice - 1) / kSlice;
+    std::vector<int64_t> &off = P.off;
+    off.assign(nsl + 1, 0);
     for (int64_t sl = 0; sl < nsl; ++sl) {
         int32_t w = 0;
         for (int64_t i = sl * kSlice; i < std::min(n, (sl + 1) * kSlice); ++i)
@@ -296,13 +322,14 @@ static int build_gather(titan_sim *s, bool allow_tiled)
         w += s->slack;  // spare slots for springs added later (after an edit)
         off[sl + 1] = off[sl] + (int64_t)w * kSlice;
     }
-    const int64_t slots = off[nsl];
-    std::vector<int32_t> nbr(slots, 0);  // internal index of the other end, per slot
-    std::vector<uint16_t> nbr_local;
+    const int64_t slots = P.slots = off[nsl];
+    std::vector<int32_t> &nbr = P.nbr;  // internal index of the other end, per slot
+    nbr.assign(slots, 0);
+    std::vector<uint16_t> &nbr_local = P.nbr_local;
     if (tiled)
         nbr_local.assign(slots, 0);
-    std::vector<float> kk, cc, ac, as, d0, L0, yy;
-    std::vector<double> to;
+    std::vector<float> &kk = P.kk, &cc = P.cc, &ac = P.ac, &as = P.as, &d0 = P.d0, &L0 = P.L0, &yy = P.yy;
+    std::vector<double> &to = P.to;
     if (yield)
         yy.assign(slots, INFINITY);  // padding never breaks
     if (!k_uniform)
@@ -368,56 +395,64 @@ static int build_gather(titan_sim *s, bool allow_tiled)
                 yy[e] = s->h_yield[x.spring];
         }
     }
+}
 
+// Upload a planned gather layout and make it the current one.
+static int upload_gather(titan_sim *s, GatherPlan &P)
+{
+    const int64_t n = s->n;
+    const bool tiled = P.tiled, yield = P.yield, act = P.act, wave = P.wave, rest = P.rest;
+    const bool k_uniform = P.k_uniform, damp_uniform = P.damp_uniform;
+    const int64_t q0 = P.q0, slots = P.slots;
     GatherGraph &g = s->gg;
     g = GatherGraph{};
     g.n = n;
-    g.n_slices = nsl;
-    g.n_tiles = nt;
-    g.max_local = max_local;
+    g.n_slices = P.nsl;
+    g.n_tiles = P.nt;
+    g.max_local = P.max_local;
     g.c_uniform = (q0 >= 0 && damp_uniform) ? s->h_damp[q0] : 0.f;
     g.k_uniform = (q0 >= 0 && k_uniform) ? s->h_k[q0] : 0.f;
-    if (int rc = put(s, off, &g.slice_off))
+    if (int rc = put(s, P.off, &g.slice_off))
         return rc;
-    if (int rc = put(s, deg, &g.deg))
+    if (int rc = put(s, P.deg, &g.deg))
         return rc;
     if (tiled) {
-        if (int rc = put(s, nbr_local, &g.nbr_local))
+        if (int rc = put(s, P.nbr_local, &g.nbr_local))
             return rc;
-        if (int rc = put(s, halo_off, &g.halo_off))
+        if (int rc = put(s, P.halo_off, &g.halo_off))
             return rc;
-        if (int rc = put(s, halo_idx, &g.halo_idx))
+        if (int rc = put(s, P.halo_idx, &g.halo_idx))
             return rc;
     } else {
-        if (int rc = put(s, nbr, &g.nbr))
+        if (int rc = put(s, P.nbr, &g.nbr))
             return rc;
     }
     if (!k_uniform)
-        if (int rc = put(s, kk, &g.k))
+        if (int rc = put(s, P.kk, &g.k))
             return rc;
     if (!damp_uniform)
-        if (int rc = put(s, cc, &g.c))
+        if (int rc = put(s, P.cc, &g.c))
             return rc;
     if (act) {
-        if (int rc = put(s, ac, &g.act_c))
+        if (int rc = put(s, P.ac, &g.act_c))
             return rc;
         if (wave) {
-            if (int rc = put(s, to, &g.t_off))
+            if (int rc = put(s, P.to, &g.t_off))
                 return rc;
         } else {
-            if (int rc = put(s, as, &g.act_s))
+            if (int rc = put(s, P.as, &g.act_s))
                 return rc;
         }
     }
     if (rest) {
-        if (int rc = put(s, d0, &g.d0))
+        if (int rc = put(s, P.d0, &g.d0))
             return rc;
-        if (int rc = put(s, L0, &g.rest))
+        if (int rc = put(s, P.L0, &g.rest))
             return rc;
     }
     if (yield) {
         const float *p = nullptr;
-        if (int rc = put(s, yy, &p))
+        if (int rc = put(s, P.yy, &p))
             return rc;
         g.yield = const_cast<float *>(p);  // the step records breaks here
     }
@@ -426,19 +461,40 @@ static int build_gather(titan_sim *s, bool allow_tiled)
     s->n_slots = slots;
     // keep the staging alive until the copies have run
     HIP_TRY(s, hipStreamSynchronize(s->stream));
-    s->h_slot_nbr.swap(nbr);  // for the batched engine's layout
+    s->h_slot_nbr.swap(P.nbr);  // for the batched engine's layout
     // what insertion in place needs of the layout
-    s->h_deg.swap(deg);
-    s->h_slice_off.swap(off);
+    s->h_deg.swap(P.deg);
+    s->h_slice_off.swap(P.off);
     if (tiled) {
-        s->h_halo_off.swap(halo_off);
-        s->h_halo_idx.swap(halo_idx);
+        s->h_halo_off.swap(P.halo_off);
+        s->h_halo_idx.swap(P.halo_idx);
     } else {
         std::vector<int64_t>().swap(s->h_halo_off);
         std::vector<int32_t>().swap(s->h_halo_idx);
     }
     ++s->layout_builds;
     return TITAN_OK;
+}
+
+static int build_gather(titan_sim *s, bool allow_tiled)
+{
+    // a plan made before the device was set up (finalize) is used once
+    std::shared_ptr<GatherPlan> P = std::move(s->gplan);
+    if (!P || P->allow_tiled != allow_tiled) {
+        P = std::make_shared<GatherPlan>();
+        plan_gather(s, allow_tiled, *P);
+    }
+    return upload_gather(s, *P);
+}
+
+void plan_layouts(titan_sim *s)
+{
+    s->n = (int64_t)s->h_mass.size();
+    s->ns = (int64_t)s->h_k.size();
+    plan_order(s);
+    auto P = std::make_shared<GatherPlan>();
+    plan_gather(s, s->params.engine != TITAN_ENGINE_GATHER, *P);
+    s->gplan = std::move(P);
 }
 
 // Allocations made while an engine's layout is built or updated belong to the

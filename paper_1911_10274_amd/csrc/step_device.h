@@ -12,7 +12,7 @@
 //     l - L(t) = (l - |R|) + d0 - L0 (C sin + S cos),   d0 = |R| - L0.
 // When every rest length is the initial length, d0 = 0 and L0 = |R|.
 //
-// Breakable springs (Sec. III-B, material yield values): a spring whose
+// Breakable springs (Sec. III-E, material yield values): a spring whose
 // elastic force |k (l - L(t))| exceeds its yield value Y breaks in that force
 // evaluation and exerts no force from then on (its damper included).  Per
 // slot, Y = +inf never breaks and Y < 0 marks a broken spring; both ends of a

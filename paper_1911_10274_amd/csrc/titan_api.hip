@@ -659,14 +659,14 @@ static int finalize_locked(titan_sim *s)
         return TITAN_OK;
     if (s->dev_error)
         return fail(TITAN_EDEVICE, "sim is in a failed device state");
+    // Host planning first (internal order, incidence layout): it needs no
+    // device, and systems of any size, empty ones included, go through it.
+    plan_layouts(s);
     if (int rc = ensure_device(s))
         return rc;
-    const int64_t n = (int64_t)s->h_mass.size();
-    s->n = n;
-    s->ns = (int64_t)s->h_k.size();
+    const int64_t n = s->n;
 
     // Reference positions and initial state in internal (spatial) order.
-    plan_order(s);
     std::vector<float4> hX0(n), hU(n), hV(n);
     for (int64_t i = 0; i < n; ++i) {
         const int64_t u = s->perm[i];

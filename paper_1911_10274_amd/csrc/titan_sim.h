@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -27,6 +28,7 @@ struct BP {
 };
 
 struct BatchEngine;  // defined by the batched engine
+struct GatherPlan;   // host tables of the gather layout (engine_gather.hip)
 
 }  // namespace titan
 
@@ -76,6 +78,7 @@ struct titan_sim {
     std::vector<int64_t> h_owner_slot;  // per spring (caller order): its slot at the lower-index end
     std::vector<int64_t> h_other_slot;  // per spring: its slot at the other end
     float2 *trig = nullptr;           // clock table: kTrigChunk entries + 1 for force queries
+    std::shared_ptr<titan::GatherPlan> gplan;  // planned before the device was set up; used once
 
     // topology edits after finalize: the engines' layouts are rebuilt before
     // the next step when dirty; removed springs stay in the spring table
@@ -144,6 +147,9 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
 // selected engine after the state buffers exist, enqueue steps, compute the
 // spring-force sum, and release engine-private resources.
 void plan_order(titan_sim *s);  // fills perm (internal -> caller)
+// Host planning of the first layouts (n, ns, perm, inv_perm, the gather
+// layout's tables), without the device; build_engines then uploads them.
+void plan_layouts(titan_sim *s);
 int build_engines(titan_sim *s);
 int enqueue_steps(titan_sim *s, int64_t first_step, int64_t count);
 int compute_forces(titan_sim *s);

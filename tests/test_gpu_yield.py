@@ -1,4 +1,4 @@
-"""Breakable springs (Sec. III-B yield values) on the GPU, through the C ABI.
+"""Breakable springs (Sec. III-E yield values) on the GPU, through the C ABI.
 
 A break is an integer decision taken from a floating-point value: the GPU
 takes it in FP32, the oracle in FP64.  The parity test uses yields whose

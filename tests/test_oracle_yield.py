@@ -1,4 +1,4 @@
-"""Pins of the oracle's breakable springs (Sec. III-B, material yield values
+"""Pins of the oracle's breakable springs (Sec. III-E, material yield values
 compared against in the force calculation).
 
 Reading: the value compared is the magnitude of the elastic force
