@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TITAN_ABI_VERSION 5
+#define TITAN_ABI_VERSION 6
 
 /* Status codes. */
 #define TITAN_OK 0
@@ -345,6 +345,33 @@ int titan_get_body_displacement(titan_sim *sim, float *disp_nb3);
 int titan_set_springs(titan_sim *sim, int64_t first, int64_t count, const float *k_n, const float *damping_n,
                       const float *amp_n, const float *phase_n);
 
+/* Set the actuation phasor of springs [first, first + count) directly
+ * (Sec. IV-B Eq. 4 with a per-spring phase, written as a phasor): the rest
+ * length at time t becomes rest (1 + C sin(omega t) + S cos(omega t)) with
+ * C = act_c[q], S = act_s[q] exactly as given (titan_set_springs takes amp
+ * and phase and rounds C = amp cos(phase), S = amp sin(phase) to FP32).
+ * Phasor law only (TITAN_ESTATE under the wave law); values must be finite.
+ * In stream order like titan_set_springs.  Ends the voxel map of
+ * titan_set_voxel_actuation if a listed spring was voxel-driven. */
+int titan_set_springs_phasor(titan_sim *sim, int64_t first, int64_t count, const float *act_c,
+                             const float *act_s);
+
+/* Per-voxel actuation (Sec. IV-C drives a swarm's bodies by their own
+ * actuation parameters; here each voxel of a voxel robot has an amplitude
+ * and a phase).  n_voxels voxels with amplitude voxel_a[v] and phase
+ * voxel_phi[v]; sv_ptr (n_springs + 1 entries, sv_ptr[0] = 0, non-decreasing)
+ * and sv_idx list, for each spring s, the voxels sv_idx[sv_ptr[s] ..
+ * sv_ptr[s+1]) that contain it (each at most once).  A spring with a
+ * non-empty list gets the mean of its voxels' phasors a (cos phi, sin phi)
+ * (computed in FP64, stored in FP32) as its actuation phasor; springs with
+ * an empty list keep theirs.  The map is kept for titan_rollout_grad_voxel
+ * until a call changes a voxel-driven spring's actuation directly; springs
+ * added later are not voxel-driven.  Phasor law only (TITAN_ESTATE
+ * otherwise); TITAN_EINVAL for malformed lists or non-finite values.  In
+ * stream order like titan_set_springs. */
+int titan_set_voxel_actuation(titan_sim *sim, int64_t n_voxels, const float *voxel_a, const float *voxel_phi,
+                              const int64_t *sv_ptr, const int32_t *sv_idx);
+
 /* Gradient of a rollout by the adjoint method (not in the paper; Sec. II
  * names differentiable simulation as related work): backward in time through
  * the steps, with the forward states recomputed from checkpoints taken every
@@ -366,6 +393,19 @@ int titan_set_springs(titan_sim *sim, int64_t first, int64_t count, const float 
  * and friction included (their switches are not smoothed). */
 int titan_rollout_grad(titan_sim *sim, int64_t nsteps, int32_t checkpoint_every, const float *body_weights,
                        float *loss_out, float *grad_k, float *grad_act_c, float *grad_act_s);
+
+/* The rollout gradient of titan_rollout_grad (same rollout, loss, checkpoints
+ * and refusals; not in the paper) with the actuation gradient taken per
+ * voxel of the map set by titan_set_voxel_actuation (TITAN_ESTATE if none):
+ * through the mean-phasor map, on the device,
+ *   grad_voxel_a[v]   = dJ/da_v   = sum_s (dJ/dC_s cos phi_v + dJ/dS_s sin phi_v) / n_s,
+ *   grad_voxel_phi[v] = dJ/dphi_v = a_v sum_s (dJ/dS_s cos phi_v - dJ/dC_s sin phi_v) / n_s,
+ * over the springs s that voxel v drives, n_s the number of voxels driving
+ * spring s; each voxel's sum runs over its springs in ascending order.
+ * Outputs (each may be NULL): loss_out[n_bodies], grad_k[n_springs],
+ * grad_voxel_a[n_voxels], grad_voxel_phi[n_voxels]. */
+int titan_rollout_grad_voxel(titan_sim *sim, int64_t nsteps, int32_t checkpoint_every, const float *body_weights,
+                             float *loss_out, float *grad_k, float *grad_voxel_a, float *grad_voxel_phi);
 
 /* Summed spring force on masses [first, first+count) at the current state
  * and the current step's time (blocks): the spring pass of Sec. III-B

@@ -416,6 +416,33 @@ __global__ void gather_spring_grads(const float4 *gslot, const int64_t *owner_sl
     gS[s] = v.z;
 }
 
+// Per-voxel actuation gradients (Sec. IV-C drives bodies by per-voxel
+// parameters; the adjoint itself is not in the paper).  A voxel-driven
+// spring's phasor is the mean of its voxels' a (cos phi, sin phi), so
+// dJ/da_v = sum_s (gC_s cos phi_v + gS_s sin phi_v) / n_s and
+// dJ/dphi_v = a_v sum_s (gS_s cos phi_v - gC_s sin phi_v) / n_s over the
+// springs s of voxel v (n_s: the spring's voxel count).  One thread per voxel,
+// its springs in ascending order: deterministic, no atomics.
+// vw[v] = (cos phi_v, sin phi_v, a_v, 0); inv_cnt[s] = 1 / n_s.
+__global__ void voxel_grads_kernel(int64_t nv, const int64_t *vs_ptr, const int32_t *vs_spring, const float *inv_cnt,
+                                   const float4 *vw, const float *gC, const float *gS, float *ga, float *gphi)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv)
+        return;
+    const float4 w = vw[v];
+    float sa = 0.f, sp = 0.f;
+    for (int64_t e = vs_ptr[v]; e < vs_ptr[v + 1]; ++e) {
+        const int32_t q = vs_spring[e];
+        const float r = inv_cnt[q];
+        const float c = gC[q] * r, sn = gS[q] * r;
+        sa += c * w.x + sn * w.y;
+        sp += sn * w.x - c * w.y;
+    }
+    ga[v] = sa;
+    gphi[v] = w.z * sp;
+}
+
 // J_b = -sum_{i in b} (m_i / M_b) * dux_i: one thread per body, masses of a
 // body contiguous, summed in index order (deterministic).
 __global__ void body_loss(const float *dux, const float *coef, const int64_t *body_off, int64_t nb, float *loss)
@@ -463,6 +490,17 @@ hipError_t launch_spring_grads(const float4 *gslot, const int64_t *owner_slot, i
         return hipSuccess;
     hipLaunchKernelGGL(gather_spring_grads, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, stream, gslot,
                        owner_slot, ns, gk, gC, gS);
+    return hipGetLastError();
+}
+
+hipError_t launch_voxel_grads(int64_t nv, const int64_t *vs_ptr, const int32_t *vs_spring, const float *inv_cnt,
+                              const float4 *vw, const float *gC, const float *gS, float *ga, float *gphi,
+                              hipStream_t stream)
+{
+    if (nv == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(voxel_grads_kernel, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, stream, nv, vs_ptr,
+                       vs_spring, inv_cnt, vw, gC, gS, ga, gphi);
     return hipGetLastError();
 }
 

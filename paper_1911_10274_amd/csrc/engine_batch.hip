@@ -317,8 +317,12 @@ void destroy_batch_engine(titan_sim *s)
 
 // Adjoint rollout on the batched layout (see adjoint_step.hip).
 int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weights, float *loss, float *gk,
-                 float *gC, float *gS)
+                 float *gC, float *gS, float *gvox_a, float *gvox_phi)
 {
+    const bool voxels = gvox_a || gvox_phi;
+    const int64_t nv = (int64_t)s->h_vox_a.size();
+    if (voxels && s->h_vs_ptr.empty())
+        return fail(TITAN_ESTATE, "no voxel actuation (titan_set_voxel_actuation)");
     if (!s->batch)
         return fail(TITAN_ESTATE, "the rollout gradient needs every body to fit one workgroup's LDS");
     if (nsteps < 0 || K < 1)
@@ -339,6 +343,9 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
         for (float *g : {gk, gC, gS})
             if (g)
                 std::fill(g, g + ns, 0.f);
+        for (float *g : {gvox_a, gvox_phi})
+            if (g)
+                std::fill(g, g + nv, 0.f);
         return TITAN_OK;
     }
     K = (int32_t)std::min<int64_t>(K, std::max<int64_t>(nsteps, 1));
@@ -437,6 +444,45 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
     TRY(launch_adjoint(s->gg, s->batch->lay, a, sc, s->stream));
     TRY(launch_spring_grads(a.gslot, downer, ns, dgrad, dgrad + ns, dgrad + 2 * ns, s->stream));
     TRY(launch_body_loss(a.dux, dcoef, dboff, nruns, dloss, s->stream));
+    // per-voxel gradients through the mean-phasor map, on the device: each
+    // voxel sums over its springs (ascending) the spring's (dJ/dC, dJ/dS)
+    // divided by the spring's voxel count, turned by the voxel's phase
+    std::vector<float> hvox;
+    float *dvox = nullptr;
+    if (voxels && nv > 0) {
+        int64_t *dvptr = nullptr;
+        int32_t *dvspring = nullptr;
+        float *dinv = nullptr;
+        float4 *dvw = nullptr;
+        const int64_t nidx = (int64_t)s->h_vs_spring.size();
+        std::vector<float> inv(ns, 0.f);
+        for (int64_t q = 0; q < ns; ++q)
+            if (q < (int64_t)s->h_sv_count.size() && s->h_sv_count[q] > 0)
+                inv[q] = (float)(1.0 / (double)s->h_sv_count[q]);
+        std::vector<float4> vw(nv);
+        for (int64_t v = 0; v < nv; ++v) {
+            const double ph = s->h_vox_phi[v];
+            vw[v] = make_float4((float)std::cos(ph), (float)std::sin(ph), s->h_vox_a[v], 0.f);
+        }
+        if ((rc = get(sizeof(int64_t) * (nv + 1), (void **)&dvptr)) ||
+            (rc = get(sizeof(int32_t) * std::max<int64_t>(nidx, 1), (void **)&dvspring)) ||
+            (rc = get(sizeof(float) * std::max<int64_t>(ns, 1), (void **)&dinv)) ||
+            (rc = get(sizeof(float4) * nv, (void **)&dvw)) || (rc = get(sizeof(float) * 2 * nv, (void **)&dvox))) {
+            cleanup();
+            return rc;
+        }
+        TRY(hipMemcpyAsync(dvptr, s->h_vs_ptr.data(), sizeof(int64_t) * (nv + 1), hipMemcpyHostToDevice, s->stream));
+        if (nidx)
+            TRY(hipMemcpyAsync(dvspring, s->h_vs_spring.data(), sizeof(int32_t) * nidx, hipMemcpyHostToDevice,
+                               s->stream));
+        if (ns)
+            TRY(hipMemcpyAsync(dinv, inv.data(), sizeof(float) * ns, hipMemcpyHostToDevice, s->stream));
+        TRY(hipMemcpyAsync(dvw, vw.data(), sizeof(float4) * nv, hipMemcpyHostToDevice, s->stream));
+        TRY(launch_voxel_grads(nv, dvptr, dvspring, dinv, dvw, dgrad + ns, dgrad + 2 * ns, dvox, dvox + nv,
+                               s->stream));
+        hvox.resize(2 * nv);
+        TRY(hipMemcpyAsync(hvox.data(), dvox, sizeof(float) * 2 * nv, hipMemcpyDeviceToHost, s->stream));
+    }
     std::vector<float> hgrad(3 * ns), hloss(nruns);
     unsigned long long bad = ~0ull;
     TRY(hipMemcpyAsync(hgrad.data(), dgrad, sizeof(float) * 3 * ns, hipMemcpyDeviceToHost, s->stream));
@@ -453,6 +499,10 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
         std::copy(hgrad.begin() + ns, hgrad.begin() + 2 * ns, gC);
     if (gS)
         std::copy(hgrad.begin() + 2 * ns, hgrad.end(), gS);
+    if (gvox_a && nv)
+        std::copy(hvox.begin(), hvox.begin() + nv, gvox_a);
+    if (gvox_phi && nv)
+        std::copy(hvox.begin() + nv, hvox.end(), gvox_phi);
     if (loss) {
         for (int32_t b = 0; b < nb; ++b)
             loss[b] = 0.f;

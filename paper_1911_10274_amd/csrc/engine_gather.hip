@@ -142,12 +142,19 @@ void plan_order(titan_sim *s)
     }
 }
 
-// Per-spring constants in the layouts' form (FP64 -> FP32).
-// Phasor actuation: C = amp cos(phase), S = amp sin(phase).
+// Per-spring constants in the layouts' form.
+// Phasor actuation: C = amp cos(phase), S = amp sin(phase), kept in the host
+// tables (FP32 of the FP64 products, or the values given directly).
 static void phasor_consts(const titan_sim *s, int64_t q, float &C, float &S)
 {
-    C = (float)((double)s->h_amp[q] * std::cos((double)s->h_phase[q]));
-    S = (float)((double)s->h_amp[q] * std::sin((double)s->h_phase[q]));
+    C = s->h_C[q];
+    S = s->h_S[q];
+}
+
+// Does spring q carry actuation (either law)?
+static bool actuated(const titan_sim *s, int64_t q)
+{
+    return s->h_amp[q] != 0.f || s->h_C[q] != 0.f || s->h_S[q] != 0.f;
 }
 
 // Explicit rest length L (else the reference length |R|): d0 = |R| - L, L0 = L.
@@ -281,7 +288,7 @@ static void plan_gather(titan_sim *s, bool allow_tiled, GatherPlan &P)
             continue;
         if (q0 < 0)
             q0 = q;
-        act |= s->h_amp[q] != 0.f;
+        act |= actuated(s, q);
         rest |= s->h_rest[q] > 0.f;
         damp_uniform &= s->h_damp[q] == s->h_damp[q0];
         k_uniform &= s->h_k[q] == s->h_k[q0];
@@ -636,13 +643,9 @@ int update_spring_list(titan_sim *s, const std::vector<int64_t> &springs, bool k
     } else if (!e && amp && s->params.actuation == TITAN_ACT_WAVE) {
         rc = fail(TITAN_ESTATE, "wave actuation must be present when the system is finalized");
     } else if (!e && amp) {
-        e = apply(&g.act_c, 0.f, [&](int64_t q) {
-            return (float)((double)s->h_amp[q] * std::cos((double)s->h_phase[q]));
-        });
+        e = apply(&g.act_c, 0.f, [&](int64_t q) { return s->h_C[q]; });
         if (!e)
-            e = apply(&g.act_s, 0.f, [&](int64_t q) {
-                return (float)((double)s->h_amp[q] * std::sin((double)s->h_phase[q]));
-            });
+            e = apply(&g.act_s, 0.f, [&](int64_t q) { return s->h_S[q]; });
     }
     if (e != hipSuccess)
         rc = e == hipErrorOutOfMemory ? fail(TITAN_ENOMEM, "out of device memory updating spring constants")
@@ -976,7 +979,7 @@ int insert_springs(titan_sim *s, int64_t first, int64_t count)
     std::unordered_map<int64_t, int32_t> extra;  // slots taken in this call, per row
     for (int64_t q = first; q < first + count; ++q) {
         if ((!g.k && s->h_k[q] != g.k_uniform) || (!g.c && s->h_damp[q] != g.c_uniform) ||
-            (!act && s->h_amp[q] != 0.f))
+            (!act && actuated(s, q)))
             return 2;
         const int64_t i = s->inv_perm_of(s->h_ends[2 * q]), j = s->inv_perm_of(s->h_ends[2 * q + 1]);
         for (int side = 0; side < 2; ++side) {

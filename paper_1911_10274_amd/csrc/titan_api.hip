@@ -170,6 +170,24 @@ static int check_params(const titan_params *p)
     return TITAN_OK;
 }
 
+// A direct change of the actuation of springs [first, first + count) ends the
+// voxel map if any of them was voxel-driven (their phasors no longer follow
+// the voxels).
+static void drop_voxel_map_over(titan_sim *s, int64_t first, int64_t count)
+{
+    if (s->h_sv_count.empty())
+        return;
+    for (int64_t q = first; q < first + count && q < (int64_t)s->h_sv_count.size(); ++q)
+        if (s->h_sv_count[q] > 0) {
+            s->h_vox_a.clear();
+            s->h_vox_phi.clear();
+            s->h_vs_ptr.clear();
+            s->h_vs_spring.clear();
+            s->h_sv_count.clear();
+            return;
+        }
+}
+
 // ---------------------------------------------------------------------------
 // ABI: lifetime
 // ---------------------------------------------------------------------------
@@ -347,10 +365,18 @@ extern "C" int titan_add_springs(titan_sim *s, int64_t n, const int64_t *ends, c
     if (amp) {
         s->h_amp.insert(s->h_amp.end(), amp, amp + n);
         s->h_phase.insert(s->h_phase.end(), phase, phase + n);
+        for (int64_t q = 0; q < n; ++q) {
+            s->h_C.push_back((float)((double)amp[q] * std::cos((double)phase[q])));
+            s->h_S.push_back((float)((double)amp[q] * std::sin((double)phase[q])));
+        }
     } else {
         s->h_amp.insert(s->h_amp.end(), (size_t)n, 0.f);
         s->h_phase.insert(s->h_phase.end(), (size_t)n, 0.f);
+        s->h_C.insert(s->h_C.end(), (size_t)n, 0.f);
+        s->h_S.insert(s->h_S.end(), (size_t)n, 0.f);
     }
+    if (!s->h_sv_count.empty())
+        s->h_sv_count.resize(s->h_k.size(), 0);  // new springs are not voxel-driven
     if (!s->h_removed.empty())
         s->h_removed.resize(s->h_k.size(), 0);
     if (!s->h_yield.empty())
@@ -1075,13 +1101,128 @@ extern "C" int titan_set_springs(titan_sim *s, int64_t first, int64_t count, con
         if (amp) {
             s->h_amp[first + q] = amp[q];
             s->h_phase[first + q] = phase[q];
+            s->h_C[first + q] = (float)((double)amp[q] * std::cos((double)phase[q]));
+            s->h_S[first + q] = (float)((double)amp[q] * std::sin((double)phase[q]));
         }
     }
+    if (amp)
+        drop_voxel_map_over(s, first, count);
     if (!s->finalized)
         return TITAN_OK;
     if (int rc = ready(s))
         return rc;
     return update_springs(s, first, count, k, damping, amp, phase);
+}
+
+extern "C" int titan_set_springs_phasor(titan_sim *s, int64_t first, int64_t count, const float *act_c,
+                                        const float *act_s)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (first < 0 || count < 0 || first + count > (int64_t)s->h_k.size())
+        return fail(TITAN_EINVAL, "spring range [%lld, %lld) outside [0, %lld)", (long long)first,
+                    (long long)(first + count), (long long)s->h_k.size());
+    if (count > 0 && (!act_c || !act_s))
+        return fail(TITAN_EINVAL, "act_c and act_s are required");
+    if (s->params.actuation != TITAN_ACT_PHASOR)
+        return fail(TITAN_ESTATE, "(C, S) phasors belong to the phasor actuation law");
+    for (int64_t q = 0; q < count; ++q)
+        if (!(std::isfinite(act_c[q]) && std::isfinite(act_s[q])))
+            return fail(TITAN_EINVAL, "spring %lld: non-finite actuation", (long long)(first + q));
+    invalidate_step_cache(s);
+    for (int64_t q = 0; q < count; ++q) {
+        const int64_t t = first + q;
+        s->h_C[t] = act_c[q];
+        s->h_S[t] = act_s[q];
+        s->h_amp[t] = (float)std::hypot((double)act_c[q], (double)act_s[q]);
+        s->h_phase[t] = (float)std::atan2((double)act_s[q], (double)act_c[q]);
+    }
+    drop_voxel_map_over(s, first, count);
+    if (!s->finalized)
+        return TITAN_OK;
+    if (int rc = ready(s))
+        return rc;
+    std::vector<float> one(count, 1.f);  // marks "actuation changed" (values come from the tables)
+    return update_springs(s, first, count, nullptr, nullptr, one.data(), one.data());
+}
+
+extern "C" int titan_set_voxel_actuation(titan_sim *s, int64_t n_voxels, const float *voxel_a, const float *voxel_phi,
+                                         const int64_t *sv_ptr, const int32_t *sv_idx)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    const int64_t ns = (int64_t)s->h_k.size();
+    if (n_voxels < 0 || (n_voxels > 0 && (!voxel_a || !voxel_phi)) || !sv_ptr)
+        return fail(TITAN_EINVAL, "need n_voxels >= 0, voxel_a, voxel_phi and sv_ptr");
+    if (n_voxels > (int64_t)std::numeric_limits<int32_t>::max())
+        return fail(TITAN_EINVAL, "too many voxels");
+    if (s->params.actuation != TITAN_ACT_PHASOR)
+        return fail(TITAN_ESTATE, "voxel actuation drives the phasor actuation law");
+    if (sv_ptr[0] != 0)
+        return fail(TITAN_EINVAL, "sv_ptr[0] must be 0");
+    for (int64_t q = 0; q < ns; ++q)
+        if (sv_ptr[q + 1] < sv_ptr[q])
+            return fail(TITAN_EINVAL, "sv_ptr decreases at spring %lld", (long long)q);
+    const int64_t nidx = sv_ptr[ns];
+    if (nidx > 0 && !sv_idx)
+        return fail(TITAN_EINVAL, "sv_idx is required");
+    for (int64_t e = 0; e < nidx; ++e)
+        if (sv_idx[e] < 0 || sv_idx[e] >= n_voxels)
+            return fail(TITAN_EINVAL, "voxel index %d out of range [0, %lld)", sv_idx[e], (long long)n_voxels);
+    for (int64_t v = 0; v < n_voxels; ++v)
+        if (!(std::isfinite(voxel_a[v]) && std::isfinite(voxel_phi[v])))
+            return fail(TITAN_EINVAL, "voxel %lld: non-finite actuation", (long long)v);
+    for (int64_t q = 0; q < ns; ++q)
+        for (int64_t e = sv_ptr[q] + 1; e < sv_ptr[q + 1]; ++e)
+            if (sv_idx[e] == sv_idx[e - 1])
+                return fail(TITAN_EINVAL, "spring %lld lists voxel %d twice", (long long)q, sv_idx[e]);
+    invalidate_step_cache(s);
+    // each voxel-driven spring's phasor: the mean of its voxels' a (cos phi,
+    // sin phi), in FP64, stored in FP32
+    std::vector<int64_t> changed;
+    for (int64_t q = 0; q < ns; ++q) {
+        const int64_t cnt = sv_ptr[q + 1] - sv_ptr[q];
+        if (cnt == 0)
+            continue;
+        double c = 0.0, sn = 0.0;
+        for (int64_t e = sv_ptr[q]; e < sv_ptr[q + 1]; ++e) {
+            const double a = voxel_a[sv_idx[e]], ph = voxel_phi[sv_idx[e]];
+            c += a * std::cos(ph);
+            sn += a * std::sin(ph);
+        }
+        c /= (double)cnt;
+        sn /= (double)cnt;
+        s->h_C[q] = (float)c;
+        s->h_S[q] = (float)sn;
+        s->h_amp[q] = (float)std::hypot(c, sn);
+        s->h_phase[q] = (float)std::atan2(sn, c);
+        changed.push_back(q);
+    }
+    // the map, turned around: each voxel's springs in ascending order
+    s->h_vox_a.assign(voxel_a, voxel_a + n_voxels);
+    s->h_vox_phi.assign(voxel_phi, voxel_phi + n_voxels);
+    s->h_sv_count.assign(ns, 0);
+    s->h_vs_ptr.assign(n_voxels + 1, 0);
+    for (int64_t e = 0; e < nidx; ++e)
+        ++s->h_vs_ptr[sv_idx[e] + 1];
+    for (int64_t v = 0; v < n_voxels; ++v)
+        s->h_vs_ptr[v + 1] += s->h_vs_ptr[v];
+    s->h_vs_spring.assign(nidx, 0);
+    {
+        std::vector<int64_t> fill(s->h_vs_ptr.begin(), s->h_vs_ptr.end() - 1);
+        for (int64_t q = 0; q < ns; ++q) {
+            s->h_sv_count[q] = (int32_t)(sv_ptr[q + 1] - sv_ptr[q]);
+            for (int64_t e = sv_ptr[q]; e < sv_ptr[q + 1]; ++e)
+                s->h_vs_spring[fill[sv_idx[e]]++] = (int32_t)q;
+        }
+    }
+    if (!s->finalized || changed.empty())
+        return TITAN_OK;
+    if (int rc = ready(s))
+        return rc;
+    return update_spring_list(s, changed, false, false, true, false);
 }
 
 extern "C" int titan_get_body_displacement(titan_sim *s, float *disp)
@@ -1172,6 +1313,36 @@ extern "C" int titan_rollout_grad(titan_sim *s, int64_t nsteps, int32_t checkpoi
     if (int rc = ensure_layout(s))
         return rc;
     return rollout_grad(s, nsteps, checkpoint_every, body_weights, loss_out, grad_k, grad_act_c, grad_act_s);
+}
+
+extern "C" int titan_rollout_grad_voxel(titan_sim *s, int64_t nsteps, int32_t checkpoint_every,
+                                        const float *body_weights, float *loss_out, float *grad_k,
+                                        float *grad_voxel_a, float *grad_voxel_phi)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->h_vs_ptr.empty())
+        return fail(TITAN_ESTATE, "no voxel actuation (titan_set_voxel_actuation)");
+    if (s->params.actuation != TITAN_ACT_PHASOR)
+        return fail(TITAN_ESTATE, "the rollout adjoint covers phasor actuation only");
+    if (s->params.integrator != TITAN_INTEG_EULER)
+        return fail(TITAN_ESTATE, "the rollout adjoint covers the Euler integrator only");
+    if (!s->h_yield.empty())
+        return fail(TITAN_ESTATE, "the rollout adjoint covers unbreakable springs only");
+    if (int rc = ready(s))
+        return rc;
+    if (int rc = ensure_layout(s))
+        return rc;
+    std::vector<float> ga(s->h_vox_a.size()), gp(s->h_vox_a.size());
+    if (int rc = rollout_grad(s, nsteps, checkpoint_every, body_weights, loss_out, grad_k, nullptr, nullptr,
+                              ga.data(), gp.data()))
+        return rc;
+    if (grad_voxel_a)
+        std::copy(ga.begin(), ga.end(), grad_voxel_a);
+    if (grad_voxel_phi)
+        std::copy(gp.begin(), gp.end(), grad_voxel_phi);
+    return TITAN_OK;
 }
 
 extern "C" int titan_get_info(titan_sim *s, titan_info *info)

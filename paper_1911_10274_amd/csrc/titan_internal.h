@@ -182,6 +182,9 @@ hipError_t launch_adjoint(const GatherGraph &g, const BatchLayout &b, const Adjo
 hipError_t launch_spring_grads(const float4 *gslot, const int64_t *owner_slot, int64_t ns, float *gk, float *gC,
                                float *gS, hipStream_t stream);
 // loss[b] = -sum over internal masses [body_off[b], body_off[b+1]) of coef * dux
+hipError_t launch_voxel_grads(int64_t nv, const int64_t *vs_ptr, const int32_t *vs_spring, const float *inv_cnt,
+                              const float4 *vw, const float *gC, const float *gS, float *ga, float *gphi,
+                              hipStream_t stream);
 hipError_t launch_body_loss(const float *dux, const float *coef, const int64_t *body_off, int64_t nb, float *loss,
                             hipStream_t stream);
 

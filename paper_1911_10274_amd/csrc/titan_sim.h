@@ -44,6 +44,16 @@ struct titan_sim {
     std::vector<int32_t> h_body;
     std::vector<int64_t> h_ends;
     std::vector<float> h_k, h_damp, h_rest, h_amp, h_phase;
+    // phasor law: each spring's (C, S) = amp (cos phase, sin phase), rounded
+    // to FP32 from FP64, or given directly (titan_set_springs_phasor, voxels)
+    std::vector<float> h_C, h_S;
+    // per-voxel actuation (titan_set_voxel_actuation): each voxel's amplitude
+    // and phase, its springs in ascending order, and per spring the number of
+    // voxels that drive it (0: not voxel-driven).  Empty: no voxel map.
+    std::vector<float> h_vox_a, h_vox_phi;
+    std::vector<int64_t> h_vs_ptr;
+    std::vector<int32_t> h_vs_spring;
+    std::vector<int32_t> h_sv_count;
 
     // device state
     bool finalized = false;
@@ -140,8 +150,10 @@ int update_springs(titan_sim *s, int64_t first, int64_t count, const float *k, c
 // write per-slot arrays even where the values stay uniform (removal).
 int update_spring_list(titan_sim *s, const std::vector<int64_t> &springs, bool k, bool damping, bool amp,
                        bool force);
+// The rollout adjoint; with gvox_a / gvox_phi (either non-null) also the
+// gradients of the per-voxel actuation (the sim's voxel map must be set).
 int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weights, float *loss, float *gk,
-                 float *gC, float *gS);
+                 float *gC, float *gS, float *gvox_a = nullptr, float *gvox_phi = nullptr);
 
 // Engines (engine_gather.hip): build the device representation of the
 // selected engine after the state buffers exist, enqueue steps, compute the

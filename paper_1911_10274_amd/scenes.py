@@ -325,11 +325,30 @@ def concat(robots: list[dict]) -> dict:
         return np.concatenate([r[key] for r in robots])
 
     body = np.concatenate([np.full(r["pos"].shape[0], b, np.int32) for b, r in enumerate(robots)])
-    return dict(
+    out = dict(
         pos=cat("pos"), vel=cat("vel"), mass=cat("mass"), ends=ends, k=cat("k"),
         damping=cat("damping"), amp=cat("amp"), phase=cat("phase"), body=body,
         mass_ptr=mass_ptr, spring_ptr=spring_ptr,
     )
+    if all("sv_ptr" in r for r in robots):
+        # the voxel maps side by side: voxels numbered body after body
+        voxel_ptr = np.zeros(len(robots) + 1, np.int64)
+        for b, r in enumerate(robots):
+            voxel_ptr[b + 1] = voxel_ptr[b] + np.asarray(r["voxel_a"]).size
+        sv_ptr = [np.zeros(1, np.int64)]
+        base = 0
+        for r in robots:
+            sv_ptr.append(np.asarray(r["sv_ptr"][1:], np.int64) + base)
+            base += int(r["sv_ptr"][-1])
+        out.update(
+            voxel_a=np.concatenate([r["voxel_a"] for r in robots]),
+            voxel_phi=np.concatenate([r["voxel_phi"] for r in robots]),
+            voxel_ptr=voxel_ptr,
+            sv_ptr=np.concatenate(sv_ptr),
+            sv_idx=np.concatenate([np.asarray(r["sv_idx"], np.int64) + voxel_ptr[b]
+                                   for b, r in enumerate(robots)]).astype(np.int32),
+        )
+    return out
 
 
 # ----------------------------------------------------------------------------

@@ -134,6 +134,9 @@ def _load():
         "titan_set_yield": ([_vp, ctypes.c_int64, ctypes.c_int64, _fp], ctypes.c_int),
         "titan_get_broken": ([_vp, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint8)], ctypes.c_int),
         "titan_rollout_grad": ([_vp, ctypes.c_int64, ctypes.c_int32, _fp, _fp, _fp, _fp, _fp], ctypes.c_int),
+        "titan_set_springs_phasor": ([_vp, ctypes.c_int64, ctypes.c_int64, _fp, _fp], ctypes.c_int),
+        "titan_set_voxel_actuation": ([_vp, ctypes.c_int64, _fp, _fp, _i64p, _i32p], ctypes.c_int),
+        "titan_rollout_grad_voxel": ([_vp, ctypes.c_int64, ctypes.c_int32, _fp, _fp, _fp, _fp, _fp], ctypes.c_int),
         "titan_get_info": ([_vp, ctypes.POINTER(_Info)], ctypes.c_int),
         "titan_mlp_create": ([ctypes.c_int32, _i32p, _vp, ctypes.POINTER(_Allocator), ctypes.POINTER(_vp)],
                              ctypes.c_int),
@@ -417,6 +420,37 @@ class Sim:
         _check(lib.titan_rollout_grad(self._h, int(nsteps), int(checkpoint_every), wp, loss.ctypes.data_as(_fp),
                                       gk.ctypes.data_as(_fp), gc.ctypes.data_as(_fp), gs.ctypes.data_as(_fp)))
         return loss, gk, gc, gs
+
+    def set_springs_phasor(self, first: int = 0, act_c=None, act_s=None):
+        """Actuation phasors (C, S) of springs [first, first + len) as given."""
+        c, cp = _f32(act_c, (-1,))
+        s_, sp = _f32(act_s, (c.size,))
+        _check(lib.titan_set_springs_phasor(self._h, int(first), c.size, cp, sp))
+
+    def set_voxel_actuation(self, voxel_a, voxel_phi, sv_ptr, sv_idx):
+        """Per-voxel amplitude and phase; sv_ptr / sv_idx list each spring's
+        voxels (n_springs + 1 offsets)."""
+        a, ap = _f32(voxel_a, (-1,))
+        ph, pp = _f32(voxel_phi, (a.size,))
+        ptr = np.ascontiguousarray(sv_ptr, dtype=np.int64)
+        idx = np.ascontiguousarray(sv_idx, dtype=np.int32)
+        _check(lib.titan_set_voxel_actuation(self._h, a.size, ap, pp, ptr.ctypes.data_as(_i64p),
+                                             idx.ctypes.data_as(_i32p)))
+        self._n_voxels = a.size
+
+    def rollout_grad_voxel(self, nsteps: int, checkpoint_every: int = 50, body_weights=None, n_voxels=None):
+        """As ``rollout_grad`` with the actuation gradient per voxel: returns
+        (loss per body, dJ/dk, dJ/da per voxel, dJ/dphi per voxel)."""
+        info = self.info()
+        nb, ns = info["n_bodies"], info["n_springs"]
+        w, wp = _f32(body_weights, (nb,)) if body_weights is not None else (None, None)
+        nv = int(n_voxels if n_voxels is not None else getattr(self, "_n_voxels", 0))
+        loss = np.empty(nb, np.float32)
+        gk = np.empty(ns, np.float32)
+        ga, gp = np.empty(nv, np.float32), np.empty(nv, np.float32)
+        _check(lib.titan_rollout_grad_voxel(self._h, int(nsteps), int(checkpoint_every), wp, loss.ctypes.data_as(_fp),
+                                            gk.ctypes.data_as(_fp), ga.ctypes.data_as(_fp), gp.ctypes.data_as(_fp)))
+        return loss, gk, ga, gp
 
     def set_step(self, step: int):
         _check(lib.titan_set_step(self._h, int(step)))

@@ -194,3 +194,43 @@ def test_host_layout_planning_of_degenerate_systems():
     r = subprocess.run([sys.executable, "-c", _PLAN_SCRIPT.format(root=ROOT)], capture_output=True, text=True,
                        timeout=300)
     assert r.returncode == 0 and "PLANNED" in r.stdout, (r.returncode, r.stdout[-2000:], r.stderr[-2000:])
+
+
+def test_voxel_actuation_validation_without_gpu():
+    from paper_1911_10274_amd import titan as T
+
+    sim = _host_sim()
+    sim.add_masses([[0, 0, 0], [1, 0, 0], [0, 1, 0]], [1, 1, 1])
+    sim.add_springs([[0, 1], [1, 2], [0, 2]], [1.0, 1.0, 1.0])
+    a = np.array([0.1, 0.2], np.float32)
+    ph = np.array([0.5, 1.0], np.float32)
+    good_ptr, good_idx = [0, 1, 3, 3], [0, 0, 1]
+    sim.set_voxel_actuation(a, ph, good_ptr, good_idx)  # host tables only before the first step
+    bad = [
+        (a, ph, [1, 1, 3, 3], good_idx),            # sv_ptr[0] != 0
+        (a, ph, [0, 2, 1, 3], [0, 0, 1]),           # decreasing
+        (a, ph, [0, 1, 3, 3], [0, 0, 2]),           # voxel out of range
+        (a, ph, [0, 1, 3, 3], [0, 1, 1]),           # a voxel listed twice for one spring
+        (np.array([np.nan, 0.2], np.float32), ph, good_ptr, good_idx),
+    ]
+    for va, vp, ptr, idx in bad:
+        with pytest.raises(T.TitanError) as ei:
+            sim.set_voxel_actuation(va, vp, ptr, idx)
+        assert ei.value.code == T.EINVAL
+    with pytest.raises(T.TitanError) as ei:
+        sim.set_springs_phasor(0, [np.inf], [0.0])
+    assert ei.value.code == T.EINVAL
+    with pytest.raises(T.TitanError) as ei:
+        sim.set_springs_phasor(2, [0.1, 0.1], [0.0, 0.0])  # past the last spring
+    assert ei.value.code == T.EINVAL
+    sim.set_springs_phasor(0, [0.1, 0.0, -0.2], [0.0, 0.3, 0.1])
+    sim.close()
+    wave = T.Sim(T.Params(actuation=T.ACT_WAVE), memory="hip")
+    wave.add_masses([[0, 0, 0], [1, 0, 0]], [1, 1])
+    wave.add_springs([[0, 1]], [1.0])
+    for call in (lambda: wave.set_springs_phasor(0, [0.1], [0.0]),
+                 lambda: wave.set_voxel_actuation([0.1], [0.0], [0, 1], [0])):
+        with pytest.raises(T.TitanError) as ei:
+            call()
+        assert ei.value.code == T.ESTATE
+    wave.close()

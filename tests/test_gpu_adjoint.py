@@ -55,19 +55,73 @@ def test_adjoint_matches_oracle_adjoint_8_robots():
     np.testing.assert_allclose(loss, ref["loss"], rtol=1e-3)
 
 
+def _voxel_scene(robots):
+    """The robots side by side with their voxel maps, voxel values rounded to
+    FP32 (what the library receives) and the springs' phasors recomputed in
+    FP64 from those values (what the oracle receives)."""
+    sc = scenes.concat(robots)
+    sc["voxel_a"] = sc["voxel_a"].astype(np.float32)
+    sc["voxel_phi"] = sc["voxel_phi"].astype(np.float32)
+    amp, ph = scenes.voxel_to_spring_actuation(sc["voxel_a"], sc["voxel_phi"], sc["sv_ptr"], sc["sv_idx"])
+    return sc, dict(sc, amp=amp, phase=ph)
+
+
+def _gpu_voxel_grad(sc, nsteps, K=50):
+    from paper_1911_10274_amd import titan as T
+
+    sim = T.sim_from_scene(sc, _tp())
+    sim.set_voxel_actuation(sc["voxel_a"], sc["voxel_phi"], sc["sv_ptr"], sc["sv_idx"])
+    out = sim.rollout_grad_voxel(nsteps, K)
+    per_spring = sim.rollout_grad(nsteps, K)
+    sim.close()
+    return out, per_spring
+
+
+def test_voxel_grads_match_oracle_adjoint_8_robots():
+    """Config 4's check set (8 robots of the 256-robot batch generator):
+    per-voxel amplitude and phase gradients from the library (mapped on the
+    device) against the oracle's FP64 adjoint mapped by the oracle's chain
+    rule; and the device map against the same chain rule applied to the
+    library's own per-spring gradients (FP32 sums of at most 28 terms)."""
+    robots = scenes.robot_batch(8, seed=4, side_lo=4, side_hi=8)
+    sc, osc = _voxel_scene(robots)
+    (loss, gk, ga, gp), (loss2, gk2, gC2, gS2) = _gpu_voxel_grad(sc, 500, 50)
+    np.testing.assert_array_equal(loss, loss2)
+    np.testing.assert_array_equal(gk, gk2)
+    ref = O.System(osc).rollout_grad(OP, 500, body=sc["body"])
+    ra, rp = O.voxel_grads(ref["gC"], ref["gS"], sc["voxel_a"], sc["voxel_phi"], sc["sv_ptr"], sc["sv_idx"])
+    for name, g, r in (("a", ga, ra), ("phi", gp, rp), ("k", gk, ref["gk"])):
+        e = np.linalg.norm(g - r) / np.linalg.norm(r)
+        c = _cos(g.astype(np.float64), r)
+        print("voxel", name, "rel", e, "cos", c)
+        assert e <= 1e-3 and c >= 0.9999
+    np.testing.assert_allclose(loss, ref["loss"], rtol=1e-3)
+    # the device map itself: same chain rule on the library's per-spring output
+    ma, mp = O.voxel_grads(gC2.astype(np.float64), gS2.astype(np.float64), sc["voxel_a"], sc["voxel_phi"],
+                           sc["sv_ptr"], sc["sv_idx"])
+    absg = np.abs(gC2.astype(np.float64)) + np.abs(gS2.astype(np.float64))
+    bound_a, _ = O.voxel_grads(absg, absg, np.ones(sc["voxel_a"].size), np.zeros(sc["voxel_a"].size),
+                               sc["sv_ptr"], sc["sv_idx"])
+    tol = 64 * 2.0 ** -24 * bound_a
+    assert np.all(np.abs(ga - ma) <= tol)
+    assert np.all(np.abs(gp - mp) <= tol * np.abs(sc["voxel_a"]))
+
+
 def test_adjoint_voxel_grads_match_fp64_fd():
     # the 8-robot check of the adjoint batch: FP64 central differences
-    # (h = 1e-6) of the oracle's 500-step rollout for the largest voxel
-    # gradients of each robot
+    # (h = 1e-6) of the oracle's 500-step rollout, in the voxel amplitudes and
+    # phases, against the library's per-voxel gradients, for the largest
+    # voxel gradients of each robot
     robots = scenes.robot_batch(8, seed=4, side_lo=4, side_hi=8)
-    sc = scenes.concat(robots)
-    (loss, gk, gC, gS), _ = _gpu_grad(sc, 500, 50)
+    sc, _ = _voxel_scene(robots)
+    (loss, gk, ga_all, gp_all), _ = _gpu_voxel_grad(sc, 500, 50)
     h = 1e-6
     checked = skipped = 0
     for b, r in enumerate(robots):
-        s0, s1 = sc["spring_ptr"][b], sc["spring_ptr"][b + 1]
-        ga, gp = O.voxel_grads(gC[s0:s1].astype(np.float64), gS[s0:s1].astype(np.float64), r["voxel_a"],
-                               r["voxel_phi"], r["sv_ptr"], r["sv_idx"])
+        v0, v1 = sc["voxel_ptr"][b], sc["voxel_ptr"][b + 1]
+        ga, gp = ga_all[v0:v1].astype(np.float64), gp_all[v0:v1].astype(np.float64)
+        va0 = sc["voxel_a"][v0:v1].astype(np.float64)
+        vp0 = sc["voxel_phi"][v0:v1].astype(np.float64)
         scale = max(np.abs(ga).max(), np.abs(gp).max())
 
         def loss_at(va, vp):
@@ -77,12 +131,12 @@ def test_adjoint_voxel_grads_match_fp64_fd():
             l, sig = O.System(s2).rollout_loss(OP, 500)
             return l[0], sig
 
-        _, base_sig = loss_at(r["voxel_a"], r["voxel_phi"])
+        _, base_sig = loss_at(va0, vp0)
         for which, grad in (("a", ga), ("phi", gp)):
             for v in np.argsort(-np.abs(grad))[:4]:
                 vals, sigs = [], []
                 for sgn in (1, -1):
-                    va, vp = r["voxel_a"].copy(), r["voxel_phi"].copy()
+                    va, vp = va0.copy(), vp0.copy()
                     (va if which == "a" else vp)[v] += sgn * h
                     l, sg = loss_at(va, vp)
                     vals.append(l)
@@ -95,6 +149,59 @@ def test_adjoint_voxel_grads_match_fp64_fd():
                 assert abs(fd - grad[v]) <= 1e-3 * scale, (b, which, v, fd, grad[v], scale)
     print("checked", checked, "skipped", skipped)
     assert checked >= 48
+
+
+def _mean_phasor(va, vp, sv_ptr, sv_idx):
+    # each spring's mean of a (cos phi, sin phi) over its voxels, in list
+    # order in FP64, rounded to FP32
+    C = np.zeros(len(sv_ptr) - 1, np.float32)
+    S = np.zeros(len(sv_ptr) - 1, np.float32)
+    for q in range(len(sv_ptr) - 1):
+        c = s = 0.0
+        for e in range(sv_ptr[q], sv_ptr[q + 1]):
+            a, ph = float(va[sv_idx[e]]), float(vp[sv_idx[e]])
+            c += a * math.cos(ph)
+            s += a * math.sin(ph)
+        n = sv_ptr[q + 1] - sv_ptr[q]
+        C[q], S[q] = c / n, s / n
+    return C, S
+
+
+def test_voxel_actuation_sets_mean_phasors_and_map_ends_on_direct_change():
+    from paper_1911_10274_amd import titan as T
+
+    robots = scenes.robot_batch(3, seed=15, side_lo=3, side_hi=5)
+    sc, osc = _voxel_scene(robots)
+    # a sim whose springs start unactuated gets its phasors from the voxels:
+    # the same run as a sim built with the oracle's phasors
+    bare = dict(sc, amp=None, phase=None)
+    a = T.sim_from_scene(bare, _tp())
+    a.set_voxel_actuation(sc["voxel_a"], sc["voxel_phi"], sc["sv_ptr"], sc["sv_idx"])
+    c, s_ = _mean_phasor(sc["voxel_a"], sc["voxel_phi"], sc["sv_ptr"], sc["sv_idx"])
+    b = T.sim_from_scene(bare, _tp())
+    b.set_springs_phasor(0, c, s_)
+    a.step(200)
+    b.step(200)
+    pa, va, _ = a.get_state(displacement=True)
+    pb, vb, _ = b.get_state(displacement=True)
+    assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+    # voxels changed while running: still equal to setting the phasors
+    va2 = (sc["voxel_a"] * 0.5).astype(np.float32)
+    a.set_voxel_actuation(va2, sc["voxel_phi"], sc["sv_ptr"], sc["sv_idx"])
+    b.set_springs_phasor(0, *_mean_phasor(va2, sc["voxel_phi"], sc["sv_ptr"], sc["sv_idx"]))
+    a.step(100)
+    b.step(100)
+    pa, va, _ = a.get_state(displacement=True)
+    pb, vb, _ = b.get_state(displacement=True)
+    assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+    a.rollout_grad_voxel(20, 10)
+    # a direct change of a voxel-driven spring ends the map
+    a.set_springs_phasor(0, [0.0], [0.0])
+    with pytest.raises(T.TitanError) as ei:
+        a.rollout_grad_voxel(20, 10)
+    assert ei.value.code == T.ESTATE
+    a.close()
+    b.close()
 
 
 @pytest.mark.parametrize("K", [1, 7, 500])
