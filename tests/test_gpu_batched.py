@@ -9,7 +9,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1911_10274_amd import scenes
-from tests.parity import TOL, both_params, compare_series, gpu_series
+from tests.parity import assert_parity, both_params, compare_series, gpu_series
 
 pytestmark = pytest.mark.gpu
 
@@ -47,7 +47,7 @@ def test_batched_parity_10_steps():
     sysm = O.System(sc)
     err = compare_series(gpu, sysm.trajectory(op, 10), sysm.mass)
     print("batched robots", err)
-    assert max(err.values()) <= TOL
+    assert_parity(err)
 
 
 @pytest.mark.parametrize("steps", [1, 37, 2000])
@@ -120,7 +120,7 @@ def test_tiny_bodies_and_isolated_masses():
     sysm = O.System(sc)
     err = compare_series(gpu, sysm.trajectory(op, 10), sysm.mass)
     print("tiny bodies", err)
-    assert max(err.values()) <= TOL
+    assert_parity(err)
 
 
 def test_batched_ineligible_body_is_rejected():

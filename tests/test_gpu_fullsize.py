@@ -1,6 +1,7 @@
 """Parity at the benchmark's full size and in its launch configuration: the
 1,000,000-mass / 12,731,796-spring actuated lattice, every mass, steps 1..10,
-and a 64-robot sub-batch of the uneven voxel-robot workload."""
+and a 64-robot sub-batch of the uneven voxel-robot workload on the per-step
+(tiled) and the batched engine."""
 import math
 
 import numpy as np
@@ -8,7 +9,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1911_10274_amd import scenes
-from tests.parity import TOL, both_params, compare_series, gpu_series
+from tests.parity import assert_parity, both_params, compare_series, gpu_series
 
 pytestmark = pytest.mark.gpu
 
@@ -28,20 +29,24 @@ def test_large_lattice_full_size_10_steps():
     ref = sysm.trajectory(op, 10)
     err = compare_series(gpu, ref, sysm.mass)
     print("full size lattice", err)
-    assert max(err.values()) <= TOL
+    assert_parity(err)
 
 
-def test_voxel_robot_subbatch_10_steps():
+@pytest.mark.parametrize("engine", ["tiled", "batched"])
+def test_voxel_robot_subbatch_10_steps(engine):
     from paper_1911_10274_amd import titan as T
 
     robots = scenes.robot_batch(64, seed=3, side_lo=3, side_hi=12)
     sc = scenes.concat(robots)
-    tp, op = both_params(dt=1e-4, omega=2 * math.pi * 2)
+    eng = {"tiled": T.ENGINE_TILED, "batched": T.ENGINE_BATCHED}[engine]
+    tp, op = both_params(dt=1e-4, omega=2 * math.pi * 2, engine=eng)
     sim = T.sim_from_scene(sc, tp)
+    sim.finalize()
+    assert sim.info()["engine"] == eng
     gpu = gpu_series(sim, 10)
     sim.close()
     sysm = O.System(sc)
     ref = sysm.trajectory(op, 10)
     err = compare_series(gpu, ref, sysm.mass)
-    print("voxel sub-batch", err)
-    assert max(err.values()) <= TOL
+    print("voxel sub-batch", engine, err)
+    assert_parity(err)

@@ -12,7 +12,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1911_10274_amd import scenes
-from tests.parity import TOL, compare_series, gpu_series, rel
+from tests.parity import TOL, assert_parity, compare_series, gpu_series, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -51,7 +51,7 @@ def test_first_10_steps_match_the_oracle(integ, engine):
     sysm = O.System(sc)
     err = compare_series(gpu, sysm.trajectory(_oparams(integ), 10), sysm.mass)
     print(integ, engine, err)
-    assert max(err.values()) <= TOL
+    assert_parity(err)
 
 
 @pytest.mark.parametrize("integ", ["verlet", "rk4"])
@@ -101,7 +101,7 @@ def test_worm_wave_law(integ):
     op = _oparams(integ, dt=1e-4, omega=20.0, wave=True, period=1.0)
     err = compare_series(gpu, sysm.trajectory(op, 10), sysm.mass)
     print(integ, "worm", err)
-    assert max(err.values()) <= TOL
+    assert_parity(err)
 
 
 @pytest.mark.parametrize("integ", ["verlet", "rk4"])

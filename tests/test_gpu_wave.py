@@ -9,7 +9,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1911_10274_amd import scenes
-from tests.parity import TOL, compare_series, gpu_series, rel
+from tests.parity import TOL, assert_parity, compare_series, gpu_series, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +46,7 @@ def test_worm_first_10_steps(engine):
     sim.close()
     err = compare_series(gpu, sysm.trajectory(op, 10), sysm.mass)
     print("worm", engine, err)
-    assert max(err.values()) <= TOL
+    assert_parity(err)
 
 
 def test_worm_window_across_a_period_boundary():
@@ -125,7 +125,7 @@ def test_hundred_worms_full_size_10_steps():
     sim.close()
     err = compare_series(gpu, sysm.trajectory(op, 10), sysm.mass)
     print("100 worms", err)
-    assert max(err.values()) <= TOL
+    assert_parity(err)
 
 
 def test_wave_law_refusals():
