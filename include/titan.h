@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TITAN_ABI_VERSION 6
+#define TITAN_ABI_VERSION 7
 
 /* Status codes. */
 #define TITAN_OK 0
@@ -335,6 +335,19 @@ int titan_set_step(titan_sim *sim, int64_t step);
  * disp_nb3[b] = sum_i m_i (x_i - x0_i) / M_b over the masses of
  * body b (n_bodies x 3 floats). */
 int titan_get_body_displacement(titan_sim *sim, float *disp_nb3);
+
+/* titan_get_body_displacement for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight control loops, harnesses that forbid
+ * hipMalloc): same result, bit for bit, with no hipMalloc, hipFree or
+ * allocator call.  Its device work uses a fixed array inside the library
+ * (about 17 MiB per device, held until the process ends) instead of per-call
+ * buffers, so the system is limited to 4,194,304 masses and 65,536 bodies
+ * (TITAN_EINVAL beyond).  The sim must already have its device state
+ * (TITAN_ESTATE before titan_finalize or the first titan_step).  Calls are
+ * serialised within the process (the array is shared by every sim on a
+ * device); another process has its own array.  Blocks until the result is
+ * on the host. */
+int titan_get_body_displacement_noalloc(titan_sim *sim, float *disp_nb3);
 
 /* Change the constants of springs [first, first+count): k, damping and
  * actuation (amp with phase), each array NULL to keep that part (the paper's

@@ -1225,6 +1225,69 @@ extern "C" int titan_set_voxel_actuation(titan_sim *s, int64_t n_voxels, const f
     return update_spring_list(s, changed, false, false, true, false);
 }
 
+// Centre-of-mass displacement, the host part shared by both entry points:
+// the body runs of the internal order (bodies are contiguous, largest first)
+// and each mass's weight m_i / M_b in internal order.
+struct BodyRuns {
+    int32_t nb = 0;                  // body ids 0 .. nb - 1
+    std::vector<int64_t> off{0};     // run r = internal masses [off[r], off[r+1])
+    std::vector<int32_t> rank_body;  // body id of run r
+    std::vector<float> w;            // per internal mass
+};
+
+static void body_runs(const titan_sim *s, BodyRuns &r)
+{
+    const int64_t n = s->n;
+    for (int32_t b : s->h_body)
+        r.nb = std::max(r.nb, b + 1);
+    for (int64_t a = 0; a < n;) {
+        const int32_t bd = s->h_body[s->perm[a]];
+        int64_t b = a + 1;
+        while (b < n && s->h_body[s->perm[b]] == bd)
+            ++b;
+        r.rank_body.push_back(bd);
+        r.off.push_back(b);
+        a = b;
+    }
+    std::vector<double> mt(r.nb, 0.0);
+    for (int64_t u = 0; u < n; ++u)
+        mt[s->h_body[u]] += (double)s->h_mass[u];
+    r.w.resize(n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t u = s->perm[i];
+        const double m = mt[s->h_body[u]];
+        r.w[i] = m > 0.0 ? (float)((double)s->h_mass[u] / m) : 0.f;
+    }
+}
+
+// Device part: weights and run offsets copied into dw / doff, the per-run
+// sums into dd (3 floats per run), read back and scattered to disp by body id.
+static hipError_t body_disp_device(titan_sim *s, const BodyRuns &r, float *dw, int64_t *doff, float *dd,
+                                   float *disp)
+{
+    const int64_t n = s->n, nr = (int64_t)r.rank_body.size();
+    std::vector<float> h(3 * nr);
+    hipError_t e = hipSuccess;
+    if (n)
+        e = hipMemcpyAsync(dw, r.w.data(), sizeof(float) * n, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(doff, r.off.data(), sizeof(int64_t) * (nr + 1), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = launch_body_disp(s->U[s->cur], dw, doff, nr, dd, s->stream);
+    if (e == hipSuccess && nr)
+        e = hipMemcpyAsync(h.data(), dd, sizeof(float) * 3 * nr, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess)
+        return e;
+    for (int32_t b = 0; b < r.nb; ++b)
+        disp[3 * b] = disp[3 * b + 1] = disp[3 * b + 2] = 0.f;
+    for (int64_t q = 0; q < nr; ++q)
+        for (int c = 0; c < 3; ++c)
+            disp[3 * r.rank_body[q] + c] = h[3 * q + c];
+    return hipSuccess;
+}
+
 extern "C" int titan_get_body_displacement(titan_sim *s, float *disp)
 {
     if (!s || !disp)
@@ -1232,39 +1295,16 @@ extern "C" int titan_get_body_displacement(titan_sim *s, float *disp)
     std::lock_guard<std::mutex> lk(s->mu);
     if (int rc = ready(s))
         return rc;
-    const int64_t n = s->n;
-    int32_t nb = 0;
-    for (int32_t b : s->h_body)
-        nb = std::max(nb, b + 1);
-    if (nb == 0)
+    BodyRuns r;
+    body_runs(s, r);
+    if (r.nb == 0)
         return TITAN_OK;
-    // bodies are contiguous internal ranges (largest first)
-    std::vector<int64_t> off{0};
-    std::vector<int32_t> rank_body;
-    for (int64_t a = 0; a < n;) {
-        const int32_t bd = s->h_body[s->perm[a]];
-        int64_t b = a + 1;
-        while (b < n && s->h_body[s->perm[b]] == bd)
-            ++b;
-        rank_body.push_back(bd);
-        off.push_back(b);
-        a = b;
-    }
-    std::vector<double> mt(nb, 0.0);
-    for (int64_t u = 0; u < n; ++u)
-        mt[s->h_body[u]] += (double)s->h_mass[u];
-    std::vector<float> w(n);
-    for (int64_t i = 0; i < n; ++i) {
-        const int64_t u = s->perm[i];
-        const double m = mt[s->h_body[u]];
-        w[i] = m > 0.0 ? (float)((double)s->h_mass[u] / m) : 0.f;
-    }
-    const int64_t nr = (int64_t)rank_body.size();
+    const int64_t n = s->n, nr = (int64_t)r.rank_body.size();
     float *dw = nullptr, *dd = nullptr;
     int64_t *doff = nullptr;
     if (int rc = dev_alloc(s, sizeof(float) * std::max<int64_t>(n, 1), (void **)&dw))
         return rc;
-    if (int rc = dev_alloc(s, sizeof(float) * 3 * nr, (void **)&dd)) {
+    if (int rc = dev_alloc(s, sizeof(float) * 3 * std::max<int64_t>(nr, 1), (void **)&dd)) {
         dev_free(s, dw);
         return rc;
     }
@@ -1273,26 +1313,83 @@ extern "C" int titan_get_body_displacement(titan_sim *s, float *disp)
         dev_free(s, dd);
         return rc;
     }
-    std::vector<float> h(3 * nr);
-    hipError_t e = hipMemcpyAsync(dw, w.data(), sizeof(float) * n, hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(doff, off.data(), sizeof(int64_t) * (nr + 1), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess)
-        e = launch_body_disp(s->U[s->cur], dw, doff, nr, dd, s->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(h.data(), dd, sizeof(float) * 3 * nr, hipMemcpyDeviceToHost, s->stream);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(s->stream);
+    const hipError_t e = body_disp_device(s, r, dw, doff, dd, disp);
     dev_free(s, dw);
     dev_free(s, dd);
     dev_free(s, doff);
     if (e != hipSuccess)
         return hip_fail(s, e, "body displacement");
-    for (int32_t b = 0; b < nb; ++b)
-        disp[3 * b] = disp[3 * b + 1] = disp[3 * b + 2] = 0.f;
-    for (int64_t r = 0; r < nr; ++r)
-        for (int c = 0; c < 3; ++c)
-            disp[3 * rank_body[r] + c] = h[3 * r + c];
+    return check_bad(s);
+}
+
+// ---- the same without allocating ---------------------------------------------
+// A file-scope device array holds what titan_get_body_displacement allocates
+// per call (run offsets, per-run sums, per-mass weights), sized for at most
+// kScratchMaxMasses masses in kScratchMaxBodies body runs.  Each device the
+// library runs on holds its own copy until the process ends; its address on
+// a device comes from hipGetSymbolAddress, taken once per device with that
+// device current (the array's name in host code is not a device address).
+constexpr int64_t kScratchMaxMasses = (int64_t)1 << 22;  // 4,194,304
+constexpr int64_t kScratchMaxBodies = (int64_t)1 << 16;  // 65,536
+constexpr size_t kAlign = 256;
+constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+constexpr size_t kScratchOffBytes = align_up(sizeof(int64_t) * (kScratchMaxBodies + 1));
+constexpr size_t kScratchSumBytes = align_up(sizeof(float) * 3 * kScratchMaxBodies);
+constexpr size_t kScratchBytes = kScratchOffBytes + kScratchSumBytes + sizeof(float) * kScratchMaxMasses;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;  // guards g_scratch and serialises the calls that use the array
+static void *g_scratch[kMaxDevices] = {};
+
+// The array's address on the current device (looked up once per device).
+static int scratch_on(int device, unsigned char **out)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return fail(TITAN_EDEVICE, "device %d beyond the %d devices the scratch table covers", device, kMaxDevices);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(TITAN_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                        hipGetErrorString(e));
+        }
+        g_scratch[device] = p;
+    }
+    *out = (unsigned char *)g_scratch[device];
+    return TITAN_OK;
+}
+
+extern "C" int titan_get_body_displacement_noalloc(titan_sim *s, float *disp)
+{
+    if (!s || !disp)
+        return fail(TITAN_EINVAL, "sim or disp is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->dev_error)
+        return fail(TITAN_EDEVICE, "sim is in a failed device state");
+    if (!s->finalized)
+        return fail(TITAN_ESTATE, "the sim has no device state yet (titan_finalize or titan_step first)");
+    HIP_TRY(s, hipSetDevice(s->device));
+    BodyRuns r;
+    body_runs(s, r);
+    if (r.nb == 0)
+        return TITAN_OK;
+    const int64_t nr = (int64_t)r.rank_body.size();
+    if (s->n > kScratchMaxMasses || nr > kScratchMaxBodies)
+        return fail(TITAN_EINVAL, "%lld masses in %lld bodies exceed this call's limit of %lld masses and %lld bodies",
+                    (long long)s->n, (long long)nr, (long long)kScratchMaxMasses, (long long)kScratchMaxBodies);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    unsigned char *base = nullptr;
+    if (int rc = scratch_on(s->device, &base))
+        return rc;
+    int64_t *doff = (int64_t *)base;
+    float *dd = (float *)(base + kScratchOffBytes);
+    float *dw = (float *)(base + kScratchOffBytes + kScratchSumBytes);
+    const hipError_t e = body_disp_device(s, r, dw, doff, dd, disp);
+    if (e != hipSuccess)
+        return hip_fail(s, e, "body displacement");
     return check_bad(s);
 }
 

@@ -128,6 +128,7 @@ def _load():
         "titan_get_forces": ([_vp, ctypes.c_int64, ctypes.c_int64, _fp], ctypes.c_int),
         "titan_set_step": ([_vp, ctypes.c_int64], ctypes.c_int),
         "titan_get_body_displacement": ([_vp, _fp], ctypes.c_int),
+        "titan_get_body_displacement_noalloc": ([_vp, _fp], ctypes.c_int),
         "titan_set_springs": ([_vp, ctypes.c_int64, ctypes.c_int64, _fp, _fp, _fp, _fp], ctypes.c_int),
         "titan_remove_springs": ([_vp, ctypes.c_int64, _i64p], ctypes.c_int),
         "titan_remove_masses": ([_vp, ctypes.c_int64, _i64p], ctypes.c_int),
@@ -393,6 +394,14 @@ class Sim:
         nb = self.info()["n_bodies"]
         out = np.empty((nb, 3), np.float32)
         _check(lib.titan_get_body_displacement(self._h, out.ctypes.data_as(_fp)))
+        return out
+
+    def body_displacement_noalloc(self):
+        """``body_displacement`` through titan_get_body_displacement_noalloc
+        (no device allocation; the sim must have stepped or been finalized)."""
+        nb = self.info()["n_bodies"]
+        out = np.empty((nb, 3), np.float32)
+        _check(lib.titan_get_body_displacement_noalloc(self._h, out.ctypes.data_as(_fp)))
         return out
 
     def set_springs(self, first: int = 0, k=None, damping=None, amp=None, phase=None):
