@@ -75,25 +75,65 @@ def build_workload(n: int, seed: int):
 PARAMS = dict(dt=5e-5, gravity=(0.0, 0.0, -9.81), ground=True, ground_k=1e5, mu=0.5, omega=2 * math.pi * 2)
 
 
-def cpu_baseline(scene, steps: int):
+def _host_cores() -> int:
+    """Cores this process may use: the affinity mask, capped by the thread
+    budget the environment sets (OMP_NUM_THREADS), if any."""
+    n = len(os.sched_getaffinity(0))
+    cap = os.environ.get("OMP_NUM_THREADS")
+    return max(1, min(n, int(cap))) if cap and cap.isdigit() else n
+
+
+def cpu_baseline(scene, steps: int, repeats: int = 3):
     """The FP64 oracle, as it stands, on the first ``steps`` steps of the same
-    workload (single thread)."""
+    workload, built for this host (gcc -O3 -march=native, no FMA
+    contraction): the median of ``repeats`` single-thread runs, and the
+    aggregate rate of one copy of the same window per host core, run
+    concurrently (independent processes; the oracle is a serial loop).  Each
+    measurement times the step loop alone, in its own process."""
+    import statistics
+    import subprocess
+    import tempfile
+
+    import numpy as np
+
     from oracle import oracle as O
 
-    op = O.Params(dt=PARAMS["dt"], gravity=PARAMS["gravity"], ground=PARAMS["ground"],
-                  ground_k=PARAMS["ground_k"], mu=PARAMS["mu"], omega=PARAMS["omega"])
-    sysm = O.System(scene)
-    t0 = time.perf_counter()
-    sysm.run(op, sysm.x0, sysm.v0, 0, steps)
-    sec = time.perf_counter() - t0
     ns = scene["ends"].shape[0]
+    with tempfile.TemporaryDirectory(prefix="titan_cpu_") as tmp:
+        lib = O.build_native(tmp)
+        path = os.path.join(tmp, "scene.npz")
+        np.savez(path, pos=scene["pos"], vel=scene["vel"], mass=scene["mass"], ends=scene["ends"], k=scene["k"],
+                 damping=scene["damping"], amp=scene["amp"], phase=scene["phase"], dt=PARAMS["dt"],
+                 g=np.asarray(PARAMS["gravity"]), ground=PARAMS["ground"], ground_k=PARAMS["ground_k"],
+                 mu=PARAMS["mu"], omega=PARAMS["omega"])
+        cmd = [sys.executable, "-m", "oracle.baseline", path, str(steps), lib]
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+
+        def run(count):
+            procs = [subprocess.Popen(cmd, cwd=ROOT, env=env, stdout=subprocess.PIPE, text=True) for _ in range(count)]
+            outs = [p.communicate()[0] for p in procs]
+            if any(p.returncode for p in procs):
+                raise RuntimeError("CPU baseline worker failed")
+            return [json.loads(o.strip().splitlines()[-1])["seconds"] for o in outs]
+
+        single = [run(1)[0] for _ in range(repeats)]
+        cores = _host_cores()
+        many = run(cores)
+    sec = statistics.median(single)
     return {
         "value": ns * steps / sec,
         "unit": "spring updates/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"first {steps} steps of the same {scene['pos'].shape[0]}-mass / {ns}-spring lattice, "
-                  f"serial FP64 C oracle, {sec:.2f} s",
+        "sample": f"first {steps} steps of the same {scene['pos'].shape[0]}-mass / {ns}-spring lattice, serial FP64 "
+                  f"C oracle (gcc -O3 -march=native), median of {repeats} runs: "
+                  + ", ".join(f"{x:.2f}" for x in single) + " s",
+        "all_cores": {
+            "value": cores * ns * steps / max(many),
+            "cores": cores,
+            "sample": f"{cores} concurrent single-thread oracle processes, each the same {steps}-step window "
+                      f"(slowest {max(many):.2f} s): aggregate host throughput",
+        },
     }
 
 
@@ -414,7 +454,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--n", type=int, default=100, help="lattice side (masses per edge)")
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate training / GEMM figures")

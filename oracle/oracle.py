@@ -51,13 +51,31 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+def build_native(out_dir: str) -> str:
+    """The same source compiled for the host it runs on (-O3 -march=native,
+    still no FMA contraction and no fast-math), into ``out_dir``: the build
+    the CPU baseline times.  The tests use ``build()``'s portable library."""
+    out = os.path.join(out_dir, "liboracle_native.so")
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", _SRC,
+                           "-o", out, "-lm"])
+    return out
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from ``path`` (a build of the same source) instead of
+    the default library; call before any other use."""
+    global _lib
+    _lib = None
+    _load(path)
+
+
 _lib = None
 
 
-def _load():
+def _load(path: str | None = None):
     global _lib
     if _lib is None:
-        lib = ctypes.CDLL(build())
+        lib = ctypes.CDLL(path or build())
         lib.orc_rest_lengths.argtypes = [ctypes.c_int64, _lp, _dp, _dp]
         _u8p = ctypes.POINTER(ctypes.c_uint8)
         lib.orc_spring_forces.argtypes = [ctypes.c_int64, ctypes.c_int64, _lp, _dp, _dp, _dp, _dp, _dp,
