@@ -109,23 +109,36 @@ class Surrogate:
         self.mu = np.zeros(dims[-1])
         self.sd = np.ones(dims[-1])
 
-    def fit(self, X, Y, epochs: int = 30, batch: int = 1024, lr: float = 1e-3, seed: int = 1, log=None):
+    def fit(self, X, Y, epochs: int = 30, batch: int = 1024, lr: float = 1e-3, seed: int = 1, log=None,
+            X_val=None, Y_val=None):
         """Adam on standardised targets, cosine-decayed learning rate.
-        Returns the mean training loss of every epoch."""
+        Returns a dict: the mean training loss of every epoch, the held-out
+        loss (standardised MSE) after every epoch when a validation set is
+        given, the seconds spent in the training calls alone (the upload of
+        the data set and the validation passes excluded) and the steps run."""
+        import torch
+
         rng = np.random.Generator(np.random.PCG64(seed))
         self.mu = Y.mean(axis=0)
         self.sd = Y.std(axis=0) + 1e-12
         self.net.set_data(X, ((Y - self.mu) / self.sd).astype(np.float32))
         n = X.shape[0]
         steps = n // batch
-        hist = []
+        hist, val, train_s = [], [], 0.0
         for ep in range(epochs):
             e_lr = lr * 0.5 * (1 + math.cos(math.pi * ep / epochs))
             idx = rng.permutation(n)[: steps * batch].reshape(steps, batch)
-            hist.append(float(np.mean(self.net.train(idx, lr=e_lr))))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            losses = self.net.train(idx, lr=e_lr)  # returns after the last step
+            train_s += time.perf_counter() - t0
+            hist.append(float(np.mean(losses)))
+            if X_val is not None:
+                pz = (self.predict(X_val) - self.mu) / self.sd
+                val.append(float(np.mean((pz - (Y_val - self.mu) / self.sd) ** 2)))
             if log:
-                log(f"epoch {ep}: loss {hist[-1]:.4f}")
-        return hist
+                log(f"epoch {ep}: loss {hist[-1]:.4f}" + (f", held out {val[-1]:.4f}" if val else ""))
+        return {"train_loss": hist, "val_loss": val, "train_s": train_s, "steps": steps * epochs}
 
     def predict(self, X):
         return self.net.predict(X).astype(np.float64) * self.sd + self.mu
@@ -222,16 +235,19 @@ def main(argv=None):
     model = Surrogate(seed=3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    hist = model.fit(Xt, Yt, args.epochs, args.batch, args.lr, log=log)
+    fit = model.fit(Xt, Yt, args.epochs, args.batch, args.lr, log=log, X_val=Xe, Y_val=Ye)
     torch.cuda.synchronize()
-    t_train = time.perf_counter() - t1
-    steps = (args.train // args.batch) * args.epochs
-    flops = 3 * 2 * sum(DIMS[l] * DIMS[l + 1] for l in range(len(DIMS) - 1)) * args.batch * steps
+    t_fit = time.perf_counter() - t1
+    hist = fit["train_loss"]
+    t_train = fit["train_s"]
+    flops = 3 * 2 * sum(DIMS[l] * DIMS[l + 1] for l in range(len(DIMS) - 1)) * args.batch * fit["steps"]
     res = screen(model, Xe, Ye, eval_batch)
     out = {
         "metric": "surrogate screening", "train_robots": args.train, "eval_robots": args.eval,
         "epochs": args.epochs, "batch": args.batch, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
-        "train_s": t_train, "train_tflops": flops / t_train / 1e12,
+        "train_loss_per_epoch": hist, "held_out_loss_per_epoch": fit["val_loss"],
+        "train_steps": fit["steps"], "train_s": t_train, "train_ms_per_step": t_train / fit["steps"] * 1e3,
+        "train_tflops": flops / t_train / 1e12, "fit_s_incl_data_upload_and_validation": t_fit,
         "dataset_s": t_data, "dataset_gpu_step_s": gpu_t, "eval_simulate_all_s": gpu_e,
         "screen_s": res["predict_s"] + res["resimulate_s"],
         "screen_speedup_vs_simulate_all": gpu_e / (res["predict_s"] + res["resimulate_s"]),
