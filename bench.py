@@ -240,7 +240,8 @@ def bench_batched(T, robots_n: int, steps: int, loop_sample: int):
     integ_batched = other_integrators(sim, T.ENGINE_BATCHED)
     sim.close()
     res.update(value=ns * steps / (ms / 1e3), ms_per_step=ms / steps, engine="batched",
-               workgroup_threads=info["batch_threads"])
+               workgroup_threads=info["batch_threads"], groups=info["batch_groups"],
+               largest_group_masses=info["batch_max_group"])
     sim = mk(T.ENGINE_TILED)
     sim.step(20)
     sim.sync()

@@ -67,9 +67,13 @@ extern "C" {
 /* Kernel selection (titan_params.engine). */
 #define TITAN_ENGINE_AUTO 0    /* library chooses (autotuned) */
 #define TITAN_ENGINE_GATHER 1  /* per-mass gather, one launch per step */
-#define TITAN_ENGINE_BATCHED 2 /* one workgroup per independent body with its
-                                  state resident in LDS, many steps per
-                                  launch; needs body ids (titan_add_masses) */
+#define TITAN_ENGINE_BATCHED 2 /* one workgroup per group of independent
+                                  bodies, their state resident in LDS, many
+                                  steps per launch; needs body ids
+                                  (titan_add_masses).  The tuner picks the
+                                  workgroup size and how many bodies a group
+                                  holds (up to 2048 masses when packing more
+                                  than the largest body) by timing them */
 #define TITAN_ENGINE_TILED 3   /* per-mass gather over LDS-staged tiles of
                                   spatially ordered masses, one launch per
                                   step (falls back to GATHER when a tile's
@@ -168,6 +172,9 @@ typedef struct titan_info {
                                 then each rebuild after a topology edit) */
     int64_t springs_in_place; /* springs added after the first step that went
                                  into spare slots without a rebuild */
+    int64_t batch_groups;     /* groups of the batched layout (0 if none) */
+    int32_t batch_max_group;  /* masses in its largest group: the packing the
+                                 tuner chose (bodies per group) */
 } titan_info;
 
 /* ABI version this library implements (TITAN_ABI_VERSION).  Library

@@ -34,6 +34,8 @@ constexpr int64_t kPackMin = 256;
 constexpr int64_t kMaxGroup = 160 * 1024 / (3 * 16);
 // Steps timed per candidate by the tuner.
 constexpr int kTuneSteps = 16;
+// Largest group the tuner may form by packing more bodies per group.
+constexpr int64_t kMaxPackTuned = 2048;
 
 static bool threads_fit(int threads, int64_t max_group) { return (max_group + threads - 1) / threads <= 8; }
 
@@ -83,24 +85,15 @@ static int time_gather(titan_sim *s, float4 *su, float4 *sv, float *ms)
     return TITAN_OK;
 }
 
-int build_batch_engine(titan_sim *s, bool may_step)
+// Groups of whole bodies for a packing size: consecutive body runs of the
+// internal order (largest first) are put in one group until the next would
+// take it past `pack` masses.  Returns the group offsets and the largest group.
+static void make_groups(const titan_sim *s, int64_t pack, std::vector<int64_t> &goff, int64_t &max_group)
 {
-    s->batch = nullptr;
-    s->batch_step = false;
     const int64_t n = s->n;
-    if (n == 0 || (s->h_slot_nbr.empty() && s->ns > 0))
-        return TITAN_OK;
-
-    // Body runs in internal order (largest body first), then groups.
-    std::vector<int64_t> goff{0};
-    int64_t gsize = 0, max_group = 0;
-    int64_t pack = kPackMin;
-    {
-        int64_t b = 1;
-        while (b < n && s->h_body[s->perm[b]] == s->h_body[s->perm[0]])
-            ++b;
-        pack = std::max<int64_t>(pack, b);  // the first body is a largest one
-    }
+    goff.assign(1, 0);
+    int64_t gsize = 0;
+    max_group = 0;
     for (int64_t a = 0; a < n;) {
         const int32_t body = s->h_body[s->perm[a]];
         int64_t b = a + 1;
@@ -117,15 +110,16 @@ int build_batch_engine(titan_sim *s, bool may_step)
     }
     goff.push_back(n);
     max_group = std::max(max_group, gsize);
-    if (max_group > kMaxGroup)
-        return TITAN_OK;  // a body too large for LDS: not eligible
-    const int64_t ng = (int64_t)goff.size() - 1;
+}
 
-    // Per-slot neighbour index relative to the group's first mass.
+// The batched layout of the groups `goff` on the device: group offsets and
+// each slot's neighbour relative to its group's first mass.
+static int upload_groups(titan_sim *s, const std::vector<int64_t> &goff, int64_t max_group,
+                         const std::vector<int64_t> &hoff, BatchEngine *be)
+{
+    const int64_t ng = (int64_t)goff.size() - 1;
     const int64_t slots = (int64_t)s->h_slot_nbr.size();
     std::vector<uint16_t> nbr_group(slots, 0);
-    std::vector<int64_t> hoff(s->gg.n_slices + 1);
-    HIP_TRY(s, hipMemcpy(hoff.data(), s->gg.slice_off, sizeof(int64_t) * hoff.size(), hipMemcpyDeviceToHost));
     for (int64_t q = 0; q < ng; ++q)
         for (int64_t i = goff[q]; i < goff[q + 1]; ++i) {
             const int64_t sl = i / kSlice, base = hoff[sl] + (i % kSlice);
@@ -137,31 +131,66 @@ int build_batch_engine(titan_sim *s, bool may_step)
                 nbr_group[base + w * kSlice] = (uint16_t)(j - goff[q]);
             }
         }
+    be->lay.n_groups = ng;
+    be->lay.max_group = (int32_t)max_group;
+    int64_t *d = nullptr;
+    if (int rc = dev_alloc(s, sizeof(int64_t) * goff.size(), (void **)&d))
+        return rc;
+    HIP_TRY(s, hipMemcpyAsync(d, goff.data(), sizeof(int64_t) * goff.size(), hipMemcpyHostToDevice, s->stream));
+    be->lay.mass_off = d;
+    uint16_t *e = nullptr;
+    if (int rc = dev_alloc(s, sizeof(uint16_t) * std::max<int64_t>(slots, 1), (void **)&e))
+        return rc;
+    if (slots)
+        HIP_TRY(s, hipMemcpyAsync(e, nbr_group.data(), sizeof(uint16_t) * slots, hipMemcpyHostToDevice, s->stream));
+    be->lay.nbr_group = e;
+    // the host table goes away with this call
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return TITAN_OK;
+}
 
+static void free_groups(titan_sim *s, BatchEngine *be)
+{
+    if (!be)
+        return;
+    dev_free(s, const_cast<int64_t *>(be->lay.mass_off));
+    dev_free(s, const_cast<uint16_t *>(be->lay.nbr_group));
+    delete be;
+}
+
+int build_batch_engine(titan_sim *s, bool may_step)
+{
+    s->batch = nullptr;
+    s->batch_step = false;
+    const int64_t n = s->n;
+    if (n == 0 || (s->h_slot_nbr.empty() && s->ns > 0))
+        return TITAN_OK;
+
+    // Packing: bodies go into groups of up to `pack` masses, at least the
+    // largest body (the first body run of the internal order is a largest
+    // one) and at least kPackMin.
+    int64_t pack = kPackMin;
+    {
+        int64_t b = 1;
+        while (b < n && s->h_body[s->perm[b]] == s->h_body[s->perm[0]])
+            ++b;
+        pack = std::max<int64_t>(pack, b);
+    }
+    std::vector<int64_t> goff;
+    int64_t max_group = 0;
+    make_groups(s, pack, goff, max_group);
+    if (max_group > kMaxGroup)
+        return TITAN_OK;  // a body too large for LDS: not eligible
+    std::vector<int64_t> hoff(s->gg.n_slices + 1);
+    HIP_TRY(s, hipMemcpy(hoff.data(), s->gg.slice_off, sizeof(int64_t) * hoff.size(), hipMemcpyDeviceToHost));
     BatchEngine *be = new (std::nothrow) BatchEngine();
     if (!be)
         return fail(TITAN_ENOMEM, "out of host memory");
-    be->lay.n_groups = ng;
-    s->h_group_off = goff;
-    be->lay.max_group = (int32_t)max_group;
-    {
-        int64_t *d = nullptr;
-        if (int rc = dev_alloc(s, sizeof(int64_t) * goff.size(), (void **)&d)) {
-            delete be;
-            return rc;
-        }
-        HIP_TRY(s, hipMemcpyAsync(d, goff.data(), sizeof(int64_t) * goff.size(), hipMemcpyHostToDevice, s->stream));
-        be->lay.mass_off = d;
-        uint16_t *e = nullptr;
-        if (int rc = dev_alloc(s, sizeof(uint16_t) * std::max<int64_t>(slots, 1), (void **)&e)) {
-            delete be;
-            return rc;
-        }
-        if (slots)
-            HIP_TRY(s, hipMemcpyAsync(e, nbr_group.data(), sizeof(uint16_t) * slots, hipMemcpyHostToDevice,
-                                      s->stream));
-        be->lay.nbr_group = e;
+    if (int rc = upload_groups(s, goff, max_group, hoff, be)) {
+        free_groups(s, be);
+        return rc;
     }
+    s->h_group_off = goff;
 
     if (!may_step) {
         s->batch = be;
@@ -186,7 +215,7 @@ int build_batch_engine(titan_sim *s, bool may_step)
     } ycopy{s};
     if (s->gg.yield && s->n_slots > 0) {
         if (int rc = dev_alloc(s, sizeof(float) * s->n_slots, (void **)&ycopy.tmp)) {
-            delete be;
+            free_groups(s, be);
             return rc;
         }
         ycopy.keep = s->gg.yield;
@@ -196,32 +225,88 @@ int build_batch_engine(titan_sim *s, bool may_step)
     }
     float4 *su = nullptr, *sv = nullptr;
     if (int rc = dev_alloc(s, sizeof(float4) * n, (void **)&su)) {
-        delete be;
+        free_groups(s, be);
         return rc;
     }
     if (int rc = dev_alloc(s, sizeof(float4) * n, (void **)&sv)) {
-        delete be;
+        free_groups(s, be);
         return rc;
     }
     HIP_TRY(s, launch_trig_table(s->trig, 0, kTuneSteps, s->params.omega, s->params.dt, s->stream));
+    // Candidates: the base packing, then groups of two and four times as many
+    // masses while the largest group stays within kMaxPackTuned masses (the
+    // adjoint and the batched RK4 take groups of up to 2048), each with every
+    // workgroup size that fits.
+    std::vector<int64_t> packs{pack};
+    for (int64_t f = 2; f <= 4; f *= 2)
+        if (pack * f <= kMaxPackTuned)
+            packs.push_back(pack * f);
     float best = 1e30f;
     int best_t = 0;
-    for (int t : kBatchThreadChoices) {
-        if (!threads_fit(t, max_group))
-            continue;
-        float ms = 0.f;
-        if (int rc = time_batch(s, *be, t, su, sv, &ms)) {
-            delete be;
-            return rc;
+    BatchEngine *best_be = nullptr;
+    std::vector<int64_t> best_goff;
+    int64_t prev_groups = -1;
+    for (int64_t p : packs) {
+        BatchEngine *cand = nullptr;
+        std::vector<int64_t> cg;
+        int64_t cmax = 0;
+        if (p == pack) {
+            cand = be;
+            cg = goff;
+            cmax = max_group;
+        } else {
+            make_groups(s, p, cg, cmax);
+            if (cmax > kMaxPackTuned || (int64_t)cg.size() - 1 == prev_groups)
+                continue;  // too large, or the same groups as the last candidate
+            cand = new (std::nothrow) BatchEngine();
+            if (!cand) {
+                free_groups(s, best_be != be ? best_be : nullptr);
+                free_groups(s, be);
+                return fail(TITAN_ENOMEM, "out of host memory");
+            }
+            if (int rc = upload_groups(s, cg, cmax, hoff, cand)) {
+                free_groups(s, cand);
+                free_groups(s, best_be != be ? best_be : nullptr);
+                free_groups(s, be);
+                return rc;
+            }
         }
-        if (ms < best) {
-            best = ms;
-            best_t = t;
+        prev_groups = (int64_t)cg.size() - 1;
+        bool won = false;
+        for (int t : kBatchThreadChoices) {
+            if (!threads_fit(t, cmax))
+                continue;
+            float ms = 0.f;
+            if (int rc = time_batch(s, *cand, t, su, sv, &ms)) {
+                if (cand != be)
+                    free_groups(s, cand);
+                free_groups(s, best_be != be ? best_be : nullptr);
+                free_groups(s, be);
+                return rc;
+            }
+            if (ms < best) {
+                best = ms;
+                best_t = t;
+                won = true;
+            }
+        }
+        if (won) {
+            if (best_be && best_be != be && best_be != cand)
+                free_groups(s, best_be);
+            best_be = cand;
+            best_goff = cg;
+        } else if (cand != be) {
+            free_groups(s, cand);
         }
     }
     if (best_t == 0) {
-        delete be;
+        free_groups(s, be);
         return TITAN_OK;
+    }
+    if (best_be != be) {
+        free_groups(s, be);
+        be = best_be;
+        s->h_group_off = best_goff;
     }
     be->threads = best_t;
     s->tune_batch_ms = best / kTuneSteps;
@@ -229,7 +314,7 @@ int build_batch_engine(titan_sim *s, bool may_step)
     if (s->params.engine == TITAN_ENGINE_AUTO) {
         float gms = 0.f;
         if (int rc = time_gather(s, su, sv, &gms)) {
-            delete be;
+            free_groups(s, be);
             return rc;
         }
         s->tune_gather_ms = gms / kTuneSteps;

@@ -1468,5 +1468,9 @@ extern "C" int titan_get_info(titan_sim *s, titan_info *info)
     info->slack = s->slack;
     info->layout_builds = s->layout_builds;
     info->springs_in_place = s->springs_in_place;
+    if (s->batch) {
+        info->batch_groups = batch_layout(s).n_groups;
+        info->batch_max_group = batch_layout(s).max_group;
+    }
     return TITAN_OK;
 }

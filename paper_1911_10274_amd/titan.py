@@ -88,6 +88,8 @@ class _Info(ctypes.Structure):
         ("slack", ctypes.c_int32),
         ("layout_builds", ctypes.c_int64),
         ("springs_in_place", ctypes.c_int64),
+        ("batch_groups", ctypes.c_int64),
+        ("batch_max_group", ctypes.c_int32),
     ]
 
 

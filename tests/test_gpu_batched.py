@@ -32,7 +32,36 @@ def test_batched_engine_is_selected_and_tuned():
     assert info["batch_threads"] in (256, 512, 1024)
     assert info["tune_batch_ms"] > 0
     assert info["n_bodies"] == 48
+    # the packing the tuner chose: at least the largest robot per group, more
+    # only up to 2048 masses
+    largest = max(np.bincount(sc["body"]))
+    assert largest <= info["batch_max_group"] <= max(largest, 2048)
+    assert 1 <= info["batch_groups"] <= 48
     sim.close()
+
+
+@pytest.mark.parametrize("lo,hi", [(3, 4), (4, 6)])
+def test_packing_choice_keeps_the_bits(lo, hi):
+    """Small robots leave the tuner several packings (bodies per group);
+    whichever it picks, the run equals the tiled engine's bit for bit."""
+    from paper_1911_10274_amd import titan as T
+
+    sc = _batch(count=300, seed=17, lo=lo, hi=hi)
+    outs = []
+    for eng in (BATCHED, TILED):
+        tp, _ = both_params(dt=1e-4, omega=2 * math.pi * 2, engine=eng)
+        sim = T.sim_from_scene(sc, tp)
+        sim.finalize()
+        info = sim.info()
+        assert info["engine"] == eng
+        if eng == BATCHED:
+            print("packing", lo, hi, "groups", info["batch_groups"], "largest group", info["batch_max_group"],
+                  "threads", info["batch_threads"])
+        sim.step(300)
+        outs.append(sim.get_state(displacement=True))
+        sim.close()
+    for a, b in zip(outs[0][:2], outs[1][:2]):
+        assert np.array_equal(a, b)
 
 
 def test_batched_parity_10_steps():
