@@ -28,6 +28,7 @@ namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f)
 {
@@ -98,31 +99,38 @@ struct GemmArgs {
 // 16-byte chunks of 8 K-values.  Otherwise element (r, k) at P[k * ld + r]:
 // each thread moves a block of 8 K-values x 2 rows, read as eight 4-byte
 // pieces along the rows (32 consecutive threads cover one 128-byte K row),
-// transposed in registers and stored as two 16-byte LDS writes.  Vector loads
-// when in range and aligned, element loads with zero fill otherwise.
+// transposed in registers and stored as two 16-byte LDS writes.
 template <bool KCONTIG>
 struct TileMove {
-    uint4 v[2];
+    u32x4 v[2];
 
-    __device__ __forceinline__ void load(const uint16_t *P, int ld, int r0, int R, int k0, int kend, bool vec,
-                                         int tid)
+    // FAST: the caller has checked that the whole tile is in range and the
+    // vector loads aligned.  Otherwise element loads at clamped positions
+    // (R >= 1 rows and K values up to kend >= 1 exist) with zero fill.
+    // Neither form branches per lane, so the compiler can count each load's
+    // completion exactly instead of waiting for all of them.
+    template <bool FAST>
+    __device__ __forceinline__ void load(const uint16_t *P, int ld, int r0, int R, int k0, int kend, int tid)
     {
         if (KCONTIG) {
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int c = tid + 256 * q;
                 const int row = r0 + (c >> 3), k = k0 + (c & 7) * 8;
-                if (vec && row < R && k + 8 <= kend) {
-                    v[q] = *(const uint4 *)(P + (int64_t)row * ld + k);
+                if (FAST) {
+                    v[q] = *(const u32x4 *)(P + (int64_t)row * ld + k);
                 } else {
+                    // element loads at clamped (always valid) positions, out
+                    // of range ones replaced by zero: no branch
+                    const int64_t rr = (int64_t)min(row, R - 1) * ld;
                     uint32_t w[4];
 #pragma unroll
                     for (int e = 0; e < 8; e += 2) {
-                        const uint32_t x0 = (row < R && k + e < kend) ? P[(int64_t)row * ld + k + e] : 0u;
-                        const uint32_t x1 = (row < R && k + e + 1 < kend) ? P[(int64_t)row * ld + k + e + 1] : 0u;
-                        w[e / 2] = x0 | x1 << 16;
+                        const uint32_t x0 = P[rr + min(k + e, kend - 1)];
+                        const uint32_t x1 = P[rr + min(k + e + 1, kend - 1)];
+                        w[e / 2] = (row < R && k + e < kend ? x0 : 0u) | (row < R && k + e + 1 < kend ? x1 : 0u) << 16;
                     }
-                    v[q] = make_uint4(w[0], w[1], w[2], w[3]);
+                    v[q] = u32x4{w[0], w[1], w[2], w[3]};
                 }
             }
         } else {
@@ -131,12 +139,13 @@ struct TileMove {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int k = kb + e;
-                if (vec && k < kend && rb + 2 <= R) {
+                if (FAST) {
                     in[e] = *(const uint32_t *)(P + (int64_t)k * ld + rb);
                 } else {
-                    const uint32_t x0 = (k < kend && rb < R) ? P[(int64_t)k * ld + rb] : 0u;
-                    const uint32_t x1 = (k < kend && rb + 1 < R) ? P[(int64_t)k * ld + rb + 1] : 0u;
-                    in[e] = x0 | x1 << 16;
+                    const int64_t kk = (int64_t)min(k, kend - 1) * ld;
+                    const uint32_t x0 = P[kk + min(rb, R - 1)];
+                    const uint32_t x1 = P[kk + min(rb + 1, R - 1)];
+                    in[e] = (k < kend && rb < R ? x0 : 0u) | (k < kend && rb + 1 < R ? x1 : 0u) << 16;
                 }
             }
             // v[n] = the 8 K-values of row rb + n
@@ -147,7 +156,7 @@ struct TileMove {
                 for (int j = 0; j < 4; ++j)
                     w[j] = n ? ((in[2 * j] >> 16) | (in[2 * j + 1] & 0xFFFF0000u))
                              : ((in[2 * j] & 0xFFFFu) | (in[2 * j + 1] << 16));
-                v[n] = make_uint4(w[0], w[1], w[2], w[3]);
+                v[n] = u32x4{w[0], w[1], w[2], w[3]};
             }
         }
     }
@@ -158,29 +167,68 @@ struct TileMove {
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int c = tid + 256 * q;
-                *(uint4 *)&S[(c >> 3) * LDK + (c & 7) * 8] = v[q];
+                *(u32x4 *)&S[(c >> 3) * LDK + (c & 7) * 8] = v[q];
             }
         } else {
             const int kb = 8 * (tid >> 5), rb = 2 * (tid & 31);
 #pragma unroll
             for (int n = 0; n < 2; ++n)
-                *(uint4 *)&S[(rb + n) * LDK + kb] = v[n];
+                *(u32x4 *)&S[(rb + n) * LDK + kb] = v[n];
         }
     }
 };
+
+// One chunk of NK K tiles of the 64 x 64 kernel, from c0: all NK tiles'
+// loads first, then per tile the LDS store (alternating buffers, by the
+// tile's index in the split), one barrier and four MFMAs per wave.  FA / FB:
+// operand A / B of the whole chunk is in range and aligned for vector loads
+// (uniform over the workgroup); the chunk's tiles past ke are skipped.
+template <bool TA, bool TB, int NK, bool FA, bool FB>
+__device__ __forceinline__ void gemm_chunk(const GemmArgs &g, int c0, int kb, int ke, int m0, int n0, int tid,
+                                           uint16_t (*sA)[BM * LDK], uint16_t (*sB)[BN * LDK], f32x16_t &acc)
+{
+    const int lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+    TileMove<!TA> ta[NK];
+    TileMove<TB> tb[NK];
+    // a stage past the range loads zeros (its K values are all >= ke)
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+        ta[s].template load<FA>(g.A, g.lda, m0, g.M, c0 + s * BK, ke, tid);
+        tb[s].template load<FB>(g.B, g.ldb, n0, g.N, c0 + s * BK, ke, tid);
+    }
+    const int t0 = (c0 - kb) / BK;  // K tiles of the split before this chunk
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+        if (c0 + s * BK < ke) {  // uniform over the workgroup
+            uint16_t *a = sA[(t0 + s) & 1], *b = sB[(t0 + s) & 1];
+            ta[s].store(a, tid);
+            tb[s].store(b, tid);
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 16) {
+                const bf16x8_t av = *(const bf16x8_t *)&a[(wm * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5)];
+                const bf16x8_t bv = *(const bf16x8_t *)&b[(wn * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5)];
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+            }
+        }
+    }
+}
 
 // C[M,N] = A[M,K] B[K,N] with A(m,k) = TA ? A[k*lda + m] : A[m*lda + k] and
 // B(k,n) = TB ? B[n*ldb + k] : B[k*ldb + n], all bf16; FP32 accumulate on
 // v_mfma_f32_32x32x16_bf16.  A 64x64 tile per workgroup, 32x32 per wave;
 // workgroup z takes K range [z*kslice, (z+1)*kslice).  Tiles are staged in
 // LDS with K contiguous per row (A) or column (B), so each lane's 8 K-values
-// of an MFMA operand are one 16-byte LDS read; the next K tile is loaded into
-// registers while the current one is multiplied.
-template <bool TA, bool TB, int EPI>
+// of an MFMA operand are one 16-byte LDS read.  The K range is taken in
+// chunks of NK tiles: the loads of a whole chunk are issued before its first
+// product (NK register stages, straight-line code, so each stage waits only
+// for its own loads), then each stage goes to one of two alternating LDS
+// buffers (one barrier per K tile) and into the MFMAs.
+template <bool TA, bool TB, int EPI, int NK>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, GemmEpi ep)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t sA[BM * LDK];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[BN * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * LDK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int wm = wave >> 1, wn = wave & 1;
@@ -188,19 +236,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, GemmEpi ep)
     // vector loads: 16 bytes along K, or 4 bytes along the rows
     const bool va = TA ? (g.lda % 2 == 0 && ((uintptr_t)g.A & 3) == 0) : (g.lda % 8 == 0 && ((uintptr_t)g.A & 15) == 0);
     const bool vb = TB ? (g.ldb % 8 == 0 && ((uintptr_t)g.B & 15) == 0) : (g.ldb % 2 == 0 && ((uintptr_t)g.B & 3) == 0);
-    TileMove<!TA> ta;
-    TileMove<TB> tb;
     f32x16_t acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (kb < ke) {
-        ta.load(g.A, g.lda, m0, g.M, kb, ke, va, tid);
-        tb.load(g.B, g.ldb, n0, g.N, kb, ke, vb, tid);
-    }
     // D layout of the 32x32 MFMA: lane l holds column l % 32 and, for
     // r = 0..15, row 8 (r / 4) + 4 (l / 32) + r % 4.
     const int j = n0 + wn * 32 + (lane & 31);
     auto row = [&](int r) { return m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); };
-    // the epilogue's own inputs are loaded before the K loop, so their
-    // latency hides behind it (one pass; a split leaves them to the reduction)
+    // the epilogue's own inputs are loaded first, so their latency hides
+    // behind the K loop (one pass; a split leaves them to the reduction)
     float pre[16];
     if (!g.part && (EPI == EPI_GELU_BWD || EPI == EPI_BIAS_GELU || EPI == EPI_BIAS)) {
         const float bj = (EPI != EPI_GELU_BWD && j < g.N) ? ep.bias[j] : 0.f;
@@ -209,22 +251,24 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, GemmEpi ep)
             pre[r] = EPI == EPI_GELU_BWD ? ((j < g.N && row(r) < g.M) ? ep.Zin[(int64_t)row(r) * ep.ldz + j] : 0.f)
                                          : bj;
     }
-    for (int k0 = kb; k0 < ke; k0 += BK) {
-        ta.store(sA, tid);
-        tb.store(sB, tid);
-        __syncthreads();
-        if (k0 + BK < ke) {
-            ta.load(g.A, g.lda, m0, g.M, k0 + BK, ke, va, tid);
-            tb.load(g.B, g.ldb, n0, g.N, k0 + BK, ke, vb, tid);
-        }
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 16) {
-            const bf16x8_t a = *(const bf16x8_t *)&sA[(wm * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5)];
-            const bf16x8_t b = *(const bf16x8_t *)&sB[(wn * 32 + (lane & 31)) * LDK + kk + 8 * (lane >> 5)];
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-        }
-        __syncthreads();
-    }
+    // Full chunks: an operand whose 64 rows are all in range (and whose
+    // vector loads are aligned) is loaded with vector loads, the other with
+    // clamped element loads; with both in range all NK tiles' loads are in
+    // flight at once, otherwise two tiles'.  The split's last partial chunk
+    // goes two K tiles at a time with element loads.
+    const bool fa = va && m0 + BM <= g.M, fb = vb && n0 + BN <= g.N;
+    int c0 = kb;
+    if (fa && fb)
+        for (; c0 + NK * BK <= ke; c0 += NK * BK)
+            gemm_chunk<TA, TB, NK, true, true>(g, c0, kb, ke, m0, n0, tid, sA, sB, acc);
+    else if (fa)
+        for (; c0 + 2 * BK <= ke; c0 += 2 * BK)
+            gemm_chunk<TA, TB, 2, true, false>(g, c0, kb, ke, m0, n0, tid, sA, sB, acc);
+    else if (fb)
+        for (; c0 + 2 * BK <= ke; c0 += 2 * BK)
+            gemm_chunk<TA, TB, 2, false, true>(g, c0, kb, ke, m0, n0, tid, sA, sB, acc);
+    for (; c0 < ke; c0 += 2 * BK)
+        gemm_chunk<TA, TB, 2, false, false>(g, c0, kb, ke, m0, n0, tid, sA, sB, acc);
 
     if (j >= g.N)
         return;
@@ -449,10 +493,16 @@ __global__ void gemm_reduce_kernel(int M, int N, int splits, const float *part, 
     epi_store<EPI>((int)(q / N), (int)(q % N), v, ep);
 }
 
+// Largest number of K tiles the 64 x 64 kernel loads at once (4 or 8).
+#ifndef TITAN_GEMM_MAXNK
+#define TITAN_GEMM_MAXNK 8
+#endif
+constexpr int kGemmMaxNk = TITAN_GEMM_MAXNK;
+
 // Workgroups a GEMM aims for before it splits K (a split costs a partial-sum
 // write and a reduce launch).
 #ifndef TITAN_GEMM_TARGET
-#define TITAN_GEMM_TARGET 256
+#define TITAN_GEMM_TARGET 128
 #endif
 constexpr int kGemmTarget = TITAN_GEMM_TARGET;
 
@@ -479,11 +529,21 @@ hipError_t gemm(int M, int N, int K, const uint16_t *A, int lda, const uint16_t 
         splits = std::max(1, std::min((kGemmTarget + tiles - 1) / tiles, kt / 2));  // at least the target
     while (splits > 1 && (int64_t)splits * M * N > part_cap)
         --splits;
-    const int kslice = ((kt + splits - 1) / splits) * BK;
+    // K tiles per split, rounded up to the chunk the kernel stages at once
+    const int per = (kt + splits - 1) / splits;
+    const int nk = per <= 1 ? 1 : per <= 2 ? 2 : per <= 4 || kGemmMaxNk == 4 ? 4 : 8;
+    const int kslice = (splits > 1 ? std::min(per, nk) : kt) * BK;
     splits = std::max(1, (K + kslice - 1) / kslice);
     GemmArgs g{M, N, K, A, lda, B, ldb, kslice, splits > 1 ? part : nullptr};
     const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)splits);
-    hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, g, ep);
+    if (nk == 1)
+        hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI, 1>), grid, dim3(256), 0, st, g, ep);
+    else if (nk == 2)
+        hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI, 2>), grid, dim3(256), 0, st, g, ep);
+    else if (nk == 4)
+        hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI, 4>), grid, dim3(256), 0, st, g, ep);
+    else
+        hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI, 8>), grid, dim3(256), 0, st, g, ep);
     if (splits > 1) {
         const int64_t n = (int64_t)M * N;
         hipLaunchKernelGGL(gemm_reduce_kernel<EPI>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, M, N, splits,
@@ -535,19 +595,100 @@ __global__ void gather_rows_kernel(const uint16_t *X, const float *Y, const int6
     }
 }
 
-// dz = bf16(2 (out - y) / (B O)); loss = mean (out - y)^2.  One workgroup, a
-// fixed summation order: deterministic.
-__global__ __launch_bounds__(256) void mse_kernel(const float *out, const float *y, int64_t n, uint16_t *dz,
-                                                  float *loss)
+// Output layers with at most kHeadMax outputs (the surrogate's three): the
+// last product, the loss and the first backward product in one launch, one
+// wave per batch row i (four rows per workgroup):
+//   z[i][o] = sum_k x[i][k] W[o][k] + b[o]            (FP32 out)
+//   e = z - y, dz[i][o] = bf16(2 e / (B O)), lrow[i] = sum_o e^2
+//   dzp[i][j] = bf16((sum_o dz[i][o] W[o][j]) gelu'(zp[i][j]))   (if zp)
+// The lane partial sums over k are combined by a butterfly of exchanges, so
+// every lane holds the same total and the order is fixed: deterministic.
+constexpr int kHeadMax = 4;
+
+template <int O>
+__global__ __launch_bounds__(256) void head_kernel(int B, int in, const uint16_t *x, int ldx, const uint16_t *W,
+                                                   const float *bias, const float *y, float *z, uint16_t *dz,
+                                                   float *lrow, const float *zp, uint16_t *dzp)
+{
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= B)
+        return;  // a whole wave; no barrier follows
+    const uint16_t *xr = x + (int64_t)i * ldx;
+    float acc[O];
+#pragma unroll
+    for (int o = 0; o < O; ++o)
+        acc[o] = 0.f;
+#pragma unroll 4
+    for (int k = lane; k < in; k += 64) {
+        const float xv = bf2f(xr[k]);
+#pragma unroll
+        for (int o = 0; o < O; ++o)
+            acc[o] = fmaf(xv, bf2f(W[(int64_t)o * in + k]), acc[o]);
+    }
+#pragma unroll
+    for (int o = 0; o < O; ++o)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            acc[o] += __shfl_xor(acc[o], off, 64);
+    const float scale = 2.f / (float)((int64_t)B * O);
+    float dzf[O], l = 0.f;
+#pragma unroll
+    for (int o = 0; o < O; ++o) {
+        const float zo = acc[o] + bias[o];
+        const float e = zo - y[(int64_t)i * O + o];
+        const uint16_t d = f2bf(e * scale);
+        dzf[o] = bf2f(d);
+        l = fmaf(e, e, l);
+        if (lane == o) {
+            z[(int64_t)i * O + o] = zo;
+            dz[(int64_t)i * O + o] = d;
+        }
+    }
+    if (lane == 0)
+        lrow[i] = l;
+    if (!zp)
+        return;
+    const float *zr = zp + (int64_t)i * in;
+    uint16_t *dr = dzp + (int64_t)i * in;
+#pragma unroll 4
+    for (int j = lane; j < in; j += 64) {
+        float g = dzf[0] * bf2f(W[j]);
+#pragma unroll
+        for (int o = 1; o < O; ++o)
+            g = fmaf(dzf[o], bf2f(W[(int64_t)o * in + j]), g);
+        dr[j] = f2bf(g * gelu_grad(zr[j]));
+    }
+}
+
+// The general output layer's loss terms: dz = bf16(2 (out - y) / (B O)) and
+// lrow[i] = sum_o (out - y)^2, one thread per row.
+__global__ void mse_rows_kernel(const float *out, const float *y, int B, int O, uint16_t *dz, float *lrow)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B)
+        return;
+    const float n = (float)((int64_t)B * O);
+    float l = 0.f;
+    for (int o = 0; o < O; ++o) {
+        const int64_t q = (int64_t)i * O + o;
+        const float d = out[q] - y[q];
+        l = fmaf(d, d, l);
+        dz[q] = f2bf(2.f * d / n);
+    }
+    lrow[i] = l;
+}
+
+// Loss of step s = sum_i lrow[s][i] / (B O), one workgroup per step, a fixed
+// summation order: deterministic.
+__global__ __launch_bounds__(256) void loss_rows_kernel(const float *lrow, int B, int O, float *loss)
 {
     __shared__ float red[256];
     const int t = threadIdx.x;
+    const float *r = lrow + (int64_t)blockIdx.x * B;
     float acc = 0.f;
-    for (int64_t q = t; q < n; q += 256) {
-        const float d = out[q] - y[q];
-        acc = fmaf(d, d, acc);
-        dz[q] = f2bf(2.f * d / (float)n);
-    }
+    for (int i = t; i < B; i += 256)
+        acc += r[i];
     red[t] = acc;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -556,7 +697,7 @@ __global__ __launch_bounds__(256) void mse_kernel(const float *out, const float 
         __syncthreads();
     }
     if (t == 0)
-        *loss = red[0] / (float)n;
+        loss[blockIdx.x] = red[0] / (float)((int64_t)B * O);
 }
 
 // Where the weight matrices sit in the flat parameters and in the bf16 copy
@@ -631,6 +772,7 @@ struct titan_mlp {
     uint16_t *dz[2] = {nullptr, nullptr};
     float *yb = nullptr;
     float *gpart = nullptr;  // split-K partial sums of the GEMMs
+    float *lrow = nullptr;   // the current batch's per-row squared errors (owned by the caller)
     int64_t gpart_cap = 0;   // floats in gpart
     int64_t *idx = nullptr;
     float *loss = nullptr;
@@ -730,11 +872,12 @@ static int refresh_bf16(titan_mlp *m)
     return TITAN_OK;
 }
 
-// Forward of a batch already in xs[0]; output in zs[L-1].
-static int forward(titan_mlp *m, int B)
+// Forward of a batch already in xs[0] through layers [0, upto); the output
+// of the whole network (upto = L) in zs[L-1].
+static int forward(titan_mlp *m, int B, int upto)
 {
     const int L = m->L();
-    for (int l = 0; l < L; ++l) {
+    for (int l = 0; l < upto; ++l) {
         const int in = m->dims[l], out = m->dims[l + 1];
         GemmEpi ep{};
         ep.bias = m->P + m->boff[l];
@@ -753,15 +896,39 @@ static int forward(titan_mlp *m, int B)
     return TITAN_OK;
 }
 
-// Loss and gradients of a batch in xs[0] / yb; loss value to *loss_dev.
-static int backward(titan_mlp *m, int B, float *loss_dev)
+template <int O>
+static void launch_head(titan_mlp *m, int B)
+{
+    const int L = m->L(), in = m->dims[L - 1];
+    hipLaunchKernelGGL(head_kernel<O>, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, m->stream, B, in, m->xs[L - 1],
+                       m->xld[L - 1], m->Wb + m->wboff[L - 1], m->P + m->boff[L - 1], m->yb, m->zs[L - 1],
+                       m->dz[0], m->lrow, L > 1 ? m->zs[L - 2] : nullptr, m->dz[1]);
+}
+
+// Loss terms and gradients of a batch in xs[0] / yb: each row's squared
+// error summed over the outputs to lrow[0..B).
+static int backward(titan_mlp *m, int B, float *lrow)
 {
     const int L = m->L();
-    if (int rc = forward(m, B))
-        return rc;
     const int O = m->dims[L];
-    hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(256), 0, m->stream, m->zs[L - 1], m->yb, (int64_t)B * O, m->dz[0],
-                       loss_dev);
+    const bool head = O <= kHeadMax;
+    m->lrow = lrow;
+    if (int rc = forward(m, B, head ? L - 1 : L))
+        return rc;
+    if (head) {
+        // the output layer's product, the loss and dz_{L-2} in one launch
+        if (O == 1)
+            launch_head<1>(m, B);
+        else if (O == 2)
+            launch_head<2>(m, B);
+        else if (O == 3)
+            launch_head<3>(m, B);
+        else
+            launch_head<4>(m, B);
+    } else {
+        hipLaunchKernelGGL(mse_rows_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, m->stream, m->zs[L - 1],
+                           m->yb, B, O, m->dz[0], lrow);
+    }
     MLP_TRY(hipGetLastError());
     int cur = 0;
     for (int l = L - 1; l >= 0; --l) {
@@ -774,7 +941,9 @@ static int backward(titan_mlp *m, int B, float *loss_dev)
         ew.db = m->G + m->boff[l];
         MLP_TRY((gemm<true, false, EPI_WGRAD>(out, in + 1, B, dz, out, m->xs[l], m->xld[l], ew, m->stream, m->gpart,
                                               m->gpart_cap)));
-        if (l > 0) {
+        if (l > 0 && head && l == L - 1) {
+            cur = 1 - cur;  // dz_{L-2} came with the loss
+        } else if (l > 0) {
             GemmEpi ed{};
             ed.Zin = m->zs[l - 1];
             ed.ldz = in;
@@ -964,10 +1133,14 @@ extern "C" int titan_mlp_train(titan_mlp *m, int64_t nsteps, int32_t batch, cons
     if (int rc = ensure_cap(m, batch))
         return rc;
     int64_t *didx = nullptr;
-    float *dloss = nullptr;
+    float *dloss = nullptr, *dlrow = nullptr;
     if (int rc = mlp_alloc(m, sizeof(int64_t) * (size_t)std::max<int64_t>(nsteps * batch, 1), (void **)&didx))
         return rc;
     if (int rc = mlp_alloc(m, sizeof(float) * (size_t)std::max<int64_t>(nsteps, 1), (void **)&dloss))
+        return rc;
+    // every step's per-row squared errors; the losses are summed after the
+    // last step (one launch for all steps)
+    if (int rc = mlp_alloc(m, sizeof(float) * (size_t)std::max<int64_t>(nsteps * batch, 1), (void **)&dlrow))
         return rc;
     if (nsteps)
         MLP_TRY(hipMemcpyAsync(didx, idx, sizeof(int64_t) * nsteps * batch, hipMemcpyHostToDevice, m->stream));
@@ -977,7 +1150,7 @@ extern "C" int titan_mlp_train(titan_mlp *m, int64_t nsteps, int32_t batch, cons
         hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, m->stream, m->X,
                            m->Y, didx + s * batch, batch, in, out, m->xs[0], m->xld[0], m->yb);
         MLP_TRY(hipGetLastError());
-        if (int rc = backward(m, batch, dloss + s))
+        if (int rc = backward(m, batch, dlrow + s * batch))
             return rc;
         m->adam_t += 1;
         const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)m->adam_t));
@@ -1000,11 +1173,15 @@ extern "C" int titan_mlp_train(titan_mlp *m, int64_t nsteps, int32_t batch, cons
             if (int rc = refresh_bf16(m))
                 return rc;
     }
-    if (loss_out && nsteps)
+    if (loss_out && nsteps) {
+        hipLaunchKernelGGL(loss_rows_kernel, dim3((unsigned)nsteps), dim3(256), 0, m->stream, dlrow, batch, out, dloss);
+        MLP_TRY(hipGetLastError());
         MLP_TRY(hipMemcpyAsync(loss_out, dloss, sizeof(float) * nsteps, hipMemcpyDeviceToHost, m->stream));
+    }
     MLP_TRY(hipStreamSynchronize(m->stream));
     mlp_free(m, didx);
     mlp_free(m, dloss);
+    mlp_free(m, dlrow);
     return TITAN_OK;
 }
 
@@ -1021,7 +1198,7 @@ extern "C" int titan_mlp_predict(titan_mlp *m, int64_t n, const float *X, float 
         const int c = (int)std::min<int64_t>(m->cap, n - a);
         if (int rc = upload_batch_f32(m, c, X + a * in, nullptr))
             return rc;
-        if (int rc = forward(m, c))
+        if (int rc = forward(m, c, m->L()))
             return rc;
         MLP_TRY(hipMemcpyAsync(out + a * O, m->zs[m->L() - 1], sizeof(float) * (size_t)c * O, hipMemcpyDeviceToHost,
                                m->stream));
@@ -1040,17 +1217,22 @@ extern "C" int titan_mlp_grad(titan_mlp *m, int32_t batch, const float *X, const
         return rc;
     if (int rc = upload_batch_f32(m, batch, X, Y))
         return rc;
-    float *dloss = nullptr;
+    float *dloss = nullptr, *dlrow = nullptr;
     if (int rc = mlp_alloc(m, sizeof(float), (void **)&dloss))
         return rc;
-    if (int rc = backward(m, batch, dloss))
+    if (int rc = mlp_alloc(m, sizeof(float) * (size_t)batch, (void **)&dlrow))
         return rc;
+    if (int rc = backward(m, batch, dlrow))
+        return rc;
+    hipLaunchKernelGGL(loss_rows_kernel, dim3(1), dim3(256), 0, m->stream, dlrow, batch, m->dims.back(), dloss);
+    MLP_TRY(hipGetLastError());
     if (loss)
         MLP_TRY(hipMemcpyAsync(loss, dloss, sizeof(float), hipMemcpyDeviceToHost, m->stream));
     if (grads)
         MLP_TRY(hipMemcpyAsync(grads, m->G, sizeof(float) * m->nparam, hipMemcpyDeviceToHost, m->stream));
     MLP_TRY(hipStreamSynchronize(m->stream));
     mlp_free(m, dloss);
+    mlp_free(m, dlrow);
     return TITAN_OK;
 }
 

@@ -132,10 +132,15 @@ def _net_case(dims, B, seed=5, data_seed=6):
     net.close()
 
 
-# B = 1024 and 1000: the training batch, where every weight-gradient product
-# (and its ones column, the bias gradient) runs split over K; 1000 is ragged
+# B = 1024 and 1000: the training batch, where the weight-gradient products
+# (and their ones column, the bias gradient) run split over K; 1000 is ragged.
+# Up to four outputs the output layer, the loss and the first input gradient
+# run as one fused kernel (one, three and four outputs; a single layer has no
+# input gradient); more outputs take the general products.
 @pytest.mark.parametrize("dims,B", [([40, 64, 64, 3], 33), ([1536, 512, 512, 512, 512, 3], 128),
-                                    ([1536, 512, 512, 512, 512, 3], 1024), ([1536, 512, 512, 512, 512, 3], 1000)])
+                                    ([1536, 512, 512, 512, 512, 3], 1024), ([1536, 512, 512, 512, 512, 3], 1000),
+                                    ([40, 64, 64, 1], 70), ([30, 72, 4], 65), ([24, 4], 50), ([40, 64, 64, 7], 33),
+                                    ([100, 9], 77)])
 def test_mlp_forward_and_gradients_match_oracle(dims, B):
     _net_case(dims, B)
 
