@@ -581,17 +581,27 @@ __global__ void activation_pad_kernel(uint16_t *x, int64_t rows, int n, int ld)
     }
 }
 
-__global__ void gather_rows_kernel(const uint16_t *X, const float *Y, const int64_t *idx, int B, int in, int out,
-                                   uint16_t *xb, int ldx, float *yb)
+// The batch's rows of the resident data set: inputs (bf16, rows of `in`
+// values) into the activation rows (stride ldx) and targets into yb.  Rows
+// over blockIdx.y; 16-byte copies when rows hold a multiple of 8 values.
+__global__ __launch_bounds__(256) void gather_rows_kernel(const uint16_t *X, const float *Y, const int64_t *idx, int B,
+                                                          int in, int out, uint16_t *xb, int ldx, float *yb)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nx = (int64_t)B * in;
-    if (q < nx) {
-        const int64_t b = q / in, c = q % in;
-        xb[b * ldx + c] = X[idx[b] * in + c];
-    } else if (q < nx + (int64_t)B * out) {
-        const int64_t r = q - nx, b = r / out, c = r % out;
-        yb[r] = Y[idx[b] * out + c];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
+    for (int b = blockIdx.y; b < B; b += gridDim.y) {
+        const int64_t r = idx[b];
+        const uint16_t *src = X + r * in;
+        uint16_t *dst = xb + (int64_t)b * ldx;
+        if (in % 8 == 0) {
+            for (int c = t; c < in / 8; c += nt)
+                *(u32x4 *)(dst + 8 * c) = *(const u32x4 *)(src + 8 * c);
+        } else {
+            for (int c = t; c < in; c += nt)
+                dst[c] = src[c];
+        }
+        if (blockIdx.x == 0)
+            for (int c = threadIdx.x; c < out; c += blockDim.x)
+                yb[(int64_t)b * out + c] = Y[r * out + c];
     }
 }
 
@@ -1146,9 +1156,10 @@ extern "C" int titan_mlp_train(titan_mlp *m, int64_t nsteps, int32_t batch, cons
         MLP_TRY(hipMemcpyAsync(didx, idx, sizeof(int64_t) * nsteps * batch, hipMemcpyHostToDevice, m->stream));
     const int in = m->dims[0], out = m->dims.back();
     for (int64_t s = 0; s < nsteps; ++s) {
-        const int64_t tot = (int64_t)batch * (in + out);
-        hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, m->stream, m->X,
-                           m->Y, didx + s * batch, batch, in, out, m->xs[0], m->xld[0], m->yb);
+        const int per_row = in % 8 == 0 ? in / 8 : in;
+        hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((per_row + 255) / 256), (unsigned)std::min(batch, 65535)),
+                           dim3(256), 0, m->stream, m->X, m->Y, didx + s * batch, batch, in, out, m->xs[0], m->xld[0],
+                           m->yb);
         MLP_TRY(hipGetLastError());
         if (int rc = backward(m, batch, dlrow + s * batch))
             return rc;
