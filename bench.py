@@ -396,7 +396,8 @@ def bench_surrogate(T, batch: int = 1024, steps: int = 60, gemm_n: int = 8192):
         gflops = 2.0 * gemm_n ** 3 / (gms * 1e-3)
         gemm[name] = {"ms": gms, "tflops": gflops / 1e12, "frac_of_bf16_peak": gflops / 2.5e15}
     return {"workload": f"surrogate MLP 1536-512x4-3 (1,576,451 parameters), batch {batch}, {steps} Adam steps",
-            "train_ms_per_step": sec * 1e3 / steps, "train_tflops": train_flops / sec / 1e12, "gemm": gemm}
+            "train_ms_per_step": sec * 1e3 / steps, "train_tflops": train_flops / sec / 1e12,
+            "train_frac_of_bf16_peak": train_flops / sec / 2.5e15, "gemm": gemm}
 
 
 def bench_integrators(T, scene, steps: int = 1000):
