@@ -1,7 +1,11 @@
 """Parity at the benchmark's full size and in its launch configuration: the
-1,000,000-mass / 12,731,796-spring actuated lattice, every mass, steps 1..10,
-and a 64-robot sub-batch of the uneven voxel-robot workload on the per-step
-(tiled) and the batched engine."""
+1,000,000-mass / 12,731,796-spring actuated lattice, every mass, steps 1..10;
+a 64-robot sub-batch of the uneven voxel-robot workload on the per-step
+(tiled) and the batched engine; the whole 4096-robot batch on the batched
+engine as tuned for the benchmark, and the 256-robot adjoint with
+checkpoints every 50 steps, each checked on sampled robots (the bodies do not
+interact, so a robot of the batch must follow the oracle run on that robot
+alone)."""
 import math
 
 import numpy as np
@@ -50,3 +54,68 @@ def test_voxel_robot_subbatch_10_steps(engine):
     err = compare_series(gpu, ref, sysm.mass)
     print("voxel sub-batch", engine, err)
     assert_parity(err)
+
+
+def _sample(robots, k, seed):
+    """The smallest and the largest robot (by springs) and k - 2 others."""
+    sizes = np.array([r["ends"].shape[0] for r in robots])
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pick = {int(np.argmin(sizes)), int(np.argmax(sizes))}
+    while len(pick) < k:
+        pick.add(int(rng.integers(len(robots))))
+    return sorted(pick)
+
+
+def test_full_robot_batch_sampled_robots_10_steps():
+    from paper_1911_10274_amd import titan as T
+
+    robots = scenes.robot_batch(4096, seed=3, side_lo=3, side_hi=12)
+    sc = scenes.concat(robots)
+    pick = _sample(robots, 6, seed=41)
+    tp, op = both_params(dt=1e-4, omega=2 * math.pi * 2, engine=T.ENGINE_BATCHED)
+    sim = T.sim_from_scene(sc, tp)
+    sim.finalize()
+    info = sim.info()
+    assert info["engine"] == T.ENGINE_BATCHED
+    print("4096 robots:", sc["pos"].shape[0], "masses", sc["ends"].shape[0], "springs; groups", info["batch_groups"],
+          "threads", info["batch_threads"], "sampled", pick, flush=True)
+    mp = sc["mass_ptr"]
+    series = {b: ([], [], []) for b in pick}
+    for _ in range(10):
+        f = sim.get_forces()
+        sim.step(1)
+        p, v, _ = sim.get_state(displacement=True)
+        for b in pick:
+            lo, hi = mp[b], mp[b + 1]
+            series[b][0].append(p[lo:hi].astype(np.float64))
+            series[b][1].append(v[lo:hi].astype(np.float64))
+            series[b][2].append(f[lo:hi].astype(np.float64))
+    sim.close()
+    for b in pick:
+        sysm = O.System(robots[b])
+        err = compare_series(tuple(np.array(x) for x in series[b]), sysm.trajectory(op, 10), sysm.mass)
+        print("robot", b, robots[b]["pos"].shape[0], "masses:", err)
+        assert_parity(err, label=f"robot {b}")
+
+
+def test_adjoint_full_batch_sampled_robots():
+    from paper_1911_10274_amd import titan as T
+
+    robots = scenes.robot_batch(256, seed=4, side_lo=4, side_hi=8)
+    sc = scenes.concat(robots)
+    pick = _sample(robots, 4, seed=42)
+    tp, op = both_params(dt=1e-4, omega=2 * math.pi * 2, engine=T.ENGINE_BATCHED)
+    sim = T.sim_from_scene(sc, tp)
+    loss, gk, gC, gS = sim.rollout_grad(500, 50)
+    assert sim.info()["engine"] == T.ENGINE_BATCHED
+    sim.close()
+    sp = sc["spring_ptr"]
+    for b in pick:
+        ref = O.System(robots[b]).rollout_grad(op, 500, body=np.zeros(robots[b]["pos"].shape[0], np.int32))
+        lo, hi = sp[b], sp[b + 1]
+        for name, g, r in (("k", gk, ref["gk"]), ("C", gC, ref["gC"]), ("S", gS, ref["gS"])):
+            g = np.asarray(g[lo:hi], np.float64)
+            e = np.linalg.norm(g - r) / np.linalg.norm(r)
+            c = float(g @ r / (np.linalg.norm(g) * np.linalg.norm(r)))
+            print("robot", b, robots[b]["pos"].shape[0], "masses,", name, "rel", e, "cos", c)
+            assert e <= 1e-3 and c >= 0.9999, (b, name, e, c)
