@@ -493,6 +493,62 @@ __global__ void gemm_reduce_kernel(int M, int N, int splits, const float *part, 
     epi_store<EPI>((int)(q / N), (int)(q % N), v, ep);
 }
 
+// Q (C x R, row stride ldq) = P^T for P (R x C, row stride ld), bf16, through
+// a 64 x 64 LDS tile (rows padded to 72 values, 16-byte aligned): 16-byte
+// loads along P's rows when in range and aligned, stored whole; then each
+// thread gathers 8 consecutive P rows of one column (a wave reads 64
+// neighbouring columns: no bank conflicts) and writes them as 16 bytes of a
+// Q row.  Used to give a large product both operands with K contiguous.
+__global__ __launch_bounds__(256) void transpose_bf16_kernel(const uint16_t *P, int R, int C, int ld, uint16_t *Q,
+                                                             int ldq)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t t[64][72];
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64, tid = threadIdx.x;
+    const bool vec = ld % 8 == 0 && ((uintptr_t)P & 15) == 0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int ch = tid + 256 * q, rr = ch >> 3, cc = (ch & 7) * 8;
+        const int r = r0 + rr, c = c0 + cc;
+        u32x4 v;
+        if (vec && r < R && c + 8 <= C) {
+            v = *(const u32x4 *)(P + (int64_t)r * ld + c);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t lo = (r < R && c + 2 * e < C) ? P[(int64_t)r * ld + c + 2 * e] : 0u;
+                const uint32_t hi = (r < R && c + 2 * e + 1 < C) ? P[(int64_t)r * ld + c + 2 * e + 1] : 0u;
+                v[e] = lo | hi << 16;
+            }
+        }
+        *(u32x4 *)&t[rr][cc] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int ch = tid + 256 * q, rr = (ch >> 6) * 8, cc = ch & 63;
+        const int c = c0 + cc, r = r0 + rr;
+        if (c >= C)
+            continue;
+        if (r + 8 <= R && ldq % 8 == 0 && ((uintptr_t)Q & 15) == 0) {
+            u32x4 v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                v[e] = (uint32_t)t[rr + 2 * e][cc] | (uint32_t)t[rr + 2 * e + 1][cc] << 16;
+            *(u32x4 *)(Q + (int64_t)c * ldq + r) = v;
+        } else {
+            for (int e = 0; e < 8 && r + e < R; ++e)
+                Q[(int64_t)c * ldq + r + e] = t[rr + e][cc];
+        }
+    }
+}
+
+static hipError_t transpose_bf16(const uint16_t *P, int R, int C, int ld, uint16_t *Q, int ldq, hipStream_t st)
+{
+    const dim3 grid((unsigned)((C + 63) / 64), (unsigned)((R + 63) / 64));
+    hipLaunchKernelGGL(transpose_bf16_kernel, grid, dim3(256), 0, st, P, R, C, ld, Q, ldq);
+    return hipGetLastError();
+}
+
 // Largest number of K tiles the 64 x 64 kernel loads at once (4 or 8).
 #ifndef TITAN_GEMM_MAXNK
 #define TITAN_GEMM_MAXNK 8
@@ -507,7 +563,10 @@ constexpr int kGemmMaxNk = TITAN_GEMM_MAXNK;
 constexpr int kGemmTarget = TITAN_GEMM_TARGET;
 
 // part (capacity part_cap floats) enables split-K when the output has too few
-// tiles; null: one pass.
+// tiles; null: one pass.  A large product uses the same buffer to copy an
+// operand whose K is strided into K-contiguous form first (the big-tile
+// kernel then loads both operands with 16-byte loads; the MFMAs see the same
+// values in the same order, so the result is the same bit for bit).
 template <bool TA, bool TB, int EPI>
 hipError_t gemm(int M, int N, int K, const uint16_t *A, int lda, const uint16_t *B, int ldb, const GemmEpi &ep,
                 hipStream_t st, float *part = nullptr, int64_t part_cap = 0)
@@ -517,6 +576,32 @@ hipError_t gemm(int M, int N, int K, const uint16_t *A, int lda, const uint16_t 
     // large outputs (at least 128 big tiles): one pass of the big-tile kernel
     const int big_tiles = ((N + GBN - 1) / GBN) * ((M + GBM - 1) / GBM);
     if (big_tiles >= 128) {
+        const int Kp = (K + 7) / 8 * 8;  // row stride of the copies: 16-byte rows
+        const int64_t need = (TA ? (int64_t)M * Kp : 0) + (TB ? 0 : (int64_t)N * Kp);  // bf16 values
+        if (need > 0 && K > 0 && part && 2 * need <= 4 * part_cap) {
+            uint16_t *w = (uint16_t *)part;
+            const uint16_t *a = A, *b = B;
+            int la = lda, lb = ldb;
+            if (TA) {  // A (K x M, stride lda) -> M x K, stride Kp
+                hipError_t e = transpose_bf16(A, K, M, lda, w, Kp, st);
+                if (e != hipSuccess)
+                    return e;
+                a = w;
+                la = Kp;
+                w += (int64_t)M * Kp;
+            }
+            if (!TB) {  // B (K x N, stride ldb) -> N x K, stride Kp
+                hipError_t e = transpose_bf16(B, K, N, ldb, w, Kp, st);
+                if (e != hipSuccess)
+                    return e;
+                b = w;
+                lb = Kp;
+            }
+            GemmArgs g{M, N, K, a, la, b, lb, std::max(K, 1), nullptr};
+            const dim3 grid((unsigned)((N + GBN - 1) / GBN), (unsigned)((M + GBM - 1) / GBM), 1);
+            hipLaunchKernelGGL((gemm_big_kernel<false, true, EPI>), grid, dim3(GT), 0, st, g, ep);
+            return hipGetLastError();
+        }
         GemmArgs g{M, N, K, A, lda, B, ldb, std::max(K, 1), nullptr};
         const dim3 grid((unsigned)((N + GBN - 1) / GBN), (unsigned)((M + GBM - 1) / GBM), 1);
         hipLaunchKernelGGL((gemm_big_kernel<TA, TB, EPI>), grid, dim3(GT), 0, st, g, ep);
@@ -1256,15 +1341,34 @@ extern "C" int titan_mlp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16
     ep.Z = C_dev;
     ep.ldz = N;
     hipStream_t st = (hipStream_t)stream;
+    // a large product with a K-strided operand copies it K-contiguous first,
+    // into stream-ordered memory released behind the product (without that
+    // memory it runs on the strided operand directly)
+    float *ws = nullptr;
+    int64_t ws_floats = 0;
+    const int Kp = (K + 7) / 8 * 8;
+    const int64_t big_tiles = (int64_t)((N + GBN - 1) / GBN) * ((M + GBM - 1) / GBM);
+    const int64_t need = (ta ? (int64_t)M * Kp : 0) + (tb ? 0 : (int64_t)N * Kp);
+    if (big_tiles >= 128 && need > 0) {
+        const size_t bytes = (size_t)(need + 1) / 2 * 4;
+        if (hipMallocAsync((void **)&ws, bytes, st) == hipSuccess)
+            ws_floats = (int64_t)(bytes / 4);
+        else {
+            (void)hipGetLastError();
+            ws = nullptr;
+        }
+    }
     hipError_t e;
     if (!ta && !tb)
-        e = gemm<false, false, EPI_F32>(M, N, K, A_dev, lda, B_dev, ldb, ep, st);
+        e = gemm<false, false, EPI_F32>(M, N, K, A_dev, lda, B_dev, ldb, ep, st, ws, ws_floats);
     else if (!ta && tb)
-        e = gemm<false, true, EPI_F32>(M, N, K, A_dev, lda, B_dev, ldb, ep, st);
+        e = gemm<false, true, EPI_F32>(M, N, K, A_dev, lda, B_dev, ldb, ep, st, ws, ws_floats);
     else if (ta && !tb)
-        e = gemm<true, false, EPI_F32>(M, N, K, A_dev, lda, B_dev, ldb, ep, st);
+        e = gemm<true, false, EPI_F32>(M, N, K, A_dev, lda, B_dev, ldb, ep, st, ws, ws_floats);
     else
-        e = gemm<true, true, EPI_F32>(M, N, K, A_dev, lda, B_dev, ldb, ep, st);
+        e = gemm<true, true, EPI_F32>(M, N, K, A_dev, lda, B_dev, ldb, ep, st, ws, ws_floats);
+    if (ws)
+        (void)hipFreeAsync(ws, st);
     if (e != hipSuccess)
         return fail(TITAN_EDEVICE, "gemm launch: %s", hipGetErrorString(e));
     return TITAN_OK;

@@ -81,6 +81,30 @@ def test_gemm_bf16_layouts_big_tiles(ta, tb, shape):
     _gemm_case(ta, tb, shape)
 
 
+@pytest.mark.parametrize("shape", [(2085, 4115, 200), (2048, 4096, 61)])
+def test_big_tile_layouts_agree_bit_for_bit(shape):
+    """A large product whose K is strided in an operand runs on a
+    K-contiguous copy of that operand (rows padded to 16 bytes: K = 61 leaves
+    three values of padding per row), so all four layouts of one product give
+    the same bits."""
+    import torch
+
+    from paper_1911_10274_amd import titan as T
+
+    M, N, K = shape
+    rng = np.random.Generator(np.random.PCG64(M + N + K))
+    a = _bf16_bits(rng.normal(0, 1, (M, K)))
+    b = _bf16_bits(rng.normal(0, 1, (K, N)))
+    outs = []
+    for ta in (0, 1):
+        for tb in (0, 1):
+            dA = torch.from_numpy((a.T if ta else a).copy().view(np.int16)).cuda()
+            dB = torch.from_numpy((b.T if tb else b).copy().view(np.int16)).cuda()
+            outs.append(T.gemm_bf16(dA, dB, ta=bool(ta), tb=bool(tb), M=M, N=N, K=K).cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
 def _init(dims, seed):
     rng = np.random.Generator(np.random.PCG64(seed))
     Ws = [rng.uniform(-1, 1, (dims[l + 1], dims[l])) * np.sqrt(3.0 / dims[l]) for l in range(len(dims) - 1)]
