@@ -303,12 +303,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, GemmEpi ep)
 #define TITAN_GEMM_BIG 2
 #endif
 // Tile shapes (compile-time choice for tuning builds; 8192^3 in TFLOP/s for
-// the NN / NT / TN layouts on MI355X: 256 x 256 683 / 987 / 609, 256 x 128
-// 705 / 750 / 355, 128 x 128 608 / 833 / 490).
+// the NN / NT / TN layouts on MI355X with the strided operand loaded inside
+// the product: 256 x 256 683 / 987 / 609, 256 x 128 705 / 750 / 355,
+// 128 x 128 608 / 833 / 490; NN / NT with the copied operand: 256 x 256 in
+// 8 waves 804-836 / 964-1,007, in 4 waves of 128 x 128 (one wave per SIMD,
+// 256 accumulators per lane) 737 / 850).
 #if TITAN_GEMM_BIG == 1
 constexpr int GWM = 2, GWN = 2, GMI = 4, GNJ = 2;  // 256 x 128, 4 waves of 128 x 64
 #elif TITAN_GEMM_BIG == 2
 constexpr int GWM = 2, GWN = 4, GMI = 4, GNJ = 2;  // 256 x 256, 8 waves of 128 x 64
+#elif TITAN_GEMM_BIG == 4
+constexpr int GWM = 2, GWN = 2, GMI = 4, GNJ = 4;  // 256 x 256, 4 waves of 128 x 128
 #else
 constexpr int GWM = 2, GWN = 2, GMI = 2, GNJ = 2;  // 128 x 128, 4 waves of 64 x 64
 #endif
