@@ -482,7 +482,12 @@ int titan_mlp_grad(titan_mlp *mlp, int32_t batch, const float *X, const float *Y
 /* The GEMM alone (not in the paper), on device arrays: C (M x N, FP32, row-major) = op(A) op(B)
  * with op(A)[m][k] = ta ? A[k*lda + m] : A[m*lda + k] and
  * op(B)[k][n] = tb ? B[n*ldb + k] : B[k*ldb + n] (bfloat16 bit patterns).
- * Asynchronous on `stream`. */
+ * Asynchronous on `stream`.  A large product (at least 128 output tiles of
+ * 256 x 256) with ta = 1 or tb = 0 first copies that operand with K
+ * contiguous into stream-ordered device memory (hipMallocAsync on `stream`,
+ * at most (M + N) x K values rounded to 16-byte rows, released on `stream`
+ * behind the product); without that memory it reads the operand in place.
+ * The result does not depend on which way it ran. */
 int titan_mlp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t *A_dev, int32_t lda, int32_t ta,
                         const uint16_t *B_dev, int32_t ldb, int32_t tb, float *C_dev, void *stream);
 
