@@ -1238,9 +1238,11 @@ extern "C" int titan_mlp_train(titan_mlp *m, int64_t nsteps, int32_t batch, cons
         return rc;
     if (int rc = mlp_alloc(m, sizeof(float) * (size_t)std::max<int64_t>(nsteps, 1), (void **)&dloss))
         return rc;
-    // every step's per-row squared errors; the losses are summed after the
-    // last step (one launch for all steps)
-    if (int rc = mlp_alloc(m, sizeof(float) * (size_t)std::max<int64_t>(nsteps * batch, 1), (void **)&dlrow))
+    // the per-row squared errors of up to kLossChunk steps; their losses are
+    // summed once per chunk (one launch for the chunk's steps)
+    constexpr int64_t kLossChunk = 1024;
+    const int64_t chunk = std::max<int64_t>(1, std::min(nsteps, kLossChunk));
+    if (int rc = mlp_alloc(m, sizeof(float) * (size_t)(chunk * batch), (void **)&dlrow))
         return rc;
     if (nsteps)
         MLP_TRY(hipMemcpyAsync(didx, idx, sizeof(int64_t) * nsteps * batch, hipMemcpyHostToDevice, m->stream));
@@ -1251,7 +1253,7 @@ extern "C" int titan_mlp_train(titan_mlp *m, int64_t nsteps, int32_t batch, cons
                            dim3(256), 0, m->stream, m->X, m->Y, didx + s * batch, batch, in, out, m->xs[0], m->xld[0],
                            m->yb);
         MLP_TRY(hipGetLastError());
-        if (int rc = backward(m, batch, dlrow + s * batch))
+        if (int rc = backward(m, batch, dlrow + (s % chunk) * batch))
             return rc;
         m->adam_t += 1;
         const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)m->adam_t));
@@ -1273,12 +1275,16 @@ extern "C" int titan_mlp_train(titan_mlp *m, int64_t nsteps, int32_t batch, cons
         if (!fused)
             if (int rc = refresh_bf16(m))
                 return rc;
+        // the losses of a completed chunk of steps (also the last, partial one)
+        if ((s + 1) % chunk == 0 || s + 1 == nsteps) {
+            const int64_t s0 = s - s % chunk;
+            hipLaunchKernelGGL(loss_rows_kernel, dim3((unsigned)(s + 1 - s0)), dim3(256), 0, m->stream, dlrow, batch,
+                               out, dloss + s0);
+            MLP_TRY(hipGetLastError());
+        }
     }
-    if (loss_out && nsteps) {
-        hipLaunchKernelGGL(loss_rows_kernel, dim3((unsigned)nsteps), dim3(256), 0, m->stream, dlrow, batch, out, dloss);
-        MLP_TRY(hipGetLastError());
+    if (loss_out && nsteps)
         MLP_TRY(hipMemcpyAsync(loss_out, dloss, sizeof(float) * nsteps, hipMemcpyDeviceToHost, m->stream));
-    }
     MLP_TRY(hipStreamSynchronize(m->stream));
     mlp_free(m, didx);
     mlp_free(m, dloss);

@@ -330,3 +330,28 @@ def test_adam_step_matches_reference_and_training_learns(n_in):
     print("loss", first, last)
     assert last < 0.2 * first
     net.close()
+
+
+def test_long_training_call_reports_every_step_loss():
+    """A training call of more steps than the loss buffer holds (its per-row
+    squared errors are summed every 1024 steps) equals the same steps taken in
+    calls of 100: every step's loss and the final parameters, bit for bit."""
+    from paper_1911_10274_amd import titan as T
+
+    dims = [8, 16, 2]
+    _, _, flat = _init(dims, 31)
+    rng = np.random.Generator(np.random.PCG64(32))
+    X = rng.normal(0, 1, (64, dims[0])).astype(np.float32)
+    Y = rng.normal(0, 1, (64, dims[-1])).astype(np.float32)
+    idx = rng.integers(0, 64, (1100, 4))
+    nets = [T.Mlp(dims), T.Mlp(dims)]
+    for net in nets:
+        net.set_params(flat)
+        net.set_data(X, Y)
+    one = nets[0].train(idx, lr=1e-3)
+    parts = np.concatenate([nets[1].train(idx[a:a + 100], lr=1e-3) for a in range(0, 1100, 100)])
+    assert one.shape == (1100,) and np.all(np.isfinite(one))
+    assert np.array_equal(one, parts)
+    assert np.array_equal(nets[0].get_params(), nets[1].get_params())
+    for net in nets:
+        net.close()
