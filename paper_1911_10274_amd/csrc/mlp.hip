@@ -731,13 +731,13 @@ __global__ __launch_bounds__(256) void head_kernel(int B, int in, const uint16_t
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1)
             acc[o] += __shfl_xor(acc[o], off, 64);
-    const float scale = 2.f / (float)((int64_t)B * O);
+    const float n = (float)((int64_t)B * O);  // dz as in the general path: 2 e / n
     float dzf[O], l = 0.f;
 #pragma unroll
     for (int o = 0; o < O; ++o) {
         const float zo = acc[o] + bias[o];
         const float e = zo - y[(int64_t)i * O + o];
-        const uint16_t d = f2bf(e * scale);
+        const uint16_t d = f2bf(2.f * e / n);
         dzf[o] = bf2f(d);
         l = fmaf(e, e, l);
         if (lane == o) {
