@@ -20,6 +20,14 @@ __global__ __launch_bounds__(T) void batch_step_kernel(GatherGraph g, BatchLayou
     float4 *sX = smem;
     float4 *sU = smem + cap;
     float4 *sV = smem + 2 * cap;
+    // wave law with offset tables: the step's sine of each of the group's
+    // distinct offsets, after the state arrays
+    float *sW = (float *)(smem + 3 * cap);
+    const bool wtab = WAVE && b.wave_cls != nullptr;
+    if (wtab)
+        g.wave_cls = b.wave_cls;
+    const int64_t w0 = wtab ? b.wave_off[blockIdx.x] : 0;
+    const int nw = wtab ? (int)(b.wave_off[blockIdx.x + 1] - w0) : 0;
     const int64_t m0 = b.mass_off[blockIdx.x];
     const int nm = (int)(b.mass_off[blockIdx.x + 1] - m0);
     const int tid = threadIdx.x;
@@ -31,7 +39,14 @@ __global__ __launch_bounds__(T) void batch_step_kernel(GatherGraph g, BatchLayou
     __syncthreads();
 
     for (int s = 0; s < nsteps; ++s) {
-        const Clock ck{(ACT && !WAVE) ? sc.trig[s] : make_float2(0.f, 1.f), (double)(sc.step + s) * sc.dt64};
+        const Clock ck{(ACT && !WAVE) ? sc.trig[s] : make_float2(0.f, 1.f), (double)(sc.step + s) * sc.dt64,
+                       wtab ? sW : nullptr};
+        if (wtab) {
+            // (the previous step's readers of the table passed two barriers)
+            for (int c = tid; c < nw; c += T)
+                sW[c] = wave_sine(ck.t, b.wave_t[w0 + c], sc);
+            __syncthreads();
+        }
         float4 nu[MAXM], nv[MAXM];
         bool ok = true;
 #pragma unroll
@@ -80,7 +95,8 @@ hipError_t launch_tm(const GatherGraph &g, const BatchLayout &b, const StateIO &
                      int nsteps, hipStream_t st)
 {
     auto kern = batch_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, YIELD, T, MAXM>;
-    const size_t lds = (size_t)b.max_group * 3 * sizeof(float4);
+    const size_t lds = (size_t)b.max_group * 3 * sizeof(float4) +
+                       (WAVE && b.wave_cls ? (size_t)b.max_wave * sizeof(float) : 0);
     if (lds > 65536) {
         const hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  (int)lds);

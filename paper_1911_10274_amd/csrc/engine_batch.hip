@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "titan_sim.h"
@@ -112,6 +113,94 @@ static void make_groups(const titan_sim *s, int64_t pack, std::vector<int64_t> &
     max_group = std::max(max_group, gsize);
 }
 
+// Wave law: each group's distinct spring offsets (bit patterns of the FP64
+// t_o the slots hold, padding slots included) and every slot's index among
+// them, so that the batched kernel evaluates the wave's sine once per
+// distinct offset and step instead of once per slot (the same function of
+// the same operands: the same bits).  Skipped when a group has more than
+// kMaxWaveCls offsets or the table would not fit in LDS beside the state.
+constexpr int64_t kMaxWaveCls = 1024;
+
+static int upload_wave_tables(titan_sim *s, const std::vector<int64_t> &goff, const std::vector<int64_t> &hoff,
+                              BatchEngine *be)
+{
+    const GatherGraph &g = s->gg;
+    const int64_t ng = (int64_t)goff.size() - 1, slots = (int64_t)s->h_slot_nbr.size();
+    if (!g.t_off || slots == 0)
+        return TITAN_OK;
+    std::vector<double> toff(slots);
+    HIP_TRY(s, hipMemcpyAsync(toff.data(), g.t_off, sizeof(double) * slots, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    std::vector<uint16_t> cls(slots, 0);
+    std::vector<int64_t> woff(1, 0);
+    std::vector<double> wt;
+    int64_t max_wave = 0;
+    for (int64_t q = 0; q < ng; ++q) {
+        std::vector<std::pair<uint64_t, int64_t>> keys;  // (bits, slot)
+        for (int64_t i = goff[q]; i < goff[q + 1]; ++i) {
+            const int64_t sl = i / kSlice, base = hoff[sl] + (i % kSlice);
+            const int64_t width = (hoff[sl + 1] - hoff[sl]) / kSlice;
+            for (int64_t w = 0; w < width; ++w) {
+                uint64_t bits;
+                memcpy(&bits, &toff[base + w * kSlice], 8);
+                keys.push_back({bits, base + w * kSlice});
+            }
+        }
+        std::sort(keys.begin(), keys.end());
+        int64_t c = -1;
+        for (size_t a = 0; a < keys.size(); ++a) {
+            if (a == 0 || keys[a].first != keys[a - 1].first) {
+                ++c;
+                double v;
+                memcpy(&v, &keys[a].first, 8);
+                wt.push_back(v);
+            }
+            if (c >= kMaxWaveCls)
+                return TITAN_OK;  // too many offsets: no tables
+            cls[keys[a].second] = (uint16_t)c;
+        }
+        woff.push_back((int64_t)wt.size());
+        max_wave = std::max(max_wave, c + 1);
+    }
+    if (be->lay.max_group * 3 * 16 + max_wave * 4 > 160 * 1024)
+        return TITAN_OK;
+    uint16_t *dc = nullptr;
+    int64_t *doff = nullptr;
+    double *dt = nullptr;
+    if (int rc = dev_alloc(s, sizeof(uint16_t) * slots, (void **)&dc))
+        return rc;
+    if (int rc = dev_alloc(s, sizeof(int64_t) * woff.size(), (void **)&doff)) {
+        dev_free(s, dc);
+        return rc;
+    }
+    if (int rc = dev_alloc(s, sizeof(double) * std::max<size_t>(wt.size(), 1), (void **)&dt)) {
+        dev_free(s, dc);
+        dev_free(s, doff);
+        return rc;
+    }
+    HIP_TRY(s, hipMemcpyAsync(dc, cls.data(), sizeof(uint16_t) * slots, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(doff, woff.data(), sizeof(int64_t) * woff.size(), hipMemcpyHostToDevice, s->stream));
+    if (!wt.empty())
+        HIP_TRY(s, hipMemcpyAsync(dt, wt.data(), sizeof(double) * wt.size(), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    be->lay.wave_cls = dc;
+    be->lay.wave_off = doff;
+    be->lay.wave_t = dt;
+    be->lay.max_wave = (int32_t)max_wave;
+    return TITAN_OK;
+}
+
+static void free_wave_tables(titan_sim *s, BatchEngine *be)
+{
+    dev_free(s, const_cast<uint16_t *>(be->lay.wave_cls));
+    dev_free(s, const_cast<int64_t *>(be->lay.wave_off));
+    dev_free(s, const_cast<double *>(be->lay.wave_t));
+    be->lay.wave_cls = nullptr;
+    be->lay.wave_off = nullptr;
+    be->lay.wave_t = nullptr;
+    be->lay.max_wave = 0;
+}
+
 // The batched layout of the groups `goff` on the device: group offsets and
 // each slot's neighbour relative to its group's first mass.
 static int upload_groups(titan_sim *s, const std::vector<int64_t> &goff, int64_t max_group,
@@ -146,7 +235,7 @@ static int upload_groups(titan_sim *s, const std::vector<int64_t> &goff, int64_t
     be->lay.nbr_group = e;
     // the host table goes away with this call
     HIP_TRY(s, hipStreamSynchronize(s->stream));
-    return TITAN_OK;
+    return upload_wave_tables(s, goff, hoff, be);
 }
 
 static void free_groups(titan_sim *s, BatchEngine *be)
@@ -155,6 +244,7 @@ static void free_groups(titan_sim *s, BatchEngine *be)
         return;
     dev_free(s, const_cast<int64_t *>(be->lay.mass_off));
     dev_free(s, const_cast<uint16_t *>(be->lay.nbr_group));
+    free_wave_tables(s, be);
     delete be;
 }
 
@@ -387,6 +477,14 @@ int enqueue_batch_integ(titan_sim *s, int64_t first_step, int64_t count)
         s->cur = 1 - s->cur;
     }
     return TITAN_OK;
+}
+
+void batch_drop_wave_tables(titan_sim *s)
+{
+    if (s->batch && s->batch->lay.wave_cls) {
+        (void)hipStreamSynchronize(s->stream);  // launches in flight may still read them
+        free_wave_tables(s, s->batch);
+    }
 }
 
 uint16_t *batch_nbr_group(titan_sim *s)

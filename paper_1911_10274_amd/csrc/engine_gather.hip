@@ -1063,6 +1063,9 @@ int insert_springs(titan_sim *s, int64_t first, int64_t count)
         err = scatter(g.act_c, 4, [&](const Put &p) { return s->h_amp[p.q]; });
         if (!err)
             err = scatter(g.t_off, 8, [&](const Put &p) { return wave_offset(s, xmin, p.q); });
+        // the batched engine's offset tables do not know the new slots
+        if (!err && grouped)
+            batch_drop_wave_tables(s);
     } else if (!err && act) {
         err = scatter(g.act_c, 4, [&](const Put &p) {
             float C, S;

@@ -39,6 +39,7 @@ struct SpringConst {
     float d0;     // |R| - L0 (only with explicit rest lengths)
     float L0;     // rest length (only with explicit rest lengths)
     double t_off; // wave-law offset t_o (only with the wave law)
+    int cls;      // wave law with a table: the offset's class in the group
     float yield;  // yield value Y; < 0: broken (only with breakable springs)
 };
 
@@ -47,6 +48,7 @@ struct SpringConst {
 struct Clock {
     float2 tr;
     double t;
+    const float *wtab = nullptr;  // wave law: this step's sine per offset class (batched engine), or null
 };
 
 // The FP64 time of step n plus an offset (an RK4 stage's c dt), rounded the
@@ -64,6 +66,20 @@ __device__ __forceinline__ double step_time(int64_t n, double dt64, double add)
 // tau = (t - t_o) mod t_p in [0, t_p).  The fold is done in FP64 with the same
 // operations as its definition, so which period a spring is in -- the
 // factor jumps at the period boundary -- does not depend on FP32 rounding.
+__device__ __forceinline__ float wave_sine(double t, double t_off, const StepConsts &sc)
+{
+#pragma clang fp contract(off)
+    const double u = t - t_off;
+    const double tau = u - sc.period * floor(u / sc.period);
+    // omega tau reaches tens of radians: reduce it to [-pi, pi] in FP64
+    // before the FP32 sine, so the argument's rounding is that of a number
+    // below pi, not of omega tau
+    constexpr double kTwoPi = 6.283185307179586, kInvTwoPi = 0.15915494309189535;
+    const double arg = sc.omega * tau;
+    const double red = arg - kTwoPi * rint(arg * kInvTwoPi);
+    return sinf((float)red);
+}
+
 template <bool ACT, bool WAVE>
 __device__ __forceinline__ float act_factor(const SpringConst &p, const Clock &ck, const StepConsts &sc)
 {
@@ -72,15 +88,8 @@ __device__ __forceinline__ float act_factor(const SpringConst &p, const Clock &c
         return 0.f;
     if (!WAVE)
         return fmaf(p.act_c, ck.tr.x, p.act_s * ck.tr.y);
-    const double u = ck.t - p.t_off;
-    const double tau = u - sc.period * floor(u / sc.period);
-    // omega tau reaches tens of radians: reduce it to [-pi, pi] in FP64
-    // before the FP32 sine, so the argument's rounding is that of a number
-    // below pi, not of omega tau
-    constexpr double kTwoPi = 6.283185307179586, kInvTwoPi = 0.15915494309189535;
-    const double arg = sc.omega * tau;
-    const double red = arg - kTwoPi * rint(arg * kInvTwoPi);
-    return p.act_c * sinf((float)red);
+    // the same sine, from the step's table when there is one
+    return p.act_c * (ck.wtab ? ck.wtab[p.cls] : wave_sine(ck.t, p.t_off, sc));
 }
 
 // Every floating-point operation below is spelled out: contraction of
@@ -373,7 +382,8 @@ __device__ __forceinline__ SpringConst load_const(const GatherGraph &g, int64_t 
     p.act_s = (ACT && !WAVE) ? const_load<NT>(g.act_s + e) : 0.f;
     p.d0 = REST ? const_load<NT>(g.d0 + e) : 0.f;
     p.L0 = REST ? const_load<NT>(g.rest + e) : 0.f;
-    p.t_off = WAVE ? const_load<NT>(g.t_off + e) : 0.0;
+    p.t_off = (WAVE && !g.wave_cls) ? const_load<NT>(g.t_off + e) : 0.0;
+    p.cls = (WAVE && g.wave_cls) ? (int)g.wave_cls[e] : 0;
     p.yield = YIELD ? const_load<NT>(g.yield + e) : 0.f;
     return p;
 }

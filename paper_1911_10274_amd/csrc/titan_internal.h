@@ -99,6 +99,9 @@ struct GatherGraph {
     const float *d0;           // [slots] |R| - rest (FP64-rounded), or null: rest = |R|
     const float *rest;         // [slots] rest length (with d0)
     const float4 *X0;          // [n] reference positions (w unused)
+    // batched engine, wave law: per slot the index of its spring's offset in
+    // the group's table of distinct offsets (BatchLayout::wave_*), or null
+    const uint16_t *wave_cls;
     float c_uniform;
     float k_uniform;
 };
@@ -140,6 +143,14 @@ struct BatchLayout {
     const int64_t *mass_off;     // [n_groups + 1]
     const uint16_t *nbr_group;   // [slots]
     int32_t max_group;           // masses of the largest group
+    // Wave law: each group's distinct spring offsets t_o are
+    // wave_t[wave_off[q] .. wave_off[q+1]) and a slot's offset is
+    // wave_t[wave_off[q] + wave_cls[slot]]; every step the batched kernel
+    // evaluates the wave's sine once per distinct offset.  Null when absent.
+    const uint16_t *wave_cls;    // [slots]
+    const int64_t *wave_off;     // [n_groups + 1]
+    const double *wave_t;
+    int32_t max_wave;            // most distinct offsets in a group
 };
 
 // Velocity Verlet / RK4 steps on the batched layout (batch_integ.hip):

@@ -190,6 +190,10 @@ int sync_broken(titan_sim *s);
 int update_yield(titan_sim *s, const std::vector<int64_t> &springs);
 // Device array of the batched layout's group-relative neighbour indices
 // (null without a batched layout).
+// The batched layout's tables of wave-law offsets are dropped (the kernel
+// then evaluates every slot's offset itself), e.g. after springs were
+// inserted in place with offsets the tables do not hold.
+void batch_drop_wave_tables(titan_sim *s);
 uint16_t *batch_nbr_group(titan_sim *s);
 // Rebuild the engines' layouts for the current topology, keeping the state,
 // the internal order and every device buffer that is not an engine's.
