@@ -198,7 +198,57 @@ struct GatherPlan {
     std::vector<uint16_t> nbr_local;
     std::vector<float> kk, cc, ac, as, d0, L0, yy;
     std::vector<double> to;
+    // wave law on the tiled layout: each tile's distinct offsets, per slot
+    // its class (see GatherGraph::tile_wave_*)
+    std::vector<uint16_t> twc;
+    std::vector<int64_t> twoff;
+    std::vector<double> twt;
+    int32_t max_tw = 0;
 };
+
+// Per tile, the distinct offsets of its masses' slots (padding included),
+// sorted by bit pattern, and each slot's index among them; none when a tile
+// has more than 1,024 or the table would not fit beside the tile's state.
+static void plan_tile_wave(GatherPlan &P, int64_t n)
+{
+    const int64_t nt = P.nt;
+    std::vector<uint16_t> cls(P.slots, 0);
+    std::vector<int64_t> woff(1, 0);
+    std::vector<double> wt;
+    int64_t maxw = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+        std::vector<std::pair<uint64_t, int64_t>> keys;
+        for (int64_t i = t * kTile; i < std::min(n, (t + 1) * kTile); ++i) {
+            const int64_t sl = i / kSlice, base = P.off[sl] + (i % kSlice);
+            const int64_t width = (P.off[sl + 1] - P.off[sl]) / kSlice;
+            for (int64_t w = 0; w < width; ++w) {
+                uint64_t bits;
+                memcpy(&bits, &P.to[base + w * kSlice], 8);
+                keys.push_back({bits, base + w * kSlice});
+            }
+        }
+        std::sort(keys.begin(), keys.end());
+        int64_t c = -1;
+        for (size_t a = 0; a < keys.size(); ++a) {
+            if (a == 0 || keys[a].first != keys[a - 1].first) {
+                if (++c >= 1024)
+                    return;
+                double v;
+                memcpy(&v, &keys[a].first, 8);
+                wt.push_back(v);
+            }
+            cls[keys[a].second] = (uint16_t)c;
+        }
+        woff.push_back((int64_t)wt.size());
+        maxw = std::max(maxw, c + 1);
+    }
+    if ((int64_t)P.max_local * 3 * 16 + maxw * 4 > 65536)  // (three state arrays at most)
+        return;
+    P.twc.swap(cls);
+    P.twoff.swap(woff);
+    P.twt.swap(wt);
+    P.max_tw = (int32_t)maxw;
+}
 
 // Plan the gather layout on the host (internal order already in s->perm):
 // incidence rows, tiles and halos, sliced-ELL slots and per-slot constants.
@@ -402,6 +452,8 @@ static void plan_gather(titan_sim *s, bool allow_tiled, GatherPlan &P)
                 yy[e] = s->h_yield[x.spring];
         }
     }
+    if (tiled && wave)
+        plan_tile_wave(P, n);
 }
 
 // Upload a planned gather layout and make it the current one.
@@ -462,6 +514,15 @@ static int upload_gather(titan_sim *s, GatherPlan &P)
         if (int rc = put(s, P.yy, &p))
             return rc;
         g.yield = const_cast<float *>(p);  // the step records breaks here
+    }
+    if (!P.twc.empty()) {
+        if (int rc = put(s, P.twc, &g.tile_wave_cls))
+            return rc;
+        if (int rc = put(s, P.twoff, &g.tile_wave_off))
+            return rc;
+        if (int rc = put(s, P.twt, &g.tile_wave_t))
+            return rc;
+        g.max_tile_wave = P.max_tw;
     }
     g.X0 = s->X0;
     s->tiled = tiled;
@@ -1063,9 +1124,18 @@ int insert_springs(titan_sim *s, int64_t first, int64_t count)
         err = scatter(g.act_c, 4, [&](const Put &p) { return s->h_amp[p.q]; });
         if (!err)
             err = scatter(g.t_off, 8, [&](const Put &p) { return wave_offset(s, xmin, p.q); });
-        // the batched engine's offset tables do not know the new slots
+        // the offset tables do not know the new slots
         if (!err && grouped)
             batch_drop_wave_tables(s);
+        if (!err && g.tile_wave_cls) {
+            dev_free(s, const_cast<uint16_t *>(g.tile_wave_cls));
+            dev_free(s, const_cast<int64_t *>(g.tile_wave_off));
+            dev_free(s, const_cast<double *>(g.tile_wave_t));
+            g.tile_wave_cls = nullptr;
+            g.tile_wave_off = nullptr;
+            g.tile_wave_t = nullptr;
+            g.max_tile_wave = 0;
+        }
     } else if (!err && act) {
         err = scatter(g.act_c, 4, [&](const Put &p) {
             float C, S;

@@ -91,11 +91,23 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
     float4 *sU = smem;
     float4 *sX = smem + L;
     float4 *sV = smem + 2 * L;  // only with damping
+    // wave law with offset tables: the step's sine of each of the tile's
+    // distinct offsets, after the state arrays
+    float *sW = (float *)(smem + (DAMP ? 3 : 2) * L);
 
     const unsigned t = xcd_tile(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
     const int64_t i = (int64_t)t * kTile + tid;
     const bool valid = i < g.n;
+    const bool wtab = WAVE && g.tile_wave_cls != nullptr;
+    if (wtab) {
+        g.wave_cls = g.tile_wave_cls;
+        const double tn = step_time(step_index(sc), sc.dt64, sc.t_add);
+        const int64_t w0 = g.tile_wave_off[t];
+        const int nw = (int)(g.tile_wave_off[t + 1] - w0);
+        for (int c = tid; c < nw; c += kTile)
+            sW[c] = wave_sine(tn, g.tile_wave_t[w0 + c], sc);  // read after the staging barrier
+    }
     // the Verlet kick stages the drifted state of the tile and its halo
     const bool drifting = MODE == kModeStage && sc.stage == kStageVerletKick;
     float4 ui = make_float4(0.f, 0.f, 0.f, 0.f), vi = ui, xi = ui;
@@ -133,7 +145,8 @@ __global__ __launch_bounds__(kTile) void tiled_step_kernel(GatherGraph g, StateI
     const int64_t base = g.slice_off[i >> 6] + (i & 63);
     float fx = 0.f, fy = 0.f, fz = 0.f;
     const int64_t n = step_index(sc);
-    const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), step_time(n, sc.dt64, sc.t_add)};
+    const Clock ck{(ACT && !WAVE) ? *sc.trig : make_float2(0.f, 1.f), step_time(n, sc.dt64, sc.t_add),
+                   wtab ? sW : nullptr};
     sum_forces<ACT, DAMP, DAMPV, REST, TITAN_NT_LOADS != 0, WAVE, yield_mode<YIELD, MODE>,
                plain_unroll<WAVE, DAMPV, REST, YIELD>>(
         g, base, slice_width(g, i), xi, ui, vi, ck, sc, [&](int64_t e) { return (int)stream_load(g.nbr_local + e); },
@@ -165,7 +178,8 @@ void launch_mode(const GatherGraph &g, const StateIO &io, const StepConsts &sc, 
 {
     if (tiled) {
         const dim3 grid((unsigned)g.n_tiles), block(kTile);
-        const size_t lds = (size_t)g.max_local * sizeof(float4) * (DAMP ? 3 : 2);
+        const size_t lds = (size_t)g.max_local * sizeof(float4) * (DAMP ? 3 : 2) +
+                           (WAVE && g.tile_wave_cls ? (size_t)g.max_tile_wave * sizeof(float) : 0);
         hipLaunchKernelGGL((tiled_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, MODE, YIELD>), grid, block, lds, st, g,
                            io, sc);
     } else {

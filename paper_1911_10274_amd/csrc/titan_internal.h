@@ -99,9 +99,17 @@ struct GatherGraph {
     const float *d0;           // [slots] |R| - rest (FP64-rounded), or null: rest = |R|
     const float *rest;         // [slots] rest length (with d0)
     const float4 *X0;          // [n] reference positions (w unused)
-    // batched engine, wave law: per slot the index of its spring's offset in
-    // the group's table of distinct offsets (BatchLayout::wave_*), or null
+    // wave law, the kernel at hand's table of distinct offsets: per slot the
+    // index of its spring's offset in that table, or null (each slot loads
+    // its own offset).  Null in the layout itself; a kernel with a table
+    // sets it in its own copy.
     const uint16_t *wave_cls;
+    // tiled layout, wave law: each tile's distinct offsets (the tiled
+    // kernel's table, as BatchLayout's wave_* for a group), or null
+    const uint16_t *tile_wave_cls;  // [slots]
+    const int64_t *tile_wave_off;   // [n_tiles + 1]
+    const double *tile_wave_t;
+    int32_t max_tile_wave;
     float c_uniform;
     float k_uniform;
 };
