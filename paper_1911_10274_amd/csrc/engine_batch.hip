@@ -164,19 +164,18 @@ static int upload_wave_tables(titan_sim *s, const std::vector<int64_t> &goff, co
     }
     if (be->lay.max_group * 3 * 16 + max_wave * 4 > 160 * 1024)
         return TITAN_OK;
+    // the tables are an optimisation: without the memory for them every slot
+    // evaluates its own offset
     uint16_t *dc = nullptr;
     int64_t *doff = nullptr;
     double *dt = nullptr;
-    if (int rc = dev_alloc(s, sizeof(uint16_t) * slots, (void **)&dc))
-        return rc;
-    if (int rc = dev_alloc(s, sizeof(int64_t) * woff.size(), (void **)&doff)) {
-        dev_free(s, dc);
-        return rc;
-    }
-    if (int rc = dev_alloc(s, sizeof(double) * std::max<size_t>(wt.size(), 1), (void **)&dt)) {
+    if (dev_alloc(s, sizeof(uint16_t) * slots, (void **)&dc) != TITAN_OK ||
+        dev_alloc(s, sizeof(int64_t) * woff.size(), (void **)&doff) != TITAN_OK ||
+        dev_alloc(s, sizeof(double) * std::max<size_t>(wt.size(), 1), (void **)&dt) != TITAN_OK) {
         dev_free(s, dc);
         dev_free(s, doff);
-        return rc;
+        dev_free(s, dt);
+        return TITAN_OK;
     }
     HIP_TRY(s, hipMemcpyAsync(dc, cls.data(), sizeof(uint16_t) * slots, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(s, hipMemcpyAsync(doff, woff.data(), sizeof(int64_t) * woff.size(), hipMemcpyHostToDevice, s->stream));
