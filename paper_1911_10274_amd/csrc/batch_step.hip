@@ -31,22 +31,26 @@ __global__ __launch_bounds__(T) void batch_step_kernel(GatherGraph g, BatchLayou
     const int64_t m0 = b.mass_off[blockIdx.x];
     const int nm = (int)(b.mass_off[blockIdx.x + 1] - m0);
     const int tid = threadIdx.x;
+    // the table of step s is written before the barrier that ends step
+    // s - 1 (the first one with the state, before the staging barrier), so
+    // it costs no barrier of its own
+    auto fill_table = [&](int s) {
+        const double ts = (double)(sc.step + s) * sc.dt64;
+        for (int c = tid; c < nw; c += T)
+            sW[c] = wave_sine(ts, b.wave_t[w0 + c], sc);
+    };
     for (int q = tid; q < nm; q += T) {
         sX[q] = g.X0[m0 + q];
         sU[q] = io.U_in[m0 + q];
         sV[q] = io.V_in[m0 + q];
     }
+    if (wtab && nsteps > 0)
+        fill_table(0);
     __syncthreads();
 
     for (int s = 0; s < nsteps; ++s) {
         const Clock ck{(ACT && !WAVE) ? sc.trig[s] : make_float2(0.f, 1.f), (double)(sc.step + s) * sc.dt64,
                        wtab ? sW : nullptr};
-        if (wtab) {
-            // (the previous step's readers of the table passed two barriers)
-            for (int c = tid; c < nw; c += T)
-                sW[c] = wave_sine(ck.t, b.wave_t[w0 + c], sc);
-            __syncthreads();
-        }
         float4 nu[MAXM], nv[MAXM];
         bool ok = true;
 #pragma unroll
@@ -81,6 +85,9 @@ __global__ __launch_bounds__(T) void batch_step_kernel(GatherGraph g, BatchLayou
                 sV[q] = nv[k];
             }
         }
+        // every reader of this step's table passed the barrier above
+        if (wtab && s + 1 < nsteps)
+            fill_table(s + 1);
         __syncthreads();
     }
 
