@@ -11,18 +11,24 @@ namespace titan {
 
 namespace {
 
-template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool YIELD, int T, int MAXM>
+// LDS a workgroup of the batched kernel may use (160 KB per CU on gfx950).
+constexpr size_t kBatchLdsBytes = 160 * 1024;
+
+// DB: the state is double-buffered in LDS (5 arrays instead of 3, when the
+// group fits): each step reads one buffer and writes the other, so one
+// barrier per step suffices instead of two.
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool YIELD, int T, int MAXM, bool DB>
 __global__ __launch_bounds__(T) void batch_step_kernel(GatherGraph g, BatchLayout b, StateIO io, StepConsts sc,
                                                        int nsteps)
 {
     extern __shared__ float4 smem[];
     const int cap = b.max_group;
     float4 *sX = smem;
-    float4 *sU = smem + cap;
-    float4 *sV = smem + 2 * cap;
+    float4 *sUa = smem + cap, *sVa = smem + 2 * cap;
+    float4 *sUb = DB ? smem + 3 * cap : sUa, *sVb = DB ? smem + 4 * cap : sVa;
     // wave law with offset tables: the step's sine of each of the group's
-    // distinct offsets, after the state arrays
-    float *sW = (float *)(smem + 3 * cap);
+    // distinct offsets, after the state arrays (two tables with DB)
+    float *sW = (float *)(smem + (DB ? 5 : 3) * cap);
     const bool wtab = WAVE && b.wave_cls != nullptr;
     if (wtab)
         g.wave_cls = b.wave_cls;
@@ -31,27 +37,33 @@ __global__ __launch_bounds__(T) void batch_step_kernel(GatherGraph g, BatchLayou
     const int64_t m0 = b.mass_off[blockIdx.x];
     const int nm = (int)(b.mass_off[blockIdx.x + 1] - m0);
     const int tid = threadIdx.x;
-    // the table of step s is written before the barrier that ends step
-    // s - 1 (the first one with the state, before the staging barrier), so
-    // it costs no barrier of its own
+    auto table = [&](int s) { return sW + ((DB && (s & 1)) ? b.max_wave : 0); };
+    // the table of step s is written before a barrier that every reader of
+    // that table's previous contents has passed (the staging barrier for
+    // step 0; then the last barrier of step s - 1, or with DB any point of
+    // step s - 1), so it costs no barrier of its own
     auto fill_table = [&](int s) {
         const double ts = (double)(sc.step + s) * sc.dt64;
+        float *tab = table(s);
         for (int c = tid; c < nw; c += T)
-            sW[c] = wave_sine(ts, b.wave_t[w0 + c], sc);
+            tab[c] = wave_sine(ts, b.wave_t[w0 + c], sc);
     };
     for (int q = tid; q < nm; q += T) {
         sX[q] = g.X0[m0 + q];
-        sU[q] = io.U_in[m0 + q];
-        sV[q] = io.V_in[m0 + q];
+        sUa[q] = io.U_in[m0 + q];
+        sVa[q] = io.V_in[m0 + q];
     }
     if (wtab && nsteps > 0)
         fill_table(0);
     __syncthreads();
 
     for (int s = 0; s < nsteps; ++s) {
+        const bool odd = DB && (s & 1);
+        const float4 *sU = odd ? sUb : sUa, *sV = odd ? sVb : sVa;  // this step's state
+        float4 *nU = DB ? (odd ? sUa : sUb) : sUa, *nV = DB ? (odd ? sVa : sVb) : sVa;  // the next
         const Clock ck{(ACT && !WAVE) ? sc.trig[s] : make_float2(0.f, 1.f), (double)(sc.step + s) * sc.dt64,
-                       wtab ? sW : nullptr};
-        float4 nu[MAXM], nv[MAXM];
+                       wtab ? table(s) : nullptr};
+        float4 nu[DB ? 1 : MAXM], nv[DB ? 1 : MAXM];
         bool ok = true;
 #pragma unroll
         for (int k = 0; k < MAXM; ++k) {
@@ -71,39 +83,47 @@ __global__ __launch_bounds__(T) void batch_step_kernel(GatherGraph g, BatchLayou
                         vj = DAMP ? sV[r] : make_float4(0.f, 0.f, 0.f, 0.f);
                     },
                     fx, fy, fz);
-                ok &= integrate_mass(xi, ui, vi, fx, fy, fz, sc, nu[k], nv[k]);
+                if (DB) {
+                    float4 uo, vo;
+                    ok &= integrate_mass(xi, ui, vi, fx, fy, fz, sc, uo, vo);
+                    nU[q] = uo;  // nobody reads this buffer during this step
+                    nV[q] = vo;
+                } else {
+                    ok &= integrate_mass(xi, ui, vi, fx, fy, fz, sc, nu[DB ? 0 : k], nv[DB ? 0 : k]);
+                }
             }
         }
         if (!ok)
             atomicMin(io.first_bad, (unsigned long long)(sc.step + s));
-        __syncthreads();
+        if (!DB) {
+            __syncthreads();
 #pragma unroll
-        for (int k = 0; k < MAXM; ++k) {
-            const int q = tid + k * T;
-            if (q < nm) {
-                sU[q] = nu[k];
-                sV[q] = nv[k];
+            for (int k = 0; k < MAXM; ++k) {
+                const int q = tid + k * T;
+                if (q < nm) {
+                    nU[q] = nu[DB ? 0 : k];
+                    nV[q] = nv[DB ? 0 : k];
+                }
             }
         }
-        // every reader of this step's table passed the barrier above
         if (wtab && s + 1 < nsteps)
             fill_table(s + 1);
         __syncthreads();
     }
 
+    const bool odd = DB && (nsteps & 1);
+    const float4 *sU = odd ? sUb : sUa, *sV = odd ? sVb : sVa;
     for (int q = tid; q < nm; q += T) {
         io.U_out[m0 + q] = sU[q];
         io.V_out[m0 + q] = sV[q];
     }
 }
 
-template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool YIELD, int T, int MAXM>
-hipError_t launch_tm(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc,
-                     int nsteps, hipStream_t st)
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool YIELD, int T, int MAXM, bool DB>
+hipError_t launch_db(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc,
+                     int nsteps, size_t lds, hipStream_t st)
 {
-    auto kern = batch_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, YIELD, T, MAXM>;
-    const size_t lds = (size_t)b.max_group * 3 * sizeof(float4) +
-                       (WAVE && b.wave_cls ? (size_t)b.max_wave * sizeof(float) : 0);
+    auto kern = batch_step_kernel<ACT, WAVE, DAMP, DAMPV, REST, YIELD, T, MAXM, DB>;
     if (lds > 65536) {
         const hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  (int)lds);
@@ -112,6 +132,20 @@ hipError_t launch_tm(const GatherGraph &g, const BatchLayout &b, const StateIO &
     }
     hipLaunchKernelGGL(kern, dim3((unsigned)b.n_groups), dim3(T), lds, st, g, b, io, sc, nsteps);
     return hipGetLastError();
+}
+
+// Double-buffered state when the group (and, with the wave law, two offset
+// tables) fits in LDS, else the single-buffered kernel.
+template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool YIELD, int T, int MAXM>
+hipError_t launch_tm(const GatherGraph &g, const BatchLayout &b, const StateIO &io, const StepConsts &sc,
+                     int nsteps, hipStream_t st)
+{
+    const size_t tab = WAVE && b.wave_cls ? (size_t)b.max_wave * sizeof(float) : 0;
+    const size_t lds_db = (size_t)b.max_group * 5 * sizeof(float4) + 2 * tab;
+    if (lds_db <= kBatchLdsBytes)
+        return launch_db<ACT, WAVE, DAMP, DAMPV, REST, YIELD, T, MAXM, true>(g, b, io, sc, nsteps, lds_db, st);
+    return launch_db<ACT, WAVE, DAMP, DAMPV, REST, YIELD, T, MAXM, false>(
+        g, b, io, sc, nsteps, (size_t)b.max_group * 3 * sizeof(float4) + tab, st);
 }
 
 template <bool ACT, bool WAVE, bool DAMP, bool DAMPV, bool REST, bool YIELD, int T>
