@@ -443,17 +443,24 @@ __global__ void voxel_grads_kernel(int64_t nv, const int64_t *vs_ptr, const int3
     gphi[v] = w.z * sp;
 }
 
-// J_b = -sum_{i in b} (m_i / M_b) * dux_i: one thread per body, masses of a
-// body contiguous, summed in index order (deterministic).
-__global__ void body_loss(const float *dux, const float *coef, const int64_t *body_off, int64_t nb, float *loss)
+// J_b = -sum_{i in b} (m_i / M_b) * dux_i: one wave per body, masses of a
+// body contiguous; lane l sums the body's masses l, l + 64, ... in index
+// order, then a butterfly of exchanges adds the 64 partial sums (the same
+// pairs in the same order on every run: deterministic, no atomics).
+__global__ __launch_bounds__(256) void body_loss(const float *dux, const float *coef, const int64_t *body_off,
+                                                 int64_t nb, float *loss)
 {
-    const int64_t bdy = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t bdy = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (bdy >= nb)
-        return;
+        return;  // the whole wave: one body per wave
     float acc = 0.f;
-    for (int64_t i = body_off[bdy]; i < body_off[bdy + 1]; ++i)
+    for (int64_t i = body_off[bdy] + lane; i < body_off[bdy + 1]; i += 64)
         acc = fmaf(coef[i], dux[i], acc);
-    loss[bdy] = -acc;
+    for (int o = 32; o > 0; o >>= 1)
+        acc += __shfl_xor(acc, o);
+    if (lane == 0)
+        loss[bdy] = -acc;
 }
 
 }  // namespace
@@ -509,8 +516,7 @@ hipError_t launch_body_loss(const float *dux, const float *coef, const int64_t *
 {
     if (nb == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(body_loss, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, stream, dux, coef, body_off, nb,
-                       loss);
+    hipLaunchKernelGGL(body_loss, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, stream, dux, coef, body_off, nb, loss);
     return hipGetLastError();
 }
 

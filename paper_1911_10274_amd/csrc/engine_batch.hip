@@ -575,7 +575,7 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
     };
     AdjointIO a{};
     float *dseed = nullptr, *dcoef = nullptr, *dloss = nullptr, *dgrad = nullptr;
-    int64_t *dboff = nullptr, *downer = nullptr;
+    int64_t *dboff = nullptr;
     float2 *dtrig = nullptr;
     unsigned long long *dbad = nullptr;
     int64_t nslots = 0;
@@ -593,7 +593,6 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
         (rc = get(sizeof(float) * n, (void **)&dseed)) || (rc = get(sizeof(float) * n, (void **)&dcoef)) ||
         (rc = get(sizeof(float) * n, (void **)&a.dux)) || (rc = get(sizeof(float) * nruns, (void **)&dloss)) ||
         (rc = get(sizeof(float) * 3 * ns, (void **)&dgrad)) || (rc = get(sizeof(int64_t) * (nruns + 1), (void **)&dboff)) ||
-        (rc = get(sizeof(int64_t) * ns, (void **)&downer)) ||
         (rc = get(sizeof(float2) * std::max<int64_t>(nsteps, 1), (void **)&dtrig)) ||
         (rc = get(sizeof(unsigned long long), (void **)&dbad))) {
         cleanup();
@@ -611,7 +610,25 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
     TRY(hipMemcpyAsync(dseed, seed.data(), sizeof(float) * n, hipMemcpyHostToDevice, s->stream));
     TRY(hipMemcpyAsync(dcoef, coef.data(), sizeof(float) * n, hipMemcpyHostToDevice, s->stream));
     TRY(hipMemcpyAsync(dboff, body_off.data(), sizeof(int64_t) * (nruns + 1), hipMemcpyHostToDevice, s->stream));
-    TRY(hipMemcpyAsync(downer, s->h_owner_slot.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, s->stream));
+    // the owner slots stay on the device between calls (sent again only
+    // after the layout or the spring set changed)
+    if (s->owner_dev_stale || s->d_owner_cap < ns) {
+        if (s->d_owner_cap < ns) {
+            if (s->d_owner_slot)
+                dev_free(s, s->d_owner_slot);
+            s->d_owner_slot = nullptr;
+            s->d_owner_cap = 0;
+            if ((rc = dev_alloc(s, sizeof(int64_t) * std::max<int64_t>(ns, 1), (void **)&s->d_owner_slot))) {
+                cleanup();
+                return rc;
+            }
+            s->d_owner_cap = ns;
+        }
+        if (ns)
+            TRY(hipMemcpyAsync(s->d_owner_slot, s->h_owner_slot.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice,
+                               s->stream));
+        s->owner_dev_stale = false;
+    }
     TRY(hipMemcpyAsync(dbad, &none, sizeof none, hipMemcpyHostToDevice, s->stream));
     TRY(hipMemsetAsync(a.gslot, 0, sizeof(float4) * std::max<int64_t>(nslots, 1), s->stream));
     TRY(launch_trig_table(dtrig, s->step_enq, (int)nsteps, s->params.omega, s->params.dt, s->stream));
@@ -624,12 +641,11 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
     a.K = K;
     const StepConsts sc = consts_for(s, s->step_enq, dtrig);
     TRY(launch_adjoint(s->gg, s->batch->lay, a, sc, s->stream));
-    TRY(launch_spring_grads(a.gslot, downer, ns, dgrad, dgrad + ns, dgrad + 2 * ns, s->stream));
+    TRY(launch_spring_grads(a.gslot, s->d_owner_slot, ns, dgrad, dgrad + ns, dgrad + 2 * ns, s->stream));
     TRY(launch_body_loss(a.dux, dcoef, dboff, nruns, dloss, s->stream));
     // per-voxel gradients through the mean-phasor map, on the device: each
     // voxel sums over its springs (ascending) the spring's (dJ/dC, dJ/dS)
     // divided by the spring's voxel count, turned by the voxel's phase
-    std::vector<float> hvox;
     float *dvox = nullptr;
     if (voxels && nv > 0) {
         int64_t *dvptr = nullptr;
@@ -662,29 +678,30 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
         TRY(hipMemcpyAsync(dvw, vw.data(), sizeof(float4) * nv, hipMemcpyHostToDevice, s->stream));
         TRY(launch_voxel_grads(nv, dvptr, dvspring, dinv, dvw, dgrad + ns, dgrad + 2 * ns, dvox, dvox + nv,
                                s->stream));
-        hvox.resize(2 * nv);
-        TRY(hipMemcpyAsync(hvox.data(), dvox, sizeof(float) * 2 * nv, hipMemcpyDeviceToHost, s->stream));
     }
-    std::vector<float> hgrad(3 * ns), hloss(nruns);
+    // the non-finite check first: on failure the caller's arrays are left
+    // as they were; then the results straight into them
     unsigned long long bad = ~0ull;
-    TRY(hipMemcpyAsync(hgrad.data(), dgrad, sizeof(float) * 3 * ns, hipMemcpyDeviceToHost, s->stream));
-    TRY(hipMemcpyAsync(hloss.data(), dloss, sizeof(float) * nruns, hipMemcpyDeviceToHost, s->stream));
     TRY(hipMemcpyAsync(&bad, dbad, sizeof bad, hipMemcpyDeviceToHost, s->stream));
+    TRY(hipStreamSynchronize(s->stream));
+    if (bad != ~0ull) {
+        cleanup();
+        return fail(TITAN_ENONFINITE, "the rollout produced a non-finite state at step %llu", bad);
+    }
+    std::vector<float> hloss(nruns);
+    float *const outs[3] = {gk, gC, gS};
+    for (int c = 0; c < 3; ++c)
+        if (outs[c] && ns)
+            TRY(hipMemcpyAsync(outs[c], dgrad + c * ns, sizeof(float) * ns, hipMemcpyDeviceToHost, s->stream));
+    if (gvox_a && nv)
+        TRY(hipMemcpyAsync(gvox_a, dvox, sizeof(float) * nv, hipMemcpyDeviceToHost, s->stream));
+    if (gvox_phi && nv)
+        TRY(hipMemcpyAsync(gvox_phi, dvox + nv, sizeof(float) * nv, hipMemcpyDeviceToHost, s->stream));
+    if (nruns)
+        TRY(hipMemcpyAsync(hloss.data(), dloss, sizeof(float) * nruns, hipMemcpyDeviceToHost, s->stream));
     TRY(hipStreamSynchronize(s->stream));
 #undef TRY
     cleanup();
-    if (bad != ~0ull)
-        return fail(TITAN_ENONFINITE, "the rollout produced a non-finite state at step %llu", bad);
-    if (gk)
-        std::copy(hgrad.begin(), hgrad.begin() + ns, gk);
-    if (gC)
-        std::copy(hgrad.begin() + ns, hgrad.begin() + 2 * ns, gC);
-    if (gS)
-        std::copy(hgrad.begin() + 2 * ns, hgrad.end(), gS);
-    if (gvox_a && nv)
-        std::copy(hvox.begin(), hvox.begin() + nv, gvox_a);
-    if (gvox_phi && nv)
-        std::copy(hvox.begin() + nv, hvox.end(), gvox_phi);
     if (loss) {
         for (int32_t b = 0; b < nb; ++b)
             loss[b] = 0.f;

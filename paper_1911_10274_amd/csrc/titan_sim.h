@@ -87,6 +87,11 @@ struct titan_sim {
     std::vector<int32_t> h_slot_nbr;  // per-slot neighbour (internal), kept only during finalize
     std::vector<int64_t> h_owner_slot;  // per spring (caller order): its slot at the lower-index end
     std::vector<int64_t> h_other_slot;  // per spring: its slot at the other end
+    // device copy of h_owner_slot for the rollout gradient, kept between
+    // calls; stale after any change to h_owner_slot
+    int64_t *d_owner_slot = nullptr;
+    int64_t d_owner_cap = 0;
+    bool owner_dev_stale = true;
     float2 *trig = nullptr;           // clock table: kTrigChunk entries + 1 for force queries
     std::shared_ptr<titan::GatherPlan> gplan;  // planned before the device was set up; used once
 
