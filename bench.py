@@ -293,31 +293,39 @@ def bench_adjoint(T, robots_n: int, steps: int, K: int):
                   omega=2 * math.pi * 2, engine=T.ENGINE_BATCHED)
     sim = T.sim_from_scene(sc, tp)
     sim.finalize()
-    sim.rollout_grad(steps, K)  # warm-up
-    torch.cuda.synchronize()
     reps = 3
-    t0 = _t.perf_counter()
-    for _ in range(reps):
-        sim.rollout_grad(steps, K)
-    sec = (_t.perf_counter() - t0) / reps
+    # outputs in HBM (titan_rollout_grad_device): the device-resident rate;
+    # the host-output call adds the copy of the gradients to host memory
+    outs = (torch.empty(len(robots), dtype=torch.float32, device="cuda"),
+            *(torch.empty(ns, dtype=torch.float32, device="cuda") for _ in range(3)))
+
+    def timed(k, device):
+        run = (lambda: sim.rollout_grad_device(steps, k, out=outs)) if device else (lambda: sim.rollout_grad(steps, k))
+        run()  # warm-up
+        torch.cuda.synchronize()
+        t0 = _t.perf_counter()
+        for _ in range(reps):
+            run()
+        return (_t.perf_counter() - t0) / reps
+
+    sec = timed(K, True)
+    sec_host = timed(K, False)
     # every state kept (one segment, no recompute): 48 B per mass per step
-    sim.rollout_grad(steps, steps)
-    torch.cuda.synchronize()
-    t0 = _t.perf_counter()
-    for _ in range(reps):
-        sim.rollout_grad(steps, steps)
-    sec_all = (_t.perf_counter() - t0) / reps
+    sec_all = timed(steps, True)
+    sec_all_host = timed(steps, False)
     ms_fwd = _timed_steps(sim, steps, torch.cuda.current_stream())
     sim.close()
     return {"workload": f"{robots_n} voxel robots, side U{{4..8}}, {steps}-step rollout, checkpoints every {K} "
-                        f"steps, gradients w.r.t. every spring's k and actuation phasor",
+                        f"steps, gradients w.r.t. every spring's k and actuation phasor (outputs in HBM)",
             "robots": robots_n, "masses": nm, "springs": ns, "steps": steps, "checkpoint_every": K,
             "value": steps / sec, "unit": "adjoint steps/s",
             "robot_steps_per_s": robots_n * steps / sec,
             "ms_per_gradient": sec * 1e3,
+            "ms_per_gradient_host_outputs": sec_host * 1e3,
             "forward_ms": ms_fwd, "gradient_over_forward": sec * 1e3 / ms_fwd,
             "all_states_kept": {"checkpoint_every": steps, "segment_bytes": 48 * nm * steps,
                                 "ms_per_gradient": sec_all * 1e3, "value": steps / sec_all,
+                                "ms_per_gradient_host_outputs": sec_all_host * 1e3,
                                 "gradient_over_forward": sec_all * 1e3 / ms_fwd}}
 
 

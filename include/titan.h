@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TITAN_ABI_VERSION 7
+#define TITAN_ABI_VERSION 8
 
 /* Status codes. */
 #define TITAN_OK 0
@@ -426,6 +426,17 @@ int titan_rollout_grad(titan_sim *sim, int64_t nsteps, int32_t checkpoint_every,
  * grad_voxel_a[n_voxels], grad_voxel_phi[n_voxels]. */
 int titan_rollout_grad_voxel(titan_sim *sim, int64_t nsteps, int32_t checkpoint_every, const float *body_weights,
                              float *loss_out, float *grad_k, float *grad_voxel_a, float *grad_voxel_phi);
+
+/* The rollout gradient of titan_rollout_grad (same rollout, loss, checkpoints,
+ * refusals and bits; not in the paper) with the outputs in device memory, for
+ * callers whose parameters and gradients live on the GPU: loss_out[n_bodies],
+ * grad_k, grad_act_c and grad_act_s[n_springs] are device pointers of the
+ * simulation's GPU (each may be NULL; TITAN_EINVAL for any other pointer).
+ * body_weights stays a host array (or NULL).  The outputs are written on the
+ * simulation's stream and the call returns once they are complete; on an
+ * error (TITAN_ENONFINITE included) they are not written. */
+int titan_rollout_grad_device(titan_sim *sim, int64_t nsteps, int32_t checkpoint_every, const float *body_weights,
+                              float *loss_out, float *grad_k, float *grad_act_c, float *grad_act_s);
 
 /* Summed spring force on masses [first, first+count) at the current state
  * and the current step's time (blocks): the spring pass of Sec. III-B

@@ -5,7 +5,9 @@ spring_body)`` returns, per body b, J_b = -(x-displacement of body b's centre
 of mass) after ``nsteps`` steps from the simulation's current state, and is
 differentiable with respect to the per-spring stiffness ``k`` and actuation
 phasor (``act_c`` = amp cos(phase), ``act_s`` = amp sin(phase)); the phasors
-go to the simulation as given (``titan_set_springs_phasor``).
+go to the simulation as given (``titan_set_springs_phasor``). With the
+parameters on the GPU the loss and gradients never leave GPU memory
+(``titan_rollout_grad_device``).
 
 ``TitanVoxelRollout.apply(k, voxel_a, voxel_phi, sim, nsteps,
 checkpoint_every, spring_body, sv_ptr, sv_idx)`` is the same loss with the
@@ -35,16 +37,19 @@ class TitanRollout(torch.autograd.Function):
     def forward(ctx, k, act_c, act_s, sim, nsteps: int, checkpoint_every: int, spring_body):
         sim.set_springs(0, k=_np32(k))
         sim.set_springs_phasor(0, _np32(act_c), _np32(act_s))
-        loss, gk, gc, gs = sim.rollout_grad(nsteps, checkpoint_every)
-        ctx.save_for_backward(torch.from_numpy(gk), torch.from_numpy(gc), torch.from_numpy(gs),
-                              spring_body.to("cpu", torch.int64))
+        if k.is_cuda:
+            # loss and gradients stay in GPU memory (titan_rollout_grad_device)
+            loss, gk, gc, gs = sim.rollout_grad_device(nsteps, checkpoint_every)
+        else:
+            loss, gk, gc, gs = (torch.from_numpy(a) for a in sim.rollout_grad(nsteps, checkpoint_every))
+        ctx.save_for_backward(gk, gc, gs, spring_body.to(gk.device, torch.int64))
         ctx.devices = (k.device, act_c.device, act_s.device)
-        return torch.from_numpy(loss).to(k.device)
+        return loss.to(k.device)
 
     @staticmethod
     def backward(ctx, grad_loss):
         gk, gc, gs, body = ctx.saved_tensors
-        w = grad_loss.detach().to("cpu", torch.float32)[body]
+        w = grad_loss.detach().to(gk.device, torch.float32)[body]
         dk, dc, ds = ctx.devices
         return (gk * w).to(dk), (gc * w).to(dc), (gs * w).to(ds), None, None, None, None
 

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "titan_sim.h"
@@ -499,7 +500,7 @@ void destroy_batch_engine(titan_sim *s)
 
 // Adjoint rollout on the batched layout (see adjoint_step.hip).
 int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weights, float *loss, float *gk,
-                 float *gC, float *gS, float *gvox_a, float *gvox_phi)
+                 float *gC, float *gS, float *gvox_a, float *gvox_phi, bool dev_out)
 {
     const bool voxels = gvox_a || gvox_phi;
     const int64_t nv = (int64_t)s->h_vox_a.size();
@@ -520,6 +521,14 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
         int32_t nb = 0;
         for (int32_t b : s->h_body)
             nb = std::max(nb, b + 1);
+        if (dev_out) {
+            const std::pair<float *, int64_t> outs[4] = {{loss, nb}, {gk, ns}, {gC, ns}, {gS, ns}};
+            for (const auto &o : outs)
+                if (o.first && o.second)
+                    HIP_TRY(s, hipMemsetAsync(o.first, 0, sizeof(float) * o.second, s->stream));
+            HIP_TRY(s, hipStreamSynchronize(s->stream));
+            return TITAN_OK;
+        }
         if (loss)
             std::fill(loss, loss + nb, 0.f);
         for (float *g : {gk, gC, gS})
@@ -692,7 +701,8 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
     float *const outs[3] = {gk, gC, gS};
     for (int c = 0; c < 3; ++c)
         if (outs[c] && ns)
-            TRY(hipMemcpyAsync(outs[c], dgrad + c * ns, sizeof(float) * ns, hipMemcpyDeviceToHost, s->stream));
+            TRY(hipMemcpyAsync(outs[c], dgrad + c * ns, sizeof(float) * ns,
+                               dev_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
     if (gvox_a && nv)
         TRY(hipMemcpyAsync(gvox_a, dvox, sizeof(float) * nv, hipMemcpyDeviceToHost, s->stream));
     if (gvox_phi && nv)
@@ -703,10 +713,14 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
 #undef TRY
     cleanup();
     if (loss) {
-        for (int32_t b = 0; b < nb; ++b)
-            loss[b] = 0.f;
+        // per body in the caller's numbering (a body without masses: 0)
+        std::vector<float> lb(nb, 0.f);
         for (int64_t r = 0; r < nruns; ++r)
-            loss[rank_body[r]] = hloss[r];
+            lb[rank_body[r]] = hloss[r];
+        if (dev_out)
+            HIP_TRY(s, hipMemcpy(loss, lb.data(), sizeof(float) * nb, hipMemcpyHostToDevice));
+        else
+            std::copy(lb.begin(), lb.end(), loss);
     }
     return TITAN_OK;
 }

@@ -1394,12 +1394,10 @@ extern "C" int titan_get_body_displacement_noalloc(titan_sim *s, float *disp)
     return check_bad(s);
 }
 
-extern "C" int titan_rollout_grad(titan_sim *s, int64_t nsteps, int32_t checkpoint_every, const float *body_weights,
-                                  float *loss_out, float *grad_k, float *grad_act_c, float *grad_act_s)
+// What every rollout-gradient entry point refuses, then the layout made
+// current (caller holds the lock).
+static int rollout_ready(titan_sim *s)
 {
-    if (!s)
-        return fail(TITAN_EINVAL, "sim is NULL");
-    std::lock_guard<std::mutex> lk(s->mu);
     if (s->params.actuation != TITAN_ACT_PHASOR)
         return fail(TITAN_ESTATE, "the rollout adjoint covers phasor actuation only");
     if (s->params.integrator != TITAN_INTEG_EULER)
@@ -1408,9 +1406,44 @@ extern "C" int titan_rollout_grad(titan_sim *s, int64_t nsteps, int32_t checkpoi
         return fail(TITAN_ESTATE, "the rollout adjoint covers unbreakable springs only");
     if (int rc = ready(s))
         return rc;
-    if (int rc = ensure_layout(s))
+    return ensure_layout(s);
+}
+
+extern "C" int titan_rollout_grad(titan_sim *s, int64_t nsteps, int32_t checkpoint_every, const float *body_weights,
+                                  float *loss_out, float *grad_k, float *grad_act_c, float *grad_act_s)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (int rc = rollout_ready(s))
         return rc;
     return rollout_grad(s, nsteps, checkpoint_every, body_weights, loss_out, grad_k, grad_act_c, grad_act_s);
+}
+
+extern "C" int titan_rollout_grad_device(titan_sim *s, int64_t nsteps, int32_t checkpoint_every,
+                                         const float *body_weights, float *loss_out, float *grad_k,
+                                         float *grad_act_c, float *grad_act_s)
+{
+    if (!s)
+        return fail(TITAN_EINVAL, "sim is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (int rc = rollout_ready(s))
+        return rc;
+    // every output given must be device memory of the simulation's GPU
+    for (const float *p : {(const float *)loss_out, (const float *)grad_k, (const float *)grad_act_c,
+                           (const float *)grad_act_s}) {
+        if (!p)
+            continue;
+        hipPointerAttribute_t at{};
+        if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(TITAN_EINVAL, "an output is not device memory");
+        }
+        if (at.type != hipMemoryTypeDevice || at.device != s->device)
+            return fail(TITAN_EINVAL, "an output is not device memory of the simulation's GPU");
+    }
+    return rollout_grad(s, nsteps, checkpoint_every, body_weights, loss_out, grad_k, grad_act_c, grad_act_s,
+                        nullptr, nullptr, true);
 }
 
 extern "C" int titan_rollout_grad_voxel(titan_sim *s, int64_t nsteps, int32_t checkpoint_every,
@@ -1422,15 +1455,7 @@ extern "C" int titan_rollout_grad_voxel(titan_sim *s, int64_t nsteps, int32_t ch
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->h_vs_ptr.empty())
         return fail(TITAN_ESTATE, "no voxel actuation (titan_set_voxel_actuation)");
-    if (s->params.actuation != TITAN_ACT_PHASOR)
-        return fail(TITAN_ESTATE, "the rollout adjoint covers phasor actuation only");
-    if (s->params.integrator != TITAN_INTEG_EULER)
-        return fail(TITAN_ESTATE, "the rollout adjoint covers the Euler integrator only");
-    if (!s->h_yield.empty())
-        return fail(TITAN_ESTATE, "the rollout adjoint covers unbreakable springs only");
-    if (int rc = ready(s))
-        return rc;
-    if (int rc = ensure_layout(s))
+    if (int rc = rollout_ready(s))
         return rc;
     std::vector<float> ga(s->h_vox_a.size()), gp(s->h_vox_a.size());
     if (int rc = rollout_grad(s, nsteps, checkpoint_every, body_weights, loss_out, grad_k, nullptr, nullptr,

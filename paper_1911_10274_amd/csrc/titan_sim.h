@@ -157,8 +157,9 @@ int update_spring_list(titan_sim *s, const std::vector<int64_t> &springs, bool k
                        bool force);
 // The rollout adjoint; with gvox_a / gvox_phi (either non-null) also the
 // gradients of the per-voxel actuation (the sim's voxel map must be set).
+// With dev_out, loss / gk / gC / gS are device pointers (no voxel outputs).
 int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weights, float *loss, float *gk,
-                 float *gC, float *gS, float *gvox_a = nullptr, float *gvox_phi = nullptr);
+                 float *gC, float *gS, float *gvox_a = nullptr, float *gvox_phi = nullptr, bool dev_out = false);
 
 // Engines (engine_gather.hip): build the device representation of the
 // selected engine after the state buffers exist, enqueue steps, compute the

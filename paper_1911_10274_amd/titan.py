@@ -140,6 +140,7 @@ def _load():
         "titan_set_springs_phasor": ([_vp, ctypes.c_int64, ctypes.c_int64, _fp, _fp], ctypes.c_int),
         "titan_set_voxel_actuation": ([_vp, ctypes.c_int64, _fp, _fp, _i64p, _i32p], ctypes.c_int),
         "titan_rollout_grad_voxel": ([_vp, ctypes.c_int64, ctypes.c_int32, _fp, _fp, _fp, _fp, _fp], ctypes.c_int),
+        "titan_rollout_grad_device": ([_vp, ctypes.c_int64, ctypes.c_int32, _fp, _vp, _vp, _vp, _vp], ctypes.c_int),
         "titan_get_info": ([_vp, ctypes.POINTER(_Info)], ctypes.c_int),
         "titan_mlp_create": ([ctypes.c_int32, _i32p, _vp, ctypes.POINTER(_Allocator), ctypes.POINTER(_vp)],
                              ctypes.c_int),
@@ -431,6 +432,30 @@ class Sim:
         _check(lib.titan_rollout_grad(self._h, int(nsteps), int(checkpoint_every), wp, loss.ctypes.data_as(_fp),
                                       gk.ctypes.data_as(_fp), gc.ctypes.data_as(_fp), gs.ctypes.data_as(_fp)))
         return loss, gk, gc, gs
+
+    def rollout_grad_device(self, nsteps: int, checkpoint_every: int = 50, body_weights=None, out=None):
+        """As ``rollout_grad`` with the results in GPU memory: returns torch
+        float32 tensors (loss per body, dJ/dk, dJ/dC, dJ/dS) on the current
+        device, or writes into ``out`` (four contiguous float32 CUDA tensors
+        of those sizes, or None for an output not wanted)."""
+        import torch
+
+        info = self.info()
+        nb, ns = info["n_bodies"], info["n_springs"]
+        w, wp = _f32(body_weights, (nb,)) if body_weights is not None else (None, None)
+        if out is None:
+            out = (torch.empty(nb, dtype=torch.float32, device="cuda"),
+                   *(torch.empty(ns, dtype=torch.float32, device="cuda") for _ in range(3)))
+        ptrs = []
+        for t, n in zip(out, (nb, ns, ns, ns)):
+            if t is None:
+                ptrs.append(None)
+                continue
+            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == n):
+                raise ValueError("outputs must be contiguous float32 CUDA tensors of n_bodies / n_springs values")
+            ptrs.append(_vp(t.data_ptr()))
+        _check(lib.titan_rollout_grad_device(self._h, int(nsteps), int(checkpoint_every), wp, *ptrs))
+        return tuple(out)
 
     def set_springs_phasor(self, first: int = 0, act_c=None, act_s=None):
         """Actuation phasors (C, S) of springs [first, first + len) as given."""

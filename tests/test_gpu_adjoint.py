@@ -257,3 +257,40 @@ def test_adjoint_needs_fitting_bodies():
         sim.rollout_grad(10, 5)
     assert ei.value.code == T.ESTATE
     sim.close()
+
+
+def test_device_outputs_equal_host_outputs_bit_for_bit():
+    """titan_rollout_grad_device: the same bits as the host-output call, into
+    device memory; any output may be left out; host pointers refused; a
+    zero-step rollout writes zeros."""
+    import ctypes
+
+    import torch
+
+    from paper_1911_10274_amd import titan as T
+
+    robots = scenes.robot_batch(6, seed=15, side_lo=3, side_hi=6)
+    sc = scenes.concat(robots)
+    w = np.linspace(0.5, 1.5, len(robots)).astype(np.float32)
+    sim = T.sim_from_scene(sc, _tp())
+    host = sim.rollout_grad(120, 40, w)
+    dev = sim.rollout_grad_device(120, 40, w)
+    assert all(t.is_cuda and t.dtype == torch.float32 for t in dev)
+    for h, d in zip(host, dev):
+        assert np.array_equal(h, d.cpu().numpy())
+    # only dJ/dk and dJ/dC wanted (NULL for the others)
+    ns = host[1].size
+    gk = torch.full((ns,), 7.0, device="cuda")
+    gc = torch.empty(ns, device="cuda")
+    sim.rollout_grad_device(120, 40, w, out=(None, gk, gc, None))
+    assert np.array_equal(gk.cpu().numpy(), host[1])
+    assert np.array_equal(gc.cpu().numpy(), host[2])
+    # a host array is not device memory: refused before any work
+    arr = np.zeros(ns, np.float32)
+    rc = T.lib.titan_rollout_grad_device(sim._h, 10, 5, None, None, ctypes.c_void_p(arr.ctypes.data), None, None)
+    assert rc == T.EINVAL
+    # zero steps: zeros
+    outs = tuple(torch.full((n,), 3.0, device="cuda") for n in (len(robots), ns, ns, ns))
+    sim.rollout_grad_device(0, 5, out=outs)
+    assert all(bool((t == 0).all()) for t in outs)
+    sim.close()

@@ -136,3 +136,33 @@ def test_gradient_ascent_moves_the_robot_further():
     print("losses", losses)
     assert losses[-1] < losses[0]
     sim.close()
+
+
+def test_autograd_function_on_gpu_tensors_equals_cpu_tensors():
+    # parameters on the GPU: loss and gradients come back through the
+    # device-output call and are the same bits as the host-output path
+    import torch
+
+    from paper_1911_10274_amd import titan as T
+    from paper_1911_10274_amd.autograd import TitanRollout
+
+    robots = scenes.robot_batch(3, seed=6, side_lo=3, side_hi=5)
+    sc = scenes.concat(robots)
+    sim = T.sim_from_scene(sc, _tp())
+    c = (sc["amp"].astype(np.float64) * np.cos(sc["phase"])).astype(np.float32)
+    s = (sc["amp"].astype(np.float64) * np.sin(sc["phase"])).astype(np.float32)
+    spring_body = torch.tensor(sc["body"][sc["ends"][:, 0]], dtype=torch.int64)
+    w = [1.0, -0.5, 2.0]
+    got = []
+    for dev in ("cpu", "cuda"):
+        k = torch.tensor(sc["k"], device=dev, requires_grad=True)
+        C = torch.tensor(c, device=dev, requires_grad=True)
+        S = torch.tensor(s, device=dev, requires_grad=True)
+        J = TitanRollout.apply(k, C, S, sim, 200, 40, spring_body.to(dev))
+        assert J.device.type == dev
+        (J * torch.tensor(w, device=dev)).sum().backward()
+        assert k.grad.device.type == dev
+        got.append([t.detach().cpu().numpy() for t in (J, k.grad, C.grad, S.grad)])
+    for a, b in zip(*got):
+        assert np.array_equal(a, b)
+    sim.close()
