@@ -55,6 +55,28 @@ def test_adjoint_matches_oracle_adjoint_8_robots():
     np.testing.assert_allclose(loss, ref["loss"], rtol=1e-3)
 
 
+@pytest.mark.parametrize("side,seed,occ,lo,hi", [
+    (4, 40, 0.6, 1, 256),       # 112 masses: 256-thread groups
+    (7, 41, 0.6, 257, 512),     # 445 masses: 512-thread groups
+    (9, 42, 0.6, 513, 1024),    # 934 masses: 1024-thread groups
+    (11, 20, 0.7, 1025, 2048),  # 1,699 masses: two masses per thread
+])
+def test_adjoint_every_group_size_matches_oracle(side, seed, occ, lo, hi):
+    # one body, so the group is that body whatever packing the batched
+    # engine's tuner picks: each launch shape of the adjoint kernel is run
+    robots = scenes.robot_batch(1, seed=seed, side_lo=side, side_hi=side, p_occ=occ)
+    sc = scenes.concat(robots)
+    (loss, gk, gC, gS), info = _gpu_grad(sc, 300, 50)
+    assert lo <= info["batch_max_group"] <= hi
+    ref = O.System(sc).rollout_grad(OP, 300, body=sc["body"])
+    for name, g, r in (("k", gk, ref["gk"]), ("C", gC, ref["gC"]), ("S", gS, ref["gS"])):
+        e = np.linalg.norm(g - r) / np.linalg.norm(r)
+        c = _cos(g.astype(np.float64), r)
+        print(side, name, "rel", e, "cos", c)
+        assert e <= 1e-3 and c >= 0.9999
+    np.testing.assert_allclose(loss, ref["loss"], rtol=1e-3)
+
+
 def _voxel_scene(robots):
     """The robots side by side with their voxel maps, voxel values rounded to
     FP32 (what the library receives) and the springs' phasors recomputed in
