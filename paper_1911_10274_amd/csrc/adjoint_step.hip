@@ -16,28 +16,40 @@
 //                -> force adjoint mu_i = dt/m * dJ/dw_i (kept in LDS)
 //   spring pass: every spring's force depends on both ends' x and v and on
 //                (k, C, S): gather, per mass, the contributions of its springs
-//                from mu_i - mu_j; the spring's owner slot (lower internal
-//                index end) adds the parameter gradients.  No atomics.
+//                from mu_i - mu_j; the spring's owner (lower internal index
+//                end) adds the parameter gradients.  No atomics.
+// Forward steps sum each mass's slots in their fixed order, as every engine
+// does (same states, bit for bit).  In the reverse steps, with the host's
+// spring tables (groups of at most 1024 masses), each spring's adjoint terms
+// and parameter gradients are evaluated once per step, by one thread, into
+// LDS records that both ends then add (the other end negated: the value it
+// would compute itself, bit for bit), in ascending spring order and in
+// chunks when a group's records exceed LDS.  Otherwise every slot evaluates
+// its spring's terms itself.
 #include "step_device.h"
 
 namespace titan {
 
 namespace {
 
-// dJ/d(spring inputs) for one incidence of mass i: updates the adjoints of
-// x_i, v_i and returns the parameter-gradient contributions (k, C, S).
+// dJ/d(spring inputs) for one incidence of mass i: the terms that move the
+// adjoints of mass i -- lx_i -= gd, lv_i -= bu -- and the parameter-gradient
+// contributions (k, C, S).  Seen from the spring's other end every operand
+// is negated, so that end receives exactly -gd and -bu (lx_j += gd,
+// lv_j += bu) and the same parameter terms.
 template <bool ACT, bool DAMP, bool REST>
-__device__ __forceinline__ void spring_adjoint(const float4 &xi, const float4 &ui, const float4 &vi,
-                                               const float4 &xj, const float4 &uj, const float4 &vj,
-                                               const SpringConst &p, float sin_wt, float cos_wt,
-                                               const float4 &mi, const float4 &mj, float3 &lx, float3 &lv,
-                                               float &gk, float &gC, float &gS)
+__device__ __forceinline__ void spring_adjoint_terms(const float4 &xi, const float4 &ui, const float4 &vi,
+                                                     const float4 &xj, const float4 &uj, const float4 &vj,
+                                                     const SpringConst &p, float sin_wt, float cos_wt,
+                                                     const float4 &mi, const float4 &mj, float3 &gd, float3 &bu,
+                                                     float &gk, float &gC, float &gS)
 {
 #pragma clang fp contract(off)
     const float Rx = xj.x - xi.x, Ry = xj.y - xi.y, Rz = xj.z - xi.z;
     const float ax = uj.x - ui.x, ay = uj.y - ui.y, az = uj.z - ui.z;
     const float dx = Rx + ax, dy = Ry + ay, dz = Rz + az;
     const float l2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    gd = bu = make_float3(0.f, 0.f, 0.f);
     gk = gC = gS = 0.f;
     if (!(l2 > 0.f))
         return;  // no force, no gradient (also the padding slots)
@@ -65,22 +77,39 @@ __device__ __forceinline__ void spring_adjoint(const float4 &xi, const float4 &u
     const float a1 = pu * p.k;
     const float a2 = DAMP ? pu * p.c * il : 0.f;
     const float a3 = mag * il;
-    const float gx = fmaf(a1, ux, fmaf(a2, fmaf(-ux, vr, dvx), a3 * fmaf(-ux, pu, mx)));
-    const float gy = fmaf(a1, uy, fmaf(a2, fmaf(-uy, vr, dvy), a3 * fmaf(-uy, pu, my)));
-    const float gz = fmaf(a1, uz, fmaf(a2, fmaf(-uz, vr, dvz), a3 * fmaf(-uz, pu, mz)));
-    lx.x -= gx;
-    lx.y -= gy;
-    lx.z -= gz;
+    gd.x = fmaf(a1, ux, fmaf(a2, fmaf(-ux, vr, dvx), a3 * fmaf(-ux, pu, mx)));
+    gd.y = fmaf(a1, uy, fmaf(a2, fmaf(-uy, vr, dvy), a3 * fmaf(-uy, pu, my)));
+    gd.z = fmaf(a1, uz, fmaf(a2, fmaf(-uz, vr, dvz), a3 * fmaf(-uz, pu, mz)));
     if (DAMP) {
+        // the damper's pull on v_i: (pu c) u
         const float b = pu * p.c;
-        lv.x = fmaf(-b, ux, lv.x);
-        lv.y = fmaf(-b, uy, lv.y);
-        lv.z = fmaf(-b, uz, lv.z);
+        bu = make_float3(b * ux, b * uy, b * uz);
     }
     gk = pu * e;
     if (ACT) {
         gC = -(a1 * L0 * sin_wt);
         gS = -(a1 * L0 * cos_wt);
+    }
+}
+
+// The same terms applied to mass i's adjoints (lx, lv) at once.
+template <bool ACT, bool DAMP, bool REST>
+__device__ __forceinline__ void spring_adjoint(const float4 &xi, const float4 &ui, const float4 &vi,
+                                               const float4 &xj, const float4 &uj, const float4 &vj,
+                                               const SpringConst &p, float sin_wt, float cos_wt,
+                                               const float4 &mi, const float4 &mj, float3 &lx, float3 &lv,
+                                               float &gk, float &gC, float &gS)
+{
+#pragma clang fp contract(off)
+    float3 gd, bu;
+    spring_adjoint_terms<ACT, DAMP, REST>(xi, ui, vi, xj, uj, vj, p, sin_wt, cos_wt, mi, mj, gd, bu, gk, gC, gS);
+    lx.x -= gd.x;
+    lx.y -= gd.y;
+    lx.z -= gd.z;
+    if (DAMP) {
+        lv.x -= bu.x;
+        lv.y -= bu.y;
+        lv.z -= bu.z;
     }
 }
 
@@ -137,7 +166,14 @@ __device__ __forceinline__ float4 mass_adjoint(const float4 &xi, const float4 &u
     return mu;
 }
 
-template <bool ACT, bool DAMP, bool DAMPV, bool REST, int T, int MAXM>
+// Springs-once loops: springs per thread whose loads are issued together,
+// and entries per batch of a mass's sum.
+constexpr int kOnceBatch = 4;
+constexpr int kSlotBatch = 8;
+
+// ONCE: the reverse steps evaluate every spring once (AdjointIO's spring
+// tables), else from both ends, slot by slot.
+template <bool ACT, bool DAMP, bool DAMPV, bool REST, int T, int MAXM, bool ONCE>
 __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b, AdjointIO a, StepConsts sc)
 {
     extern __shared__ float4 smem[];
@@ -146,13 +182,35 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
     float4 *sU = smem + cap;
     float4 *sV = smem + 2 * cap;
     float4 *sM = smem + 3 * cap;
+    // springs evaluated once: the reverse records (gd, bu.x) and (bu.y, bu.z)
+    // of a chunk of springs
+    float4 *sF = smem + 4 * cap;
+    float2 *sF2 = reinterpret_cast<float2 *>(sF + a.rev_chunk);
     const int64_t n = g.n;
     const int64_t m0 = b.mass_off[blockIdx.x];
     const int nm = (int)(b.mass_off[blockIdx.x + 1] - m0);
     const int tid = threadIdx.x;
     const int K = a.K;
+    constexpr bool once = ONCE;
+    const int64_t sp0 = once ? a.sp_off[blockIdx.x] : 0;
+    const int nsp = once ? (int)(a.sp_off[blockIdx.x + 1] - sp0) : 0;
 
     auto nbr = [&](int64_t e) { return (int)b.nbr_group[e]; };
+    // a group spring's constants, the same values load_const reads from its slots
+    auto pconst = [&](int64_t t) {
+        SpringConst p{};
+        const float4 q = a.sp_kcs[t];
+        p.k = q.x;
+        p.c = q.y;
+        p.act_c = q.z;
+        p.act_s = q.w;
+        if (REST) {
+            const float2 r = a.sp_rest[t];
+            p.d0 = r.x;
+            p.L0 = r.y;
+        }
+        return p;
+    };
     auto state = [&](int r, float4 &xj, float4 &uj, float4 &vj) {
         uj = sU[r];
         xj = sX[r];
@@ -172,8 +230,8 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
                 const float4 xi = sX[q], ui = sU[q], vi = sV[q];
                 float fx = 0.f, fy = 0.f, fz = 0.f;
                 sum_forces<ACT, DAMP, DAMPV, REST, false, false>(g, g.slice_off[i >> 6] + (i & 63),
-                                                                 slice_width(g, i), xi, ui, vi, Clock{tr, 0.0}, sc,
-                                                                 nbr, state, fx, fy, fz);
+                                                                 slice_width(g, i), xi, ui, vi,
+                                                                 Clock{tr, 0.0}, sc, nbr, state, fx, fy, fz);
                 if (fout)
                     fout[q] = make_float4(fx, fy, fz, 0.f);
                 ok &= integrate_mass(xi, ui, vi, fx, fy, fz, sc, nu[k], nv[k]);
@@ -309,6 +367,94 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
             if (r > 0)
                 fetch(r - 1);
             // spring pass
+            if constexpr (ONCE) {
+                // every spring once, in chunks of records that fit LDS: the
+                // owner end's terms and the parameter gradients, then each
+                // mass adds its springs' terms (the other end negated) in
+                // ascending spring order, resuming where the last chunk ended
+                int cw[MAXM];
+#pragma unroll
+                for (int k = 0; k < MAXM; ++k)
+                    cw[k] = 0;
+                for (int c0 = 0; c0 < nsp; c0 += a.rev_chunk) {
+                    const int c1 = min(nsp, c0 + a.rev_chunk);
+                    if (c0 > 0)
+                        __syncthreads();  // the previous chunk's records are read
+                    for (int t0 = c0 + tid; t0 < c1; t0 += kOnceBatch * T) {
+                        uint32_t rr[kOnceBatch];
+                        SpringConst p[kOnceBatch];
+                        float4 acc[kOnceBatch];
+#pragma unroll
+                        for (int u = 0; u < kOnceBatch; ++u) {
+                            const int t = min(t0 + u * T, c1 - 1);
+                            rr[u] = a.sp_ends[sp0 + t];
+                            p[u] = pconst(sp0 + t);
+                            acc[u] = a.gsp[sp0 + t];
+                        }
+#pragma unroll
+                        for (int u = 0; u < kOnceBatch; ++u) {
+                            const int t = t0 + u * T;
+                            if (t < c1) {
+                                const int qa = (int)(rr[u] & 0xffffu), qb = (int)(rr[u] >> 16);
+                                float3 gd, bu;
+                                float gk, gC, gS;
+                                spring_adjoint_terms<ACT, DAMP, REST>(
+                                    sX[qa], sU[qa], DAMP ? sV[qa] : make_float4(0.f, 0.f, 0.f, 0.f), sX[qb],
+                                    sU[qb], DAMP ? sV[qb] : make_float4(0.f, 0.f, 0.f, 0.f), p[u], tr.x, tr.y,
+                                    sM[qa], sM[qb], gd, bu, gk, gC, gS);
+                                sF[t - c0] = make_float4(gd.x, gd.y, gd.z, bu.x);
+                                if (DAMP)
+                                    sF2[t - c0] = make_float2(bu.y, bu.z);
+                                acc[u].x += gk;
+                                acc[u].y += gC;
+                                acc[u].z += gS;
+                                a.gsp[sp0 + t] = acc[u];
+                            }
+                        }
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int k = 0; k < MAXM; ++k) {
+                        const int q = tid + k * T;
+                        if (q < nm) {
+                            const int64_t i = m0 + q;
+                            const int64_t base = g.slice_off[i >> 6] + (i & 63);
+                            const int width = slice_width(g, i);
+                            // entries of kSlotBatch slots loaded at a time;
+                            // stop at a later chunk's entry or the list's end
+                            int w = cw[k];
+                            bool go = w < width;
+                            while (go) {
+                                int v[kSlotBatch];
+#pragma unroll
+                                for (int u = 0; u < kSlotBatch; ++u)
+                                    v[u] = a.rev_sp[base + (int64_t)min(w + u, width - 1) * kSlice];
+#pragma unroll
+                                for (int u = 0; u < kSlotBatch; ++u) {
+                                    go = go && w < width && (v[u] >> 1) < c1;
+                                    if (go) {
+                                        const int t = v[u] >> 1;
+                                        const unsigned sg = (unsigned)(~v[u]) << 31;  // negate at the owner end
+                                        const float4 r0 = sF[t - c0];
+                                        lx[k].x += __uint_as_float(__float_as_uint(r0.x) ^ sg);
+                                        lx[k].y += __uint_as_float(__float_as_uint(r0.y) ^ sg);
+                                        lx[k].z += __uint_as_float(__float_as_uint(r0.z) ^ sg);
+                                        if (DAMP) {
+                                            const float2 r1 = sF2[t - c0];
+                                            lv[k].x += __uint_as_float(__float_as_uint(r0.w) ^ sg);
+                                            lv[k].y += __uint_as_float(__float_as_uint(r1.x) ^ sg);
+                                            lv[k].z += __uint_as_float(__float_as_uint(r1.y) ^ sg);
+                                        }
+                                        ++w;
+                                    }
+                                }
+                            }
+                            cw[k] = w;
+                        }
+                    }
+                }
+                continue;
+            }
 #pragma unroll
             for (int k = 0; k < MAXM; ++k) {
                 const int q = tid + k * T;
@@ -365,12 +511,12 @@ __global__ __launch_bounds__(T) void adjoint_kernel(GatherGraph g, BatchLayout b
     }
 }
 
-template <bool ACT, bool DAMP, bool DAMPV, bool REST, int T, int MAXM>
+template <bool ACT, bool DAMP, bool DAMPV, bool REST, int T, int MAXM, bool ONCE>
 hipError_t launch_tm(const GatherGraph &g, const BatchLayout &b, const AdjointIO &a, const StepConsts &sc,
                      hipStream_t st)
 {
-    auto kern = adjoint_kernel<ACT, DAMP, DAMPV, REST, T, MAXM>;
-    const size_t lds = (size_t)b.max_group * 4 * sizeof(float4);
+    auto kern = adjoint_kernel<ACT, DAMP, DAMPV, REST, T, MAXM, ONCE>;
+    const size_t lds = (size_t)b.max_group * 4 * sizeof(float4) + (ONCE ? (size_t)a.once_bytes : 0);
     if (lds > 65536) {
         const hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  (int)lds);
@@ -391,15 +537,34 @@ hipError_t launch4(const GatherGraph &g, const BatchLayout &b, const AdjointIO &
                    hipStream_t st)
 {
     const int m = b.max_group;
+    const bool once = a.sp_ends != nullptr;
     if (m <= 256)
-        return launch_tm<ACT, DAMP, DAMPV, REST, 256, 1>(g, b, a, sc, st);
+        return once ? launch_tm<ACT, DAMP, DAMPV, REST, 256, 1, true>(g, b, a, sc, st)
+                    : launch_tm<ACT, DAMP, DAMPV, REST, 256, 1, false>(g, b, a, sc, st);
     if (m <= 512)
-        return launch_tm<ACT, DAMP, DAMPV, REST, 512, 1>(g, b, a, sc, st);
+        return once ? launch_tm<ACT, DAMP, DAMPV, REST, 512, 1, true>(g, b, a, sc, st)
+                    : launch_tm<ACT, DAMP, DAMPV, REST, 512, 1, false>(g, b, a, sc, st);
     if (m <= 1024)
-        return launch_tm<ACT, DAMP, DAMPV, REST, 1024, 1>(g, b, a, sc, st);
-    if (m <= 2048)
-        return launch_tm<ACT, DAMP, DAMPV, REST, 1024, 2>(g, b, a, sc, st);
+        return once ? launch_tm<ACT, DAMP, DAMPV, REST, 1024, 1, true>(g, b, a, sc, st)
+                    : launch_tm<ACT, DAMP, DAMPV, REST, 1024, 1, false>(g, b, a, sc, st);
+    // springs once needs groups of at most 1024 masses
+    if (m <= 2048 && !once)
+        return launch_tm<ACT, DAMP, DAMPV, REST, 1024, 2, false>(g, b, a, sc, st);
     return hipErrorInvalidValue;
+}
+
+// The spring-once tables' constants, one group per workgroup, as load_const
+// reads them from each spring's owner slot.
+__global__ void pack_spring_consts(GatherGraph g, const int64_t *sp_slot, const int64_t *sp_off, float4 *kcs,
+                                   float2 *rest)
+{
+    for (int64_t t = sp_off[blockIdx.x] + threadIdx.x; t < sp_off[blockIdx.x + 1]; t += blockDim.x) {
+        const int64_t e = sp_slot[t];
+        kcs[t] = make_float4(g.k ? g.k[e] : g.k_uniform, g.c ? g.c[e] : g.c_uniform, g.act_c ? g.act_c[e] : 0.f,
+                             g.act_c ? g.act_s[e] : 0.f);
+        if (rest)
+            rest[t] = make_float2(g.d0[e], g.rest[e]);
+    }
 }
 
 __global__ void gather_spring_grads(const float4 *gslot, const int64_t *owner_slot, int64_t ns, float *gk, float *gC,
@@ -488,6 +653,18 @@ hipError_t launch_adjoint(const GatherGraph &g, const BatchLayout &b, const Adjo
     case 15: return launch4<true, true, true, true>(g, b, a, sc, stream);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_pack_spring_consts(const GatherGraph &g, const BatchLayout &b, const int64_t *sp_slot,
+                                     const int64_t *sp_off, float4 *kcs, float2 *rest, hipStream_t stream)
+{
+    if (b.n_groups == 0)
+        return hipSuccess;
+    if (rest && !g.d0)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pack_spring_consts, dim3((unsigned)b.n_groups), dim3(256), 0, stream, g, sp_slot, sp_off,
+                       kcs, rest);
+    return hipGetLastError();
 }
 
 hipError_t launch_spring_grads(const float4 *gslot, const int64_t *owner_slot, int64_t ns, float *gk, float *gC,

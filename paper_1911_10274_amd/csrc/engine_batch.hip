@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <utility>
 #include <vector>
@@ -498,6 +500,113 @@ void destroy_batch_engine(titan_sim *s)
     s->batch = nullptr;
 }
 
+// LDS of one workgroup (gfx950: 160 KB).
+constexpr int64_t kLdsBytes = 160 * 1024;
+
+// The spring-once tables of the current layout, built when the slots or the
+// groups changed since the last call: each group's springs (owner mass, then
+// owner slot, ascending), their ends and owner slots, and per slot the
+// reverse sums' entries (see AdjointIO).
+static int once_tables(titan_sim *s)
+{
+    SpringOnceTables &o = s->once;
+    const std::vector<int64_t> &goff = s->h_group_off;
+    if (o.gen == s->slot_gen && o.goff == goff)
+        return TITAN_OK;
+    for (void *p : {(void *)o.ends, (void *)o.slot, (void *)o.off, (void *)o.rev_sp, (void *)o.of_spring})
+        if (p)
+            dev_free(s, p);
+    o = SpringOnceTables{};
+    const int64_t n = s->n, ns = s->ns;
+    const std::vector<int64_t> &off = s->h_slice_off;
+    const int64_t ng = (int64_t)goff.size() - 1;
+    o.gen = s->slot_gen;
+    o.goff = goff;
+    if (ng < 1 || (int64_t)off.size() != s->gg.n_slices + 1 || (int64_t)s->h_owner_slot.size() < ns)
+        return TITAN_OK;  // no usable layout: the per-slot path
+    const int64_t nslots = off.back();
+    std::vector<int32_t> group(n);
+    for (int64_t q = 0; q < ng; ++q)
+        for (int64_t i = goff[q]; i < goff[q + 1]; ++i)
+            group[i] = (int32_t)q;
+    // (owner mass, owner slot, other mass, caller spring) per group
+    struct Rec {
+        int64_t io, eo, ix, q;
+    };
+    std::vector<std::vector<Rec>> per(ng);
+    for (int64_t q = 0; q < ns; ++q) {
+        const int64_t eo = s->h_owner_slot[q];
+        if (eo < 0 || s->h_other_slot[q] < 0)
+            continue;
+        const int64_t a = s->inv_perm_of(s->h_ends[2 * q]), b = s->inv_perm_of(s->h_ends[2 * q + 1]);
+        const int64_t io = std::min(a, b), ix = std::max(a, b);
+        if (group[io] != group[ix])
+            return fail(TITAN_EINVAL, "internal: a spring leaves its body group");
+        per[group[io]].push_back({io, eo, ix, q});
+    }
+    std::vector<int64_t> sp_off(ng + 1, 0);
+    int sp_max = 0;
+    for (int64_t g = 0; g < ng; ++g) {
+        std::sort(per[g].begin(), per[g].end(),
+                  [](const Rec &x, const Rec &y) { return x.io != y.io ? x.io < y.io : x.eo < y.eo; });
+        sp_off[g + 1] = sp_off[g] + (int64_t)per[g].size();
+        sp_max = std::max<int>(sp_max, (int)per[g].size());
+    }
+    const int64_t nsp = sp_off[ng];
+    if (nsp == 0)
+        return TITAN_OK;
+    std::vector<uint32_t> ends(nsp);
+    std::vector<int64_t> slot(nsp), of(ns, -1);
+    std::vector<int32_t> rev_sp(nslots, INT32_MAX);
+    // each mass's entries: springs are in owner order, so a mass's entries
+    // as owner come in ascending order; merged with its other-end entries
+    std::vector<std::vector<int32_t>> ent;
+    for (int64_t g = 0; g < ng; ++g) {
+        const int64_t m = goff[g + 1] - goff[g];
+        ent.assign(m, {});
+        for (int64_t t = 0; t < (int64_t)per[g].size(); ++t) {
+            const Rec &r = per[g][t];
+            const int64_t u = sp_off[g] + t;
+            ends[u] = (uint32_t)(r.io - goff[g]) | ((uint32_t)(r.ix - goff[g]) << 16);
+            slot[u] = r.eo;
+            of[r.q] = u;
+            ent[r.io - goff[g]].push_back((int32_t)(2 * t));
+            ent[r.ix - goff[g]].push_back((int32_t)(2 * t + 1));
+        }
+        for (int64_t i = goff[g]; i < goff[g + 1]; ++i) {
+            std::vector<int32_t> &v = ent[i - goff[g]];
+            std::sort(v.begin(), v.end());
+            const int64_t sl = i / kSlice, base = off[sl] + (i % kSlice), width = (off[sl + 1] - off[sl]) / kSlice;
+            if ((int64_t)v.size() > width)
+                return fail(TITAN_EINVAL, "internal: a mass has more springs than slots");
+            for (size_t w = 0; w < v.size(); ++w)
+                rev_sp[base + (int64_t)w * kSlice] = v[w];
+        }
+    }
+    int rc = TITAN_OK;
+    if ((rc = dev_alloc(s, sizeof(uint32_t) * nsp, (void **)&o.ends)) ||
+        (rc = dev_alloc(s, sizeof(int64_t) * nsp, (void **)&o.slot)) ||
+        (rc = dev_alloc(s, sizeof(int64_t) * (ng + 1), (void **)&o.off)) ||
+        (rc = dev_alloc(s, sizeof(int32_t) * std::max<int64_t>(nslots, 1), (void **)&o.rev_sp)) ||
+        (rc = dev_alloc(s, sizeof(int64_t) * std::max<int64_t>(ns, 1), (void **)&o.of_spring))) {
+        o.gen = 0;  // built again next time
+        return rc;
+    }
+    HIP_TRY(s, hipMemcpyAsync(o.ends, ends.data(), sizeof(uint32_t) * nsp, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(o.slot, slot.data(), sizeof(int64_t) * nsp, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(o.off, sp_off.data(), sizeof(int64_t) * (ng + 1), hipMemcpyHostToDevice, s->stream));
+    if (nslots)
+        HIP_TRY(s, hipMemcpyAsync(o.rev_sp, rev_sp.data(), sizeof(int32_t) * nslots, hipMemcpyHostToDevice,
+                                  s->stream));
+    if (ns)
+        HIP_TRY(s, hipMemcpyAsync(o.of_spring, of.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, s->stream));
+    // the host tables go away with this call
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    o.nsp = nsp;
+    o.sp_max = sp_max;
+    return TITAN_OK;
+}
+
 // Adjoint rollout on the batched layout (see adjoint_step.hip).
 int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weights, float *loss, float *gk,
                  float *gC, float *gS, float *gvox_a, float *gvox_phi, bool dev_out)
@@ -593,12 +702,39 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
         HIP_TRY(s, hipMemcpy(last.data(), s->gg.slice_off + s->gg.n_slices, sizeof(int64_t), hipMemcpyDeviceToHost));
         nslots = last[0];
     }
+    // the reverse steps evaluate every spring once when the groups allow it
+    // (the environment variable TITAN_ADJOINT_SPRING_ONCE=0 selects the
+    // per-slot path)
+    const char *once_env = std::getenv("TITAN_ADJOINT_SPRING_ONCE");
+    const bool want_once = !(once_env && once_env[0] == '0');
     int rc = TITAN_OK;
+    if (want_once && (rc = once_tables(s)))
+        return rc;
+    const SpringOnceTables &o = s->once;
+    const int64_t avail = kLdsBytes - 4 * 16 * (int64_t)s->batch->lay.max_group;
+    const bool once = want_once && o.nsp > 0 && s->batch->lay.max_group <= 1024 && avail / 24 >= 64;
+    const bool rest = s->gg.d0 != nullptr;
+    float4 *kcs = nullptr;
+    float2 *rst = nullptr;
+    if (once) {
+        a.rev_chunk = (int)std::min<int64_t>(o.sp_max, avail / 24);
+        a.once_bytes = 24 * a.rev_chunk;
+        if ((rc = get(sizeof(float4) * o.nsp, (void **)&a.gsp)) || (rc = get(sizeof(float4) * o.nsp, (void **)&kcs)) ||
+            (rest && (rc = get(sizeof(float2) * o.nsp, (void **)&rst)))) {
+            cleanup();
+            return rc;
+        }
+        a.sp_ends = o.ends;
+        a.sp_kcs = kcs;
+        a.sp_rest = rst;
+        a.sp_off = o.off;
+        a.rev_sp = o.rev_sp;
+    }
     if ((rc = get(sizeof(float4) * n * std::max<int64_t>(nseg, 1), (void **)&a.ckU)) ||
         (rc = get(sizeof(float4) * n * std::max<int64_t>(nseg, 1), (void **)&a.ckV)) ||
         (rc = get(sizeof(float4) * n * K, (void **)&a.segU)) || (rc = get(sizeof(float4) * n * K, (void **)&a.segV)) ||
         (rc = get(sizeof(float4) * n * K, (void **)&a.segF)) ||
-        (rc = get(sizeof(float4) * std::max<int64_t>(nslots, 1), (void **)&a.gslot)) ||
+        (rc = get(sizeof(float4) * (once ? 1 : std::max<int64_t>(nslots, 1)), (void **)&a.gslot)) ||
         (rc = get(sizeof(float) * n, (void **)&dseed)) || (rc = get(sizeof(float) * n, (void **)&dcoef)) ||
         (rc = get(sizeof(float) * n, (void **)&a.dux)) || (rc = get(sizeof(float) * nruns, (void **)&dloss)) ||
         (rc = get(sizeof(float) * 3 * ns, (void **)&dgrad)) || (rc = get(sizeof(int64_t) * (nruns + 1), (void **)&dboff)) ||
@@ -621,7 +757,7 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
     TRY(hipMemcpyAsync(dboff, body_off.data(), sizeof(int64_t) * (nruns + 1), hipMemcpyHostToDevice, s->stream));
     // the owner slots stay on the device between calls (sent again only
     // after the layout or the spring set changed)
-    if (s->owner_dev_stale || s->d_owner_cap < ns) {
+    if (!once && (s->d_owner_gen != s->slot_gen || s->d_owner_cap < ns)) {
         if (s->d_owner_cap < ns) {
             if (s->d_owner_slot)
                 dev_free(s, s->d_owner_slot);
@@ -636,10 +772,15 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
         if (ns)
             TRY(hipMemcpyAsync(s->d_owner_slot, s->h_owner_slot.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice,
                                s->stream));
-        s->owner_dev_stale = false;
+        s->d_owner_gen = s->slot_gen;
     }
     TRY(hipMemcpyAsync(dbad, &none, sizeof none, hipMemcpyHostToDevice, s->stream));
-    TRY(hipMemsetAsync(a.gslot, 0, sizeof(float4) * std::max<int64_t>(nslots, 1), s->stream));
+    if (once) {
+        TRY(hipMemsetAsync(a.gsp, 0, sizeof(float4) * o.nsp, s->stream));
+        TRY(launch_pack_spring_consts(s->gg, s->batch->lay, o.slot, o.off, kcs, rst, s->stream));
+    } else {
+        TRY(hipMemsetAsync(a.gslot, 0, sizeof(float4) * std::max<int64_t>(nslots, 1), s->stream));
+    }
     TRY(launch_trig_table(dtrig, s->step_enq, (int)nsteps, s->params.omega, s->params.dt, s->stream));
     a.U0 = s->U[s->cur];
     a.V0 = s->V[s->cur];
@@ -650,7 +791,10 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
     a.K = K;
     const StepConsts sc = consts_for(s, s->step_enq, dtrig);
     TRY(launch_adjoint(s->gg, s->batch->lay, a, sc, s->stream));
-    TRY(launch_spring_grads(a.gslot, s->d_owner_slot, ns, dgrad, dgrad + ns, dgrad + 2 * ns, s->stream));
+    if (once)
+        TRY(launch_spring_grads(a.gsp, o.of_spring, ns, dgrad, dgrad + ns, dgrad + 2 * ns, s->stream));
+    else
+        TRY(launch_spring_grads(a.gslot, s->d_owner_slot, ns, dgrad, dgrad + ns, dgrad + 2 * ns, s->stream));
     TRY(launch_body_loss(a.dux, dcoef, dboff, nruns, dloss, s->stream));
     // per-voxel gradients through the mean-phasor map, on the device: each
     // voxel sums over its springs (ascending) the spring's (dJ/dC, dJ/dS)

@@ -406,7 +406,7 @@ static void plan_gather(titan_sim *s, bool allow_tiled, GatherPlan &P)
     }
     s->h_owner_slot.assign(ns, -1);
     s->h_other_slot.assign(ns, -1);
-    s->owner_dev_stale = true;
+    ++s->slot_gen;
     for (int64_t i = 0; i < n; ++i) {
         const int64_t base = off[i / kSlice] + (i % kSlice);
         const int64_t t = i / kTile, a = t * kTile;
@@ -1172,7 +1172,7 @@ int insert_springs(titan_sim *s, int64_t first, int64_t count)
             else
                 s->h_other_slot[p.q] = p.e;
         }
-        s->owner_dev_stale = true;
+        ++s->slot_gen;
         // the device copy of the row degrees: indexed by row, not by slot
         // (slot holds m >= the number of rows)
         for (int64_t e = 0; e < m; ++e)

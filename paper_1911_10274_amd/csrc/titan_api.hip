@@ -388,7 +388,7 @@ extern "C" int titan_add_springs(titan_sim *s, int64_t n, const int64_t *ends, c
         s->ns = (int64_t)s->h_k.size();
         s->h_owner_slot.resize(s->ns, -1);
         s->h_other_slot.resize(s->ns, -1);
-        s->owner_dev_stale = true;
+        ++s->slot_gen;
         // into spare slots of the current layouts if they all fit (O(1) per
         // spring), else the layouts are rebuilt before the next step, with
         // more spare slots

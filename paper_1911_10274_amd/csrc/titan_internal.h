@@ -193,11 +193,35 @@ struct AdjointIO {
     const float2 *trig;       // clock entries of rollout steps 0 .. nsteps-1
     unsigned long long *first_bad;
     int nsteps, K;
+    // Reverse steps with every spring evaluated once (groups of at most 1024
+    // masses; else sp_ends is null): group g's springs are
+    // [sp_off[g], sp_off[g+1]), each with its ends (owner end, the lower
+    // internal index, in the low 16 bits; group-local) and its constants
+    // (k, c, C, S) and (d0, L0).  Per slot, rev_sp holds a mass's entries in
+    // ascending order -- 2 * (the spring within its group), + 1 at the
+    // spring's other end -- then INT32_MAX.  gsp: each spring's running
+    // (dk, dC, dS).
+    const uint32_t *sp_ends;
+    const float4 *sp_kcs;
+    const float2 *sp_rest;
+    const int64_t *sp_off;
+    const int32_t *rev_sp;
+    float4 *gsp;
+    int rev_chunk;   // records per chunk
+    int once_bytes;  // LDS for the records beyond the state
 };
+
+// Per group spring t (AdjointIO's tables): kcs[t] = (k, c, C, S) and
+// rest[t] = (d0, L0) (explicit rest lengths only; rest may be null otherwise)
+// as load_const reads them from the owner slot sp_slot[t].
+hipError_t launch_pack_spring_consts(const GatherGraph &g, const BatchLayout &b, const int64_t *sp_slot,
+                                     const int64_t *sp_off, float4 *kcs, float2 *rest, hipStream_t stream);
 
 hipError_t launch_adjoint(const GatherGraph &g, const BatchLayout &b, const AdjointIO &a, const StepConsts &sc,
                           hipStream_t stream);
-// gk[s] = gslot[owner_slot[s]].x etc. (caller spring order)
+// gk[s] = gslot[owner_slot[s]].x etc. (caller spring order; owner_slot < 0:
+// no gradient).  The spring-once path passes its per-spring array and each
+// spring's index in it.
 hipError_t launch_spring_grads(const float4 *gslot, const int64_t *owner_slot, int64_t ns, float *gk, float *gC,
                                float *gS, hipStream_t stream);
 // loss[b] = -sum over internal masses [body_off[b], body_off[b+1]) of coef * dux

@@ -27,6 +27,20 @@ struct BP {
     float4 *snapV = nullptr;
 };
 
+// The rollout gradient's spring-once tables (see AdjointIO), kept between
+// calls for slot generation `gen` and the group offsets `goff`.
+struct SpringOnceTables {
+    uint64_t gen = 0;
+    std::vector<int64_t> goff;
+    int64_t nsp = 0;  // springs over all groups (0: no tables)
+    int sp_max = 0;   // most springs in one group
+    uint32_t *ends = nullptr;
+    int64_t *slot = nullptr;       // each group spring's owner slot
+    int64_t *off = nullptr;        // [groups + 1]
+    int32_t *rev_sp = nullptr;     // [slots]
+    int64_t *of_spring = nullptr;  // caller spring -> group spring (-1: no slot)
+};
+
 struct BatchEngine;  // defined by the batched engine
 struct GatherPlan;   // host tables of the gather layout (engine_gather.hip)
 
@@ -87,11 +101,15 @@ struct titan_sim {
     std::vector<int32_t> h_slot_nbr;  // per-slot neighbour (internal), kept only during finalize
     std::vector<int64_t> h_owner_slot;  // per spring (caller order): its slot at the lower-index end
     std::vector<int64_t> h_other_slot;  // per spring: its slot at the other end
+    // bumped whenever springs get slots (layout built, springs inserted):
+    // what the rollout gradient keeps between calls is rebuilt after that
+    uint64_t slot_gen = 1;
     // device copy of h_owner_slot for the rollout gradient, kept between
-    // calls; stale after any change to h_owner_slot
+    // calls (valid for slot generation d_owner_gen)
     int64_t *d_owner_slot = nullptr;
     int64_t d_owner_cap = 0;
-    bool owner_dev_stale = true;
+    uint64_t d_owner_gen = 0;
+    titan::SpringOnceTables once;
     float2 *trig = nullptr;           // clock table: kTrigChunk entries + 1 for force queries
     std::shared_ptr<titan::GatherPlan> gplan;  // planned before the device was set up; used once
 

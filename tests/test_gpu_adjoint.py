@@ -316,3 +316,26 @@ def test_device_outputs_equal_host_outputs_bit_for_bit():
     sim.rollout_grad_device(0, 5, out=outs)
     assert all(bool((t == 0).all()) for t in outs)
     sim.close()
+
+
+@pytest.mark.parametrize("seed,lo,hi,count", [
+    (16, 3, 5, 12),   # small robots packed several to a group
+    (17, 4, 8, 8),    # the adjoint workload's sizes
+    (41, 7, 7, 1),    # one 445-mass body: 512-thread groups
+    (42, 9, 9, 1),    # one 934-mass body: 1024-thread groups, records in chunks
+])
+def test_adjoint_springs_once_equals_per_slot(seed, lo, hi, count, monkeypatch):
+    """Reverse steps with every spring evaluated once (records shared through
+    LDS, the default) against each end evaluating every spring itself
+    (TITAN_ADJOINT_SPRING_ONCE=0): the same forward rollout (the loss, bit for
+    bit); the reverse sums run in another order (each element within 1e-5 of
+    the largest gradient)."""
+    robots = scenes.robot_batch(count, seed=seed, side_lo=lo, side_hi=hi)
+    sc = scenes.concat(robots)
+    monkeypatch.setenv("TITAN_ADJOINT_SPRING_ONCE", "0")
+    slot, _ = _gpu_grad(sc, 300, 50)
+    monkeypatch.delenv("TITAN_ADJOINT_SPRING_ONCE")
+    once, _ = _gpu_grad(sc, 300, 50)
+    assert np.array_equal(slot[0], once[0])
+    for a, b in zip(slot[1:], once[1:]):
+        assert np.abs(a - b).max() <= 1e-5 * np.abs(a).max()
