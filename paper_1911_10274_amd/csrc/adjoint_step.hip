@@ -529,9 +529,10 @@ hipError_t launch_tm(const GatherGraph &g, const BatchLayout &b, const AdjointIO
 
 // One mass per thread while a group fits 1024 threads: the reverse step is
 // a chain of LDS reads and workgroup barriers, so the more waves a CU holds
-// the more of that latency is hidden (85 VGPRs at one mass per thread, 143
-// at four; 1024 threads allow 128).  Groups up to 2048 masses take two masses
-// per thread (104 VGPRs).
+// the more of that latency is hidden (1024 threads allow 128 VGPRs; the
+// actuated, damped kernels take 116-120 at one mass per thread).  Groups up
+// to 2048 masses take two masses per thread (125 VGPRs) and the per-slot
+// reverse steps.
 template <bool ACT, bool DAMP, bool DAMPV, bool REST>
 hipError_t launch4(const GatherGraph &g, const BatchLayout &b, const AdjointIO &a, const StepConsts &sc,
                    hipStream_t st)
