@@ -339,3 +339,40 @@ def test_adjoint_springs_once_equals_per_slot(seed, lo, hi, count, monkeypatch):
     assert np.array_equal(slot[0], once[0])
     for a, b in zip(slot[1:], once[1:]):
         assert np.abs(a - b).max() <= 1e-5 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("once", ["0", "1"])
+@pytest.mark.parametrize("variant", ["rest_damping", "plain"])
+def test_adjoint_spring_constant_variants_match_oracle(variant, once, monkeypatch):
+    """The kernel variants beyond the robots' own constants, on both reverse
+    paths (TITAN_ADJOINT_SPRING_ONCE): explicit rest lengths with per-spring
+    damping (actuated), and springs with neither actuation nor damping (the
+    robots thrown sideways so the loss moves); against the FP64 adjoint."""
+    from paper_1911_10274_amd import titan as T
+
+    robots = scenes.robot_batch(6, seed=18, side_lo=3, side_hi=6)
+    sc = scenes.concat(robots)
+    rng = np.random.Generator(np.random.PCG64(19))
+    ns, nm = sc["ends"].shape[0], sc["pos"].shape[0]
+    rest = None
+    if variant == "rest_damping":
+        d = sc["pos"][sc["ends"][:, 1]].astype(np.float64) - sc["pos"][sc["ends"][:, 0]]
+        rest = (np.linalg.norm(d, axis=1) * rng.uniform(0.97, 1.03, ns)).astype(np.float32)
+        sc = dict(sc, damping=rng.uniform(0.5, 1.5, ns).astype(np.float32))
+    else:
+        vel = rng.uniform(-0.2, 0.2, (nm, 3)) + np.array([0.5, 0.0, 0.0])
+        sc = dict(sc, amp=None, phase=None, damping=np.zeros(ns, np.float32), vel=vel.astype(np.float32))
+    monkeypatch.setenv("TITAN_ADJOINT_SPRING_ONCE", once)
+    sim = T.sim_from_scene(sc, _tp(), rest=rest)
+    loss, gk, gC, gS = sim.rollout_grad(300, 50)
+    sim.close()
+    ref = O.System(sc, rest=rest).rollout_grad(OP, 300, body=sc["body"])
+    pairs = [("k", gk, ref["gk"])]
+    if variant == "rest_damping":
+        pairs += [("C", gC, ref["gC"]), ("S", gS, ref["gS"])]
+    for name, g, r in pairs:
+        e = np.linalg.norm(g - r) / np.linalg.norm(r)
+        c = _cos(g.astype(np.float64), r)
+        print(variant, once, name, "rel", e, "cos", c)
+        assert e <= 1e-3 and c >= 0.9999
+    np.testing.assert_allclose(loss, ref["loss"], rtol=1e-3)
