@@ -707,12 +707,14 @@ int rollout_grad(titan_sim *s, int64_t nsteps, int32_t K, const float *body_weig
     // per-slot path)
     const char *once_env = std::getenv("TITAN_ADJOINT_SPRING_ONCE");
     const bool want_once = !(once_env && once_env[0] == '0');
+    // (groups of at most 1024 masses, with room for at least 64 records)
+    const int64_t avail = kLdsBytes - 4 * 16 * (int64_t)s->batch->lay.max_group;
+    const bool eligible = want_once && s->batch->lay.max_group <= 1024 && avail / 24 >= 64;
     int rc = TITAN_OK;
-    if (want_once && (rc = once_tables(s)))
+    if (eligible && (rc = once_tables(s)))
         return rc;
     const SpringOnceTables &o = s->once;
-    const int64_t avail = kLdsBytes - 4 * 16 * (int64_t)s->batch->lay.max_group;
-    const bool once = want_once && o.nsp > 0 && s->batch->lay.max_group <= 1024 && avail / 24 >= 64;
+    const bool once = eligible && o.nsp > 0;
     const bool rest = s->gg.d0 != nullptr;
     float4 *kcs = nullptr;
     float2 *rst = nullptr;
