@@ -167,9 +167,18 @@ __device__ __forceinline__ float4 mass_adjoint(const float4 &xi, const float4 &u
 }
 
 // Springs-once loops: springs per thread whose loads are issued together,
-// and entries per batch of a mass's sum.
-constexpr int kOnceBatch = 4;
-constexpr int kSlotBatch = 8;
+// and entries per batch of a mass's sum (tuning builds may set them; on the
+// 256-robot gradient 1, 2 and 3 springs measured within 1% of each other and
+// 1.5-2% faster than 4, 8 springs 17% slower; 4 and 16 entries 1-3% slower
+// than 8).
+#ifndef TITAN_ADJ_ONCE_BATCH
+#define TITAN_ADJ_ONCE_BATCH 2
+#endif
+#ifndef TITAN_ADJ_SLOT_BATCH
+#define TITAN_ADJ_SLOT_BATCH 8
+#endif
+constexpr int kOnceBatch = TITAN_ADJ_ONCE_BATCH;
+constexpr int kSlotBatch = TITAN_ADJ_SLOT_BATCH;
 
 // ONCE: the reverse steps evaluate every spring once (AdjointIO's spring
 // tables), else from both ends, slot by slot.
