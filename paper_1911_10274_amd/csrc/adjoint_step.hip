@@ -646,6 +646,14 @@ hipError_t launch_adjoint(const GatherGraph &g, const BatchLayout &b, const Adjo
     if (b.n_groups == 0 || a.nsteps <= 0)
         return hipSuccess;
     const bool act = g.act_c != nullptr, dampv = g.c != nullptr, rest = g.d0 != nullptr;
+    // every buffer the chosen path reads or writes must be there
+    if (!a.U0 || !a.V0 || !a.ckU || !a.ckV || !a.segU || !a.segV || !a.segF || !a.seed || !a.dux || !a.trig ||
+        !a.first_bad || a.K < 1)
+        return hipErrorInvalidValue;
+    if (a.sp_ends ? (!a.sp_kcs || !a.sp_off || !a.rev_sp || !a.gsp || (rest && !a.sp_rest) || a.rev_chunk < 1 ||
+                     a.once_bytes < 24 * a.rev_chunk)
+                  : !a.gslot)
+        return hipErrorInvalidValue;
     const bool damp = dampv || g.c_uniform != 0.f;
     const int key = (act ? 8 : 0) | (damp ? 4 : 0) | (dampv ? 2 : 0) | (rest ? 1 : 0);
     switch (key) {
