@@ -410,7 +410,15 @@ int titan_set_voxel_actuation(titan_sim *sim, int64_t n_voxels, const float *vox
  * rest (1 + C sin(omega t) + S cos(omega t))).  Needs every body to fit the
  * batched engine's layout (TITAN_ESTATE otherwise); TITAN_ENONFINITE if the
  * rollout blows up.  Differentiates the step exactly as computed, contact
- * and friction included (their switches are not smoothed). */
+ * and friction included (their switches are not smoothed).  When the
+ * largest group of the batched layout holds at most 1024 masses, the
+ * reverse steps evaluate each spring once and share its terms between its
+ * two ends (the forward states are those of every engine, bit for bit; the
+ * gradients differ from each end's own evaluation only by the order of the
+ * sums); the tables for this (about 20 bytes per spring and 4 per incidence
+ * slot) stay allocated between calls until the springs or the layout
+ * change.  Setting the environment variable TITAN_ADJOINT_SPRING_ONCE=0
+ * selects the per-slot evaluation. */
 int titan_rollout_grad(titan_sim *sim, int64_t nsteps, int32_t checkpoint_every, const float *body_weights,
                        float *loss_out, float *grad_k, float *grad_act_c, float *grad_act_s);
 
