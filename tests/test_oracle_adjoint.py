@@ -130,3 +130,79 @@ def test_adjoint_body_weights_are_linear():
     # the per-body losses agree with the forward-only rollout
     l, _ = sysm.rollout_loss(P, N, body=sc["body"])
     np.testing.assert_allclose(g1["loss"], l, rtol=0, atol=1e-15)
+
+
+def _variant_scene(variant, seed):
+    """One small robot with the constants the library's kernel variants take:
+    explicit rest lengths (+-3% of the initial lengths) with per-spring
+    damping, actuated; or no actuation and no damping, thrown sideways."""
+    r = scenes.robot_batch(1, seed=seed, side_lo=3, side_hi=4)[0]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ns, nm = r["ends"].shape[0], r["pos"].shape[0]
+    if variant == "rest_damping":
+        d = r["pos"][r["ends"][:, 1]].astype(np.float64) - r["pos"][r["ends"][:, 0]]
+        rest = np.linalg.norm(d, axis=1) * rng.uniform(0.97, 1.03, ns)
+        return dict(r, damping=rng.uniform(0.5, 1.5, ns)), rest
+    vel = rng.uniform(-0.2, 0.2, (nm, 3)) + np.array([0.5, 0.0, 0.0])
+    return dict(r, amp=None, phase=None, damping=np.zeros(ns), vel=vel), None
+
+
+@pytest.mark.parametrize("variant", ["rest_damping", "plain"])
+def test_adjoint_matches_central_fd_on_constant_variants(variant):
+    # dJ/dk of the largest springs, and (actuated) dJ/d(amp) and dJ/d(phase)
+    # of the springs with the largest phasor gradients, which combine the
+    # gradients in C = amp cos(phase) and S = amp sin(phase) two independent
+    # ways; runs whose +-h rollouts change a contact or stick decision are
+    # skipped (and counted)
+    sc, rest = _variant_scene(variant, 23)
+    N, h = 300, 1e-6
+    sysm = O.System(sc, rest=rest)
+    g = sysm.rollout_grad(P, N)
+    base = g["sig"]
+    checked = skipped = 0
+
+    def loss(mod):
+        s2 = O.System(sc, rest=rest)
+        mod(s2)
+        l, sig = s2.rollout_loss(P, N)
+        return l[0], sig
+
+    def fd_check(mod_plus, mod_minus, step, want, scale):
+        nonlocal checked, skipped
+        (lp, sp), (lm, sm) = loss(mod_plus), loss(mod_minus)
+        if sp != base or sm != base:
+            skipped += 1
+            return
+        checked += 1
+        fd = (lp - lm) / (2 * step)
+        assert abs(fd - want) <= 1e-5 * scale, (fd, want)
+
+    kscale = np.abs(g["gk"]).max()
+    for s in np.argsort(-np.abs(g["gk"]))[:8]:
+        dk = h * sysm.k[s]
+
+        def mk(sgn, s=s, dk=dk):
+            def mod(s2):
+                s2.k = s2.k.copy()
+                s2.k[s] += sgn * dk
+            return mod
+        fd_check(mk(+1), mk(-1), dk, g["gk"][s], kscale)
+    if variant == "rest_damping":
+        amp, ph = sysm.amp, sysm.phase
+        ga = g["gC"] * np.cos(ph) + g["gS"] * np.sin(ph)
+        gp = amp * (g["gS"] * np.cos(ph) - g["gC"] * np.sin(ph))
+        for which, grad in (("amp", ga), ("phase", gp)):
+            scale = np.abs(grad).max()
+            for s in np.argsort(-np.abs(grad))[:8]:
+                def mk(sgn, s=s, which=which):
+                    def mod(s2):
+                        arr = (s2.amp if which == "amp" else s2.phase).copy()
+                        arr[s] += sgn * h
+                        if which == "amp":
+                            s2.amp = arr
+                        else:
+                            s2.phase = arr
+                    return mod
+                fd_check(mk(+1), mk(-1), h, grad[s], scale)
+    print(variant, "checked", checked, "skipped", skipped)
+    assert checked >= (20 if variant == "rest_damping" else 6) and skipped <= checked // 4
