@@ -376,3 +376,59 @@ def test_adjoint_spring_constant_variants_match_oracle(variant, once, monkeypatc
         print(variant, once, name, "rel", e, "cos", c)
         assert e <= 1e-3 and c >= 0.9999
     np.testing.assert_allclose(loss, ref["loss"], rtol=1e-3)
+
+
+def test_adjoint_after_topology_edits_matches_oracle():
+    """One sim's rollout gradient across topology edits -- springs removed
+    (tombstones), then springs added twice within a body (a layout rebuild
+    with spare slots, then insertion in place) -- each time against the FP64
+    adjoint of the edited system: the spring tables the gradient keeps
+    between calls follow every change of the slots."""
+    from paper_1911_10274_amd import titan as T
+
+    robots = scenes.robot_batch(4, seed=31, side_lo=3, side_hi=5)
+    sc = scenes.concat(robots)
+    rng = np.random.Generator(np.random.PCG64(31))
+    ns0 = sc["ends"].shape[0]
+    pos, body = sc["pos"], sc["body"]
+    b0 = np.flatnonzero(body == 0)
+    existing = set(map(tuple, np.sort(sc["ends"], axis=1).tolist()))
+
+    def new_pairs(count):
+        out = []
+        while len(out) < count:
+            a, b = sorted(int(x) for x in rng.choice(b0, 2, replace=False))
+            if (a, b) in existing or np.linalg.norm(pos[a].astype(np.float64) - pos[b]) > 0.35:
+                continue
+            existing.add((a, b))
+            out.append((a, b))
+        return np.array(out, np.int64)
+
+    cols = {key: sc[key].copy() for key in ("ends", "k", "damping", "amp", "phase")}
+    sim = T.sim_from_scene(sc, _tp())
+    sim.rollout_grad(100, 25)  # the tables of the first layout
+    removed = rng.choice(ns0, 6, replace=False)
+    sim.remove_springs(removed)
+    before = sim.info()
+    for rnd in range(2):
+        add = new_pairs(5)
+        new = dict(ends=add, k=rng.uniform(5e3, 2e4, 5).astype(np.float32), damping=np.ones(5, np.float32),
+                   amp=rng.uniform(0.0, 0.15, 5).astype(np.float32),
+                   phase=rng.uniform(0.0, 2 * np.pi, 5).astype(np.float32))
+        sim.add_springs(new["ends"], new["k"], damping=new["damping"], amp=new["amp"], phase=new["phase"])
+        for key in cols:
+            cols[key] = np.concatenate([cols[key], new[key]])
+        keep = np.ones(cols["k"].shape[0], bool)
+        keep[removed] = False
+        edited = dict(sc, **{key: v[keep] for key, v in cols.items()})
+        loss, gk, gC, gS = sim.rollout_grad(200, 50)
+        ref = O.System(edited).rollout_grad(OP, 200, body=body)
+        for name, g, r in (("k", gk[keep], ref["gk"]), ("C", gC[keep], ref["gC"]), ("S", gS[keep], ref["gS"])):
+            e = np.linalg.norm(g - r) / np.linalg.norm(r)
+            c = _cos(g.astype(np.float64), r)
+            print("edit round", rnd, name, "rel", e, "cos", c)
+            assert e <= 1e-3 and c >= 0.9999
+        np.testing.assert_allclose(loss, ref["loss"], rtol=1e-3)
+    after = sim.info()
+    sim.close()
+    assert after["layout_builds"] + after["springs_in_place"] > before["layout_builds"] + before["springs_in_place"]
