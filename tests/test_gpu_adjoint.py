@@ -426,7 +426,7 @@ def test_adjoint_after_topology_edits_matches_oracle():
         for name, g, r in (("k", gk[keep], ref["gk"]), ("C", gC[keep], ref["gC"]), ("S", gS[keep], ref["gS"])):
             e = np.linalg.norm(g - r) / np.linalg.norm(r)
             c = _cos(g.astype(np.float64), r)
-            print("edit round", rnd, name, "rel", e, "cos", c)
+            print("after edit", rnd, name, "rel", e, "cos", c)
             assert e <= 1e-3 and c >= 0.9999
         np.testing.assert_allclose(loss, ref["loss"], rtol=1e-3)
     after = sim.info()
